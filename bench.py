@@ -1,0 +1,256 @@
+"""Benchmark of the FGA hot path on one MI355X.
+
+One step = one whole registration of the LiDAR-shaped pair (two 64-beam x
+1024-azimuth ring scans, 65,536 points each; Barnes-Hut theta = 0.5, FP32
+forces with Kahan tiles, FP64 rigid state, NIV masses): normalisation and
+masses, tree build, 100 fused iterations of Alg. 2, de-normalisation. The
+iteration count is fixed (tol = 0) so every step does the same work.
+
+Printed on stdout: one JSON line. `value` is force interactions per second
+over the whole step (inputs already resident in HBM). Extra fields report the
+fused BH iteration kernel against the FP32 vector peak (`roofline`), the
+direct-sum kernel on the 131,072 x 131,072 precision-study shape, batched
+versus plain registrations/s on the 256-pair workload, and the FP64 oracle
+timed on the host cores on a bounded sample (`cpu_baseline`).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_INTERACTION = 20          # conventional n-body count (3 sub, 3+3 fma, rsqrt, 3 mul, 3 fma)
+PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (packed), FLOP/s
+PEAK_FP32_NONPACKED = 78.6e12      # 256 CU x 64 lanes x 2 flop x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip direct/batched extras")
+    ap.add_argument("--batch-pairs", type=int, default=256)
+    ap.add_argument("--plain-pairs", type=int, default=32,
+                    help="pairs of the batch timed with sequential plain solves")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2009_14005_amd as fga
+    import synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    log("generating LiDAR-shaped pair (65,536 + 65,536 points)")
+    X, Y, R_gt, t_gt = synth.lidar_pair()
+    Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)
+    Yd = torch.as_tensor(Y, dtype=torch.float32, device=dev)
+    p = fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0)
+
+    for k in range(args.warmup):
+        fga.register(Xd, Yd, p)
+        log(f"warmup {k + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    inter = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        R, t, rep = fga.register(Xd, Yd, p)
+        inter += rep.interactions
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = inter / elapsed
+    log(f"timed {args.steps} registrations: {ms_step:.2f} ms/step, {value:.3e} interactions/s")
+    phi = float(np.degrees(np.arccos(np.clip(0.5 * (np.trace(R_gt.T @ R) - 1), -1, 1))))
+    diag = float(np.linalg.norm(X.max(0) - X.min(0)))
+
+    # the dominant kernel: one fused BH iteration per launch, timed with events
+    st = fga.State(Xd, Yd, p)
+    st.step(5)
+    torch.cuda.synchronize()
+    _, _, r0 = st.get()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_it = args.iters
+    e0.record(stream)
+    st.step(n_it)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _, _, r1 = st.get()
+    st.close()
+    it_ms = e0.elapsed_time(e1) / n_it
+    it_inter = (r1.interactions - r0.interactions) / n_it
+    achieved = it_inter * FLOP_PER_INTERACTION / (it_ms * 1e-3)
+    log(f"fused BH iteration: {it_ms * 1e3:.1f} us, {it_inter:.3e} interactions/iteration, "
+        f"{achieved / 1e12:.2f} TFLOP/s")
+    out = {
+        "metric": "force interactions/s (% FP32 VALU peak) + registrations/s, batched vs plain",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lidar_ring_scan_pair_65536_bh_theta0.5", "points": [len(X), len(Y)],
+                   "theta": 0.5, "iterations": args.iters, "masses": "niv",
+                   "precision": "fp32_kahan_forces_fp64_state", "parallelism": "single_gpu"},
+        "registrations_per_s": args.steps / elapsed,
+        "pct_fp32_vector_peak": 100.0 * value * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
+        "accuracy_vs_ground_truth": {"phi_deg": phi, "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag)},
+        "roofline": {
+            "kernel": "k_iteration<float, BH, FP32_KAHAN> (fused force + ODE + moments + Kabsch)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR,
+            "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
+            "traffic": None,
+            "avg_launch_us": it_ms * 1e3,
+            "interactions_per_launch": it_inter,
+            "flop_per_interaction": FLOP_PER_INTERACTION,
+        },
+    }
+
+    if not args.no_extras:
+        out["direct"] = bench_direct(fga, torch, synth, dev, stream)
+        out["batched"] = bench_batched(fga, torch, synth, dev, args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(X, Y)
+    print(json.dumps(out), flush=True)
+
+
+def bench_direct(fga, torch, synth, dev, stream):
+    """Direct all-pairs kernel on the 131,072 x 131,072 precision-study shape,
+    as the fused iteration of a registration (FP32 Kahan tiles)."""
+    log("direct kernel: 131,072 x 131,072")
+    X, Y, _, _ = synth.precision_pair()
+    Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)
+    Yd = torch.as_tensor(Y, dtype=torch.float32, device=dev)
+    res = {}
+    for name, prec in (("fp32_kahan", fga.PREC_FP32_KAHAN), ("fp32", fga.PREC_FP32)):
+        st = fga.State(Xd, Yd, fga.default_params(theta=0.0, tol=0.0, precision=prec))
+        st.step(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n_it = 5
+        e0.record(stream)
+        st.step(n_it)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st.close()
+        ms = e0.elapsed_time(e1) / n_it
+        ips = len(X) * len(Y) / (ms * 1e-3)
+        res[name] = {"ms_per_iteration": ms, "interactions_per_s": ips,
+                     "tflops": ips * FLOP_PER_INTERACTION / 1e12,
+                     "frac_fp32_vector_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR}
+        log(f"  {name}: {ms:.2f} ms/iteration, {ips:.3e} interactions/s")
+    return res
+
+
+def bench_batched(fga, torch, synth, dev, args):
+    """256 mixture pairs with log-uniform sizes: one batched registration
+    (persistent work-queue launches replayed from a HIP graph, FP32 forces)
+    against sequential plain registrations (FP64 forces and reductions) of a
+    subset, both with per-pair convergence (tol 1e-4, at most 200 iterations)."""
+    k = args.batch_pairs
+    log(f"batched workload: {k} pairs")
+    pairs = synth.batch_pairs(k)
+    Xs = [torch.as_tensor(pp[0], dtype=torch.float32, device=dev) for pp in pairs]
+    Ys = [torch.as_tensor(pp[1], dtype=torch.float32, device=dev) for pp in pairs]
+    pb = fga.default_params(theta=0.5, max_iter=200, tol=1e-4)
+    fga.register_batch(Xs[:4], Ys[:4], pb)  # warm the code paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R, t, reps = fga.register_batch(Xs, Ys, pb)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log(f"  batched: {tb * 1e3:.1f} ms for {k} pairs")
+    nplain = min(args.plain_pairs, k)
+    Xs64 = [torch.as_tensor(pp[0], dtype=torch.float64, device=dev) for pp in pairs[:nplain]]
+    Ys64 = [torch.as_tensor(pp[1], dtype=torch.float64, device=dev) for pp in pairs[:nplain]]
+    pp64 = fga.default_params(theta=0.5, max_iter=200, tol=1e-4, precision=fga.PREC_FP64)
+    fga.register(Xs64[0], Ys64[0], pp64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    errs = []
+    for j in range(nplain):
+        Rp, tp, rp = fga.register(Xs64[j], Ys64[j], pp64)
+        diag = np.linalg.norm(pairs[j][0].max(0) - pairs[j][0].min(0))
+        c = np.clip(0.5 * (np.trace(Rp.T @ R[j]) - 1), -1, 1)
+        errs.append((float(np.degrees(np.arccos(c))), float(np.linalg.norm(tp - t[j]) / diag)))
+    torch.cuda.synchronize()
+    tp_total = time.perf_counter() - t0
+    log(f"  plain FP64: {tp_total * 1e3:.1f} ms for {nplain} pairs")
+    errs = np.array(errs)
+    gt = []
+    for j in range(k):
+        Rg, tg = pairs[j][2], pairs[j][3]
+        c = np.clip(0.5 * (np.trace(Rg.T @ R[j]) - 1), -1, 1)
+        gt.append(float(np.degrees(np.arccos(c))))
+    return {
+        "pairs": k,
+        "batched_registrations_per_s": k / tb,
+        "plain_registrations_per_s": nplain / tp_total,
+        "plain_pairs_timed": nplain,
+        "speedup": (k / tb) / (nplain / tp_total),
+        "batched_vs_plain_max_phi_deg": float(errs[:, 0].max()),
+        "batched_vs_plain_max_dt_over_diag": float(errs[:, 1].max()),
+        "median_iters": float(np.median([r.iters for r in reps])),
+        "median_phi_vs_ground_truth_deg": float(np.median(gt)),
+    }
+
+
+def cpu_baseline(X, Y):
+    """The FP64 oracle (plain C, OpenMP over template particles) on the host
+    cores: Alg. 2 with the literal BH tree on the same LiDAR pair, timed over
+    a bounded number of iterations after its one-off setup."""
+    import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log(f"cpu baseline: FP64 oracle, {threads} threads")
+    Xn, Yn, _ = oracle.normalise(X, Y)
+    p = oracle.Params(theta=0.5)
+    mX, mY = oracle.masses(Xn, Yn, p)
+    st = oracle.Stepper(Xn, Yn, mX, mY, p)
+    t0 = time.perf_counter()
+    iters = 0
+    while iters < 100 and (iters < 2 or time.perf_counter() - t0 < 15.0):
+        st.step()
+        iters += 1
+    el = time.perf_counter() - t0
+    log(f"  oracle: {iters} iterations in {el:.1f} s")
+    return {"value": st.interactions / el, "unit": "interactions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{iters} Alg. 2 iterations (literal BH tree, theta 0.5, FP64) of the "
+                      f"65,536-point LiDAR pair; tree build excluded",
+            "ms_per_iteration": 1e3 * el / iters}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * fga.h — C ABI of the MI355X-native Fast Gravitational Approach (FGA) library.
+ *
+ * FGA (arXiv 2009.14005) registers a template point set Y (M x 3) to a
+ * reference point set X (N x 3) by letting the static reference pull every
+ * template particle with a softened gravitational force (Eq. GAForce),
+ * integrating a damped second-order ODE (Eqs. GAForceDissipative,
+ * TotalGAForce, PreviousVelocity) and projecting the particle displacements
+ * onto one rigid motion with the Kabsch solution (Eqs. R_Kabsch, transEst),
+ * iterated as in Alg. 2. The pull is evaluated either as the exact all-pairs
+ * sum or with the Barnes-Hut octree of Alg. 1 and the BHForce traversal of
+ * Alg. 2 (acceptance criterion Eq. MAC).
+ *
+ * Conventions for every entry point:
+ *   - Point arrays are contiguous row-major n x 3 DEVICE arrays of the given
+ *     dtype (float or double). Mass arrays are contiguous DEVICE vectors of
+ *     the same dtype. The caller owns every buffer passed in.
+ *   - R (row-major 3x3), t (3) and reports are HOST memory, FP64.
+ *     Registration results satisfy X ~= R * Y + t in the caller's coordinates.
+ *   - `stream` is a hipStream_t (NULL = the default stream). Work is queued on
+ *     it; functions that return host results synchronise that stream.
+ *   - Every function returns an fga_status and never aborts. Argument checks
+ *     happen on the host before any device work. A non-OK status leaves a
+ *     thread-local message readable with fga_last_error().
+ *   - Non-convergence is not an error: the report carries converged = 0.
+ *   - One library instance per process drives the current HIP device. States
+ *     are not thread-safe; distinct states may run on distinct streams.
+ */
+#ifndef FGA_H
+#define FGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FGA_OK = 0,
+  FGA_E_INVALID_ARG = 1, /* null pointer, bad size or out-of-range parameter */
+  FGA_E_NOMEM = 2,       /* device allocation failed */
+  FGA_E_DEVICE = 3,      /* HIP runtime or kernel error */
+  FGA_E_NONFINITE = 4,   /* NaN or Inf in the input points or masses */
+  FGA_E_DEGENERATE = 5,  /* zero-extent input, or a collinear template */
+  FGA_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} fga_status;
+
+typedef enum { FGA_F32 = 0, FGA_F64 = 1 } fga_dtype;
+
+/* Damping of Eq. (PreviousVelocity).
+ * FRACTION: v' = (1 - eta) v + dt g, the friction removing the fraction eta of
+ *           the particle momentum per step (Sec. n-Body Simulations).
+ * LITERAL:  v' = v + dt (F - eta v) / m_Y, Eqs. GAForceDissipative-PreviousVelocity. */
+typedef enum { FGA_DAMP_FRACTION = 0, FGA_DAMP_LITERAL = 1 } fga_damping;
+
+/* Velocity carried between iterations.
+ * RIGID:    the realised rigid displacement of the previous step over dt.
+ * PARTICLE: the unconstrained per-particle velocity v' of Eq. PreviousVelocity. */
+typedef enum { FGA_VEL_RIGID = 0, FGA_VEL_PARTICLE = 1 } fga_velocity;
+
+/* Masses (Sec. Smooth-Particle Mass Function, Eq. FinalSPM with B = 1):
+ * NIV normalised intrinsic volume, or UNIFORM (the constant-NIV case). */
+typedef enum { FGA_MASS_NIV = 0, FGA_MASS_UNIFORM = 1 } fga_mass_mode;
+
+/* Arithmetic of the force sum. The displacement moments, the rigid state and
+ * the Kabsch step are FP64 in every mode except FP32_ALL.
+ * FP32:       FP32 positions and forces, plain per-lane accumulation.
+ * FP32_KAHAN: FP32 positions and forces, tile sums added with Kahan compensation.
+ * FP64:       FP64 positions and forces (requires FGA_F64 data).
+ * FP32_ALL:   like FP32, and the per-particle moments are also summed in FP32. */
+typedef enum {
+  FGA_PREC_FP32 = 0,
+  FGA_PREC_FP32_KAHAN = 1,
+  FGA_PREC_FP64 = 2,
+  FGA_PREC_FP32_ALL = 3
+} fga_precision;
+
+typedef struct {
+  double G, eps, eta, dt; /* 66.7, 0.2, 0.2, 0.1 (Sec. Baseline Methods and Parameter Settings) */
+  double theta;           /* MAC opening parameter; 0 = direct all-pairs sum */
+  double a, b;            /* normalisation range [a, b] = [-5, 5] (Appendix A) */
+  int rho;                /* NIV lattice cells per axis, 16 */
+  int max_depth;          /* octree depth limit, 20 (Sec. BH tree, step iii) */
+  int max_iter;           /* iteration cap */
+  double tol;             /* stop when ||T_k - T_{k-1}||_F^2 < tol; tol <= 0 runs max_iter */
+  int damping;            /* fga_damping */
+  int velocity;           /* fga_velocity */
+  int mass_mode;          /* fga_mass_mode */
+  int precision;          /* fga_precision */
+  int leaf_size;          /* points per BH leaf: 1 = Alg. 1 exactly; 0 = autotuned */
+  int tile;               /* reference points per Kahan tile; 0 = autotuned */
+  int check_every;        /* host checks the convergence flag every k iterations (0 = 16) */
+  int reserved[5];
+} fga_params;
+
+typedef struct {
+  int iters;              /* iterations performed */
+  int converged;          /* 1 if the tolerance was met before max_iter */
+  double last_dT2;        /* ||T_k - T_{k-1}||_F^2 of the last iteration (normalised frame) */
+  long long interactions; /* force interactions evaluated (accepted nodes + leaf points) */
+  double ms_total;        /* wall time of the call in milliseconds */
+} fga_report;
+
+typedef struct fga_state fga_state;
+typedef struct fga_tree fga_tree;
+
+/* Fills *p with the paper's parameter settings (G = 66.7, eps = 0.2,
+ * eta = 0.2, dt = 0.1, theta = 0.6, [a,b] = [-5,5], rho = 16, depth 20), 200
+ * iterations, tol = 1e-4, fraction damping, rigid velocity, NIV masses,
+ * FP32 with Kahan tiles, leaf size 1. */
+fga_status fga_default_params(fga_params* p);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char* fga_last_error(void);
+
+/* Library version string. */
+const char* fga_version(void);
+
+/* Smooth-particle masses of one point set, Eq. (Normalized_IntrinsicVol)
+ * with B = 1 (Eq. FinalSPM): the set's bounding box is split into p->rho
+ * cells per axis; every point gets V_cell / min(n_c V_ball, V_cell) with
+ * n_c the count of its cell and V_ball the volume of a ball of radius
+ * (b - a) / (2 max_depth rho). norm = 0 scales the result to sum 1, norm = 1
+ * to mean 1. pts: n x 3 device, masses_out: n device values of dtype dt. */
+fga_status fga_masses(const void* pts, fga_dtype dt, int64_t n, const fga_params* p, int norm,
+                      void* masses_out, void* stream);
+
+/* Gravitational force on every template particle, Eq. (GAForce):
+ *   F_i = -G sum_j mX_j mY_i (y_i - x_j) / (|y_i - x_j|^2 + eps^2)^(3/2).
+ * theta == 0: exact all-pairs sum. theta > 0: Barnes-Hut (Alg. 1 tree built
+ * on X here, Alg. 2 BHForce). Y: m x 3, X: n x 3, mX: n, mY: m or NULL (= 1),
+ * F_out: m x 3, all device arrays of dtype dt. interactions (host, may be
+ * NULL) receives the number of interactions evaluated. Uses p->G, p->eps,
+ * p->precision, p->leaf_size. */
+fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                      const void* mY, fga_dtype dt, double theta, const fga_params* p,
+                      void* F_out, long long* interactions, void* stream);
+
+/* Registration state for Alg. 2: normalises (Appendix A), computes masses,
+ * builds the BH tree once if p->theta > 0, and sets T = [I | 0]. The state
+ * owns device copies; X and Y may be freed after the call returns. */
+fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                            const fga_params* p, void* stream, fga_state** out);
+
+/* Runs n_iters iterations of the Alg. 2 loop body (forces, damped velocity,
+ * displacements, Kabsch step, template update) on the state's stream. Stops
+ * early only if p->tol > 0 and the tolerance is met. */
+fga_status fga_step(fga_state* st, int n_iters);
+
+/* Current transform in the caller's coordinates (de-normalised as in
+ * Appendix A) and an optional report. R, t, rep are host memory; rep may be NULL. */
+fga_status fga_state_get(const fga_state* st, double R[9], double t[3], fga_report* rep);
+
+/* Current transform in the normalised frame (Yn -> Xn), host memory. */
+fga_status fga_state_get_normalised(const fga_state* st, double R[9], double t[3]);
+
+/* Serialises the dynamic state (FP64 rigid state, per-particle velocities in
+ * particle mode) into buf. Call with buf = NULL to query *len. */
+fga_status fga_state_save(const fga_state* st, void* buf, size_t* len);
+
+/* Restores a state saved from a state created with the same inputs and parameters. */
+fga_status fga_state_load(fga_state* st, const void* buf, size_t len);
+
+void fga_state_destroy(fga_state* st);
+
+/* Whole Alg. 2 registration of Y to X: normalise, masses, tree (theta > 0),
+ * iterate to convergence or max_iter, de-normalise. */
+fga_status fga_register(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                        const fga_params* p, double R[9], double t[3], fga_report* rep,
+                        void* stream);
+
+/* npairs independent registrations run together: one set of launches builds
+ * every pair's tree, and every iteration is one persistent launch over a work
+ * queue of (pair, template tile, reference range) items, replayed from a HIP
+ * graph. X[k], Y[k] are device arrays of n[k] x 3 and m[k] x 3 points.
+ * R: npairs x 9, t: npairs x 3, reps: npairs (may be NULL), host memory. */
+fga_status fga_register_batch(int npairs, const void* const* X, const int64_t* n,
+                              const void* const* Y, const int64_t* m, fga_dtype dt,
+                              const fga_params* p, double* R, double* t, fga_report* reps,
+                              void* stream);
+
+/* ---- inspection entry points (used by tests and tools) ---- */
+
+/* Builds the compressed octree of Alg. 1 on X (n x 3) with masses mX (n),
+ * device arrays of dtype dt. Chains of single-child cells are collapsed to
+ * their deepest cell, which gives the same accept/open outcome and force. */
+fga_status fga_tree_create(const void* X, const void* mX, int64_t n, fga_dtype dt,
+                           const fga_params* p, void* stream, fga_tree** out);
+
+/* info[0] = nodes, info[1] = leaves, info[2] = internal nodes, info[3] = max depth. */
+fga_status fga_tree_info(const fga_tree* tr, int64_t info[4]);
+
+/* Copies the tree to host memory. Nodes are in depth-first preorder.
+ *   com_mass: nodes x 4 (x, y, z, mass), float
+ *   ints:     nodes x 4 (skip, first, last, depth), int32; skip is the preorder
+ *             index after the node's subtree; [first, last] the node's points in
+ *             sorted order; a leaf has skip == index + 1.
+ *   order:    n, int32: order[k] = input index of the k-th sorted point.
+ * Any pointer may be NULL. */
+fga_status fga_tree_export(const fga_tree* tr, float* com_mass, int32_t* ints, int32_t* order);
+
+void fga_tree_destroy(fga_tree* tr);
+
+/* Host evaluation of the FP64 Kabsch solution used on the device: given
+ * C = hat(Y_D)^T hat(Y) (row-major 3x3), writes R = U diag(1,1,sgn det(U V^T)) V^T
+ * (Eq. R_Kabsch). Returns FGA_E_DEGENERATE when rank(C) < 2. */
+fga_status fga_kabsch(const double C[9], double R[9]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGA_H */

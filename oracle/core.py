@@ -41,7 +41,7 @@ import numpy as np
 __all__ = [
     "build", "lib", "Params", "normalise", "denormalise_t", "niv_masses",
     "direct_forces", "BHTree", "kabsch", "Stepper", "register", "gpe",
-    "angular_deviation_deg",
+    "angular_deviation_deg", "masses",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))

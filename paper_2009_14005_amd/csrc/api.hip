@@ -1,0 +1,878 @@
+// C ABI of libfga: argument validation, state management and the host loop
+// of Alg. 2. Every argument check runs before the first HIP call, so invalid
+// requests fail identically with or without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "rigid.h"
+
+namespace fga {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+namespace {
+
+constexpr int64_t kMaxPoints = (int64_t)1 << 30;  // 32-bit indices inside the kernels
+
+fga_status check_params(const fga_params* p) {
+  if (!p) {
+    set_error("params is NULL");
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->G) && p->G > 0)) {
+    set_error("G must be finite and > 0 (got %g)", p->G);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->eps) && p->eps > 0)) {
+    set_error("eps must be finite and > 0 (got %g)", p->eps);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->dt) && p->dt > 0)) {
+    set_error("dt must be finite and > 0 (got %g)", p->dt);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->eta) && p->eta >= 0)) {
+    set_error("eta must be finite and >= 0 (got %g)", p->eta);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->damping != FGA_DAMP_FRACTION && p->damping != FGA_DAMP_LITERAL) {
+    set_error("unknown damping mode %d", p->damping);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->damping == FGA_DAMP_FRACTION && p->eta > 1.0) {
+    set_error("fraction damping needs eta in [0, 1] (got %g)", p->eta);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->theta) && p->theta >= 0)) {
+    set_error("theta must be finite and >= 0 (got %g)", p->theta);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(p->a) && std::isfinite(p->b) && p->a < p->b)) {
+    set_error("normalisation range needs a < b (got [%g, %g])", p->a, p->b);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->rho < 1 || p->rho > 64) {
+    set_error("rho must be in [1, 64] (got %d)", p->rho);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->max_depth != kQBits) {
+    set_error("max_depth %d: this build supports the paper's depth limit 20 only", p->max_depth);
+    return FGA_E_UNSUPPORTED;
+  }
+  if (p->max_iter < 0) {
+    set_error("max_iter must be >= 0 (got %d)", p->max_iter);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!std::isfinite(p->tol)) {
+    set_error("tol must be finite");
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->velocity != FGA_VEL_RIGID && p->velocity != FGA_VEL_PARTICLE) {
+    set_error("unknown velocity mode %d", p->velocity);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->mass_mode != FGA_MASS_NIV && p->mass_mode != FGA_MASS_UNIFORM) {
+    set_error("unknown mass mode %d", p->mass_mode);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->precision < FGA_PREC_FP32 || p->precision > FGA_PREC_FP32_ALL) {
+    set_error("unknown precision %d", p->precision);
+    return FGA_E_INVALID_ARG;
+  }
+  if (p->leaf_size < 0 || p->leaf_size > 1) {
+    set_error("leaf_size %d: this build builds the paper's singleton leaves (0 or 1)", p->leaf_size);
+    return FGA_E_UNSUPPORTED;
+  }
+  if (p->tile < 0 || p->check_every < 0) {
+    set_error("tile and check_every must be >= 0");
+    return FGA_E_INVALID_ARG;
+  }
+  return FGA_OK;
+}
+
+fga_status check_dtype(fga_dtype dt) {
+  if (dt != FGA_F32 && dt != FGA_F64) {
+    set_error("unknown dtype %d", (int)dt);
+    return FGA_E_INVALID_ARG;
+  }
+  return FGA_OK;
+}
+
+fga_status check_count(int64_t n, const char* what) {
+  if (n < 1 || n > kMaxPoints) {
+    set_error("%s must be in [1, 2^30] (got %lld)", what, (long long)n);
+    return FGA_E_INVALID_ARG;
+  }
+  return FGA_OK;
+}
+
+fga_status check_ptr(const void* p, const char* what) {
+  if (!p) {
+    set_error("%s is NULL", what);
+    return FGA_E_INVALID_ARG;
+  }
+  return FGA_OK;
+}
+
+// Device accessibility of a caller pointer (after the host-only checks).
+fga_status check_device_ptr(const void* p, const char* what) {
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof at);
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("%s is not device-accessible memory (%s)", what, hipGetErrorString(e));
+    return FGA_E_INVALID_ARG;
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged &&
+      at.type != hipMemoryTypeUnified && at.type != hipMemoryTypeHost) {
+    set_error("%s is not device-accessible memory (memory type %d)", what, (int)at.type);
+    return FGA_E_INVALID_ARG;
+  }
+  return FGA_OK;
+}
+
+size_t dsize(fga_dtype dt) { return dt == FGA_F64 ? 8 : 4; }
+
+IterConsts make_iter_consts(const fga_params& p) {
+  IterConsts c;
+  c.G = p.G;
+  c.eps2 = p.eps * p.eps;
+  c.dt = p.dt;
+  c.theta2 = p.theta * p.theta;
+  c.fG = (float)c.G;
+  c.feps2 = (float)c.eps2;
+  c.fdt = (float)c.dt;
+  c.ftheta2 = (float)c.theta2;
+  c.damping = p.damping;
+  c.velocity = p.velocity;
+  c.prec = p.precision;
+  c.pad_ = 0;
+  return c;
+}
+
+// Reference ranges per template tile for the BH iteration: enough waves to
+// keep every SIMD busy, few enough that the shared top of the tree is not
+// re-walked too often.
+int bh_ranges(int64_t m, int64_t n) {
+  const int64_t waves = (m + kWave - 1) / kWave;
+  int64_t jr = (4096 + waves - 1) / waves;
+  if (jr > 8) jr = 8;
+  if (jr > (n + 255) / 256) jr = (n + 255) / 256;
+  return jr < 1 ? 1 : (int)jr;
+}
+
+void denormalise(const NormInfo& ni, const double* R, const double* tn, double* t) {
+  // X = s (Xn - a) + mean(X) + l, Y = s (Yn - a) + mean(Y) + l with
+  // s = (r - l)/(b - a) (inverse of Eq. A.3); Xn = R Yn + tn then gives
+  // t = mean(X) - R mean(Y) + s (R a1 + tn - a1) + l1 - R l1.
+  const double s = (ni.r - ni.l) / (ni.b - ni.a);
+  for (int i = 0; i < 3; ++i) {
+    double Ra = 0.0, Ry = 0.0, Rl = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      Ra += R[3 * i + j] * ni.a;
+      Ry += R[3 * i + j] * ni.ybar[j];
+      Rl += R[3 * i + j] * ni.l;
+    }
+    t[i] = ni.xbar[i] - Ry + s * (Ra + tn[i] - ni.a) + ni.l - Rl;
+  }
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+}  // namespace fga
+
+using namespace fga;
+
+// ---------------------------------------------------------------- the state
+struct fga_state {
+  fga_params p;
+  fga_dtype dt;
+  hipStream_t s;
+  bool f64;
+  int64_t n, m;
+  void* X = nullptr;        // packed reference (Morton-sorted for BH)
+  void* Q = nullptr;        // packed template (Morton-sorted)
+  BHNode* nodes = nullptr;
+  int n_nodes = 0;
+  RigidState* st = nullptr;
+  double* partial = nullptr;
+  unsigned* done = nullptr;
+  void* V = nullptr;
+  PairDev pd;
+  IterConsts c;
+  NormInfo norm;
+  int tree_stats[3] = {0, 0, 0};
+};
+
+struct fga_tree {
+  int64_t n;
+  BHNode* nodes = nullptr;
+  int n_nodes = 0;
+  int* order = nullptr;
+  void* Xs = nullptr;
+  int stats[3] = {0, 0, 0};
+};
+
+static void state_free(fga_state* s) {
+  if (!s) return;
+  if (s->X) (void)hipFree(s->X);
+  if (s->Q) (void)hipFree(s->Q);
+  if (s->nodes) (void)hipFree(s->nodes);
+  if (s->st) (void)hipFree(s->st);
+  if (s->partial) (void)hipFree(s->partial);
+  if (s->done) (void)hipFree(s->done);
+  if (s->V) (void)hipFree(s->V);
+  delete s;
+}
+
+extern "C" {
+
+fga_status fga_default_params(fga_params* p) {
+  if (!p) {
+    set_error("params is NULL");
+    return FGA_E_INVALID_ARG;
+  }
+  std::memset(p, 0, sizeof *p);
+  p->G = 66.7;
+  p->eps = 0.2;
+  p->eta = 0.2;
+  p->dt = 0.1;
+  p->theta = 0.6;
+  p->a = -5.0;
+  p->b = 5.0;
+  p->rho = 16;
+  p->max_depth = 20;
+  p->max_iter = 200;
+  p->tol = 1e-4;
+  p->damping = FGA_DAMP_FRACTION;
+  p->velocity = FGA_VEL_RIGID;
+  p->mass_mode = FGA_MASS_NIV;
+  p->precision = FGA_PREC_FP32_KAHAN;
+  p->leaf_size = 1;
+  p->tile = 0;
+  p->check_every = 16;
+  return FGA_OK;
+}
+
+const char* fga_last_error(void) { return g_err.c_str(); }
+
+const char* fga_version(void) { return "fga-mi355x 0.1 (gfx950)"; }
+
+fga_status fga_kabsch(const double C[9], double R[9]) {
+  FGA_TRY(check_ptr(C, "C"));
+  FGA_TRY(check_ptr(R, "R"));
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(C[k])) {
+      set_error("C has a non-finite entry");
+      return FGA_E_NONFINITE;
+    }
+  if (kabsch3(C, R)) {
+    set_error("rank(C) < 2: the rotation is not determined");
+    return FGA_E_DEGENERATE;
+  }
+  return FGA_OK;
+}
+
+fga_status fga_masses(const void* pts, fga_dtype dt, int64_t n, const fga_params* p, int norm,
+                      void* masses_out, void* stream) {
+  FGA_TRY(check_ptr(pts, "pts"));
+  FGA_TRY(check_ptr(masses_out, "masses_out"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  if (norm != 0 && norm != 1) {
+    set_error("norm must be 0 (sum 1) or 1 (mean 1)");
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_device_ptr(pts, "pts"));
+  FGA_TRY(check_device_ptr(masses_out, "masses_out"));
+  return masses_only(pts, dt, n, *p, norm, masses_out, (hipStream_t)stream);
+}
+
+fga_status fga_tree_create(const void* X, const void* mX, int64_t n, fga_dtype dt,
+                           const fga_params* p, void* stream, fga_tree** out) {
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(mX, "mX"));
+  FGA_TRY(check_ptr(out, "out"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(mX, "mX"));
+  hipStream_t s = (hipStream_t)stream;
+  fga_tree* t = new fga_tree;
+  t->n = n;
+  const size_t v4 = dt == FGA_F64 ? sizeof(double4) : sizeof(float4);
+  hipError_t e = hipMalloc(&t->Xs, v4 * n);
+  if (e != hipSuccess) {
+    delete t;
+    set_error("hipMalloc failed: %s", hipGetErrorString(e));
+    return FGA_E_NOMEM;
+  }
+  fga_status st = dt == FGA_F64 ? pack_points<double>(X, mX, n, t->Xs, s)
+                                : pack_points<float>(X, mX, n, t->Xs, s);
+  TreeSeg seg{0, n};
+  int off[2] = {0, 0};
+  if (st == FGA_OK)
+    st = dt == FGA_F64
+             ? build_trees<double>(1, &seg, t->Xs, n, p->leaf_size, &t->nodes, off, &t->order, t->stats, s)
+             : build_trees<float>(1, &seg, t->Xs, n, p->leaf_size, &t->nodes, off, &t->order, t->stats, s);
+  if (st != FGA_OK) {
+    if (t->Xs) (void)hipFree(t->Xs);
+    delete t;
+    return st;
+  }
+  t->n_nodes = off[1] - off[0];
+  *out = t;
+  return FGA_OK;
+}
+
+fga_status fga_tree_info(const fga_tree* t, int64_t info[4]) {
+  FGA_TRY(check_ptr(t, "tree"));
+  FGA_TRY(check_ptr(info, "info"));
+  info[0] = t->n_nodes;
+  info[1] = t->stats[1];
+  info[2] = t->stats[2];
+  info[3] = t->stats[0];
+  return FGA_OK;
+}
+
+fga_status fga_tree_export(const fga_tree* t, float* com_mass, int32_t* ints, int32_t* order) {
+  FGA_TRY(check_ptr(t, "tree"));
+  std::vector<BHNode> h(t->n_nodes);
+  FGA_HIP(hipMemcpy(h.data(), t->nodes, sizeof(BHNode) * t->n_nodes, hipMemcpyDeviceToHost));
+  // node depth from the stored squared diagonal relative to the root's
+  const double l2root = h.empty() ? 0.0 : (double)h[0].l2;
+  for (int k = 0; k < t->n_nodes; ++k) {
+    if (com_mass) {
+      com_mass[4 * k] = h[k].cm.x;
+      com_mass[4 * k + 1] = h[k].cm.y;
+      com_mass[4 * k + 2] = h[k].cm.z;
+      com_mass[4 * k + 3] = h[k].cm.w;
+    }
+    if (ints) {
+      ints[4 * k] = h[k].skip;
+      ints[4 * k + 1] = h[k].first;
+      ints[4 * k + 2] = h[k].last;
+      int d = 0;
+      if (l2root > 0.0 && h[k].l2 > 0.0)
+        d = (int)std::lround(0.5 * std::log2(l2root / (double)h[k].l2));
+      ints[4 * k + 3] = d;
+    }
+  }
+  if (order) FGA_HIP(hipMemcpy(order, t->order, sizeof(int32_t) * t->n, hipMemcpyDeviceToHost));
+  return FGA_OK;
+}
+
+void fga_tree_destroy(fga_tree* t) {
+  if (!t) return;
+  if (t->nodes) (void)hipFree(t->nodes);
+  if (t->order) (void)hipFree(t->order);
+  if (t->Xs) (void)hipFree(t->Xs);
+  delete t;
+}
+
+fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                      const void* mY, fga_dtype dt, double theta, const fga_params* p,
+                      void* F_out, long long* interactions, void* stream) {
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(mX, "mX"));
+  FGA_TRY(check_ptr(F_out, "F_out"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(m, "m"));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  if (!(std::isfinite(theta) && theta >= 0)) {
+    set_error("theta must be finite and >= 0 (got %g)", theta);
+    return FGA_E_INVALID_ARG;
+  }
+  if (dt == FGA_F32 && p->precision == FGA_PREC_FP64) {
+    set_error("FP64 precision needs FP64 data");
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(mX, "mX"));
+  FGA_TRY(check_device_ptr(F_out, "F_out"));
+  if (mY) FGA_TRY(check_device_ptr(mY, "mY"));
+  hipStream_t s = (hipStream_t)stream;
+  if (theta == 0.0) {
+    fga_status st = dt == FGA_F64 ? forces_direct<double>(Y, m, X, n, mX, mY, *p, F_out, s)
+                                  : forces_direct<float>(Y, m, X, n, mX, mY, *p, F_out, s);
+    if (st == FGA_OK && interactions) *interactions = (long long)m * (long long)n;
+    return st;
+  }
+  // Barnes-Hut: tree on X, template visited in Morton order
+  fga_tree* tr = nullptr;
+  FGA_TRY(fga_tree_create(X, mX, n, dt, p, stream, &tr));
+  void* Y4 = nullptr;
+  int* yorder = nullptr;
+  const size_t v4 = dt == FGA_F64 ? sizeof(double4) : sizeof(float4);
+  fga_status st = FGA_OK;
+  if (hipMalloc(&Y4, v4 * m) != hipSuccess || hipMalloc((void**)&yorder, sizeof(int) * m) != hipSuccess) {
+    set_error("hipMalloc failed");
+    st = FGA_E_NOMEM;
+  }
+  if (st == FGA_OK)  // the masses slot is unused by the sort; any finite array of m values works
+    st = dt == FGA_F64 ? pack_points<double>(Y, Y, m, Y4, s) : pack_points<float>(Y, Y, m, Y4, s);
+  TreeSeg seg{0, m};
+  if (st == FGA_OK)
+    st = dt == FGA_F64 ? sort_points_morton<double>(1, &seg, Y4, m, yorder, s)
+                       : sort_points_morton<float>(1, &seg, Y4, m, yorder, s);
+  if (st == FGA_OK)
+    st = dt == FGA_F64
+             ? forces_bh_tree<double>(Y, m, yorder, tr->nodes, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s)
+             : forces_bh_tree<float>(Y, m, yorder, tr->nodes, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s);
+  if (Y4) (void)hipFree(Y4);
+  if (yorder) (void)hipFree(yorder);
+  fga_tree_destroy(tr);
+  return st;
+}
+
+static fga_status validate_pair(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                                const fga_params* p) {
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_count(m, "m"));
+  FGA_TRY(check_params(p));
+  return FGA_OK;
+}
+
+fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                            const fga_params* p, void* stream, fga_state** out) {
+  FGA_TRY(validate_pair(X, n, Y, m, dt, p));
+  FGA_TRY(check_ptr(out, "out"));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  hipStream_t s = (hipStream_t)stream;
+  fga_state* S = new fga_state;
+  S->p = *p;
+  S->dt = dt;
+  S->s = s;
+  S->f64 = p->precision == FGA_PREC_FP64;
+  S->n = n;
+  S->m = m;
+  const size_t v4 = S->f64 ? sizeof(double4) : sizeof(float4);
+  auto fail = [&](fga_status st) {
+    state_free(S);
+    return st;
+  };
+  if (hipMalloc(&S->X, v4 * n) != hipSuccess || hipMalloc(&S->Q, v4 * m) != hipSuccess ||
+      hipMalloc((void**)&S->st, sizeof(RigidState)) != hipSuccess) {
+    set_error("hipMalloc of the state failed");
+    return fail(FGA_E_NOMEM);
+  }
+  CloudIn cx{X, n}, cy{Y, m};
+  PrepOut po{S->X, S->Q, S->st};
+  fga_params pp = *p;
+  fga_status st = prep_pairs(1, &cx, &cy, dt, pp, &po, &S->norm, s);
+  if (st != FGA_OK) return fail(st);
+  TreeSeg sy{0, m};
+  st = S->f64 ? sort_points_morton<double>(1, &sy, S->Q, m, nullptr, s)
+              : sort_points_morton<float>(1, &sy, S->Q, m, nullptr, s);
+  if (st != FGA_OK) return fail(st);
+  if (p->theta > 0) {
+    TreeSeg sx{0, n};
+    int off[2] = {0, 0};
+    st = S->f64 ? build_trees<double>(1, &sx, S->X, n, p->leaf_size, &S->nodes, off, nullptr, S->tree_stats, s)
+                : build_trees<float>(1, &sx, S->X, n, p->leaf_size, &S->nodes, off, nullptr, S->tree_stats, s);
+    if (st != FGA_OK) return fail(st);
+    S->n_nodes = off[1] - off[0];
+  }
+  int jr = p->theta > 0 ? bh_ranges(m, n) : direct_ranges(m, n);
+  if (p->velocity == FGA_VEL_PARTICLE) jr = 1;
+  const int tiles = (int)((m + kBlock - 1) / kBlock);
+  const int items = tiles * jr;
+  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * items) != hipSuccess ||
+      hipMalloc((void**)&S->done, sizeof(unsigned)) != hipSuccess) {
+    set_error("hipMalloc of the iteration buffers failed");
+    return fail(FGA_E_NOMEM);
+  }
+  if (hipMemsetAsync(S->done, 0, sizeof(unsigned), s) != hipSuccess) return fail(FGA_E_DEVICE);
+  if (p->velocity == FGA_VEL_PARTICLE) {
+    const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
+    if (hipMalloc(&S->V, vb) != hipSuccess) {
+      set_error("hipMalloc of the velocities failed");
+      return fail(FGA_E_NOMEM);
+    }
+    if (hipMemsetAsync(S->V, 0, vb, s) != hipSuccess) return fail(FGA_E_DEVICE);
+  }
+  PairDev& pd = S->pd;
+  pd.X = S->X;
+  pd.Q = S->Q;
+  pd.nodes = S->nodes;
+  pd.V = S->V;
+  pd.st = S->st;
+  pd.partial = S->partial;
+  pd.done = S->done;
+  pd.n = (int)n;
+  pd.m = (int)m;
+  pd.n_nodes = S->n_nodes;
+  pd.jr = jr;
+  pd.n_items = items;
+  pd.pad_ = 0;
+  S->c = make_iter_consts(*p);
+  // manual stepping has no iteration cap; fga_register applies max_iter itself
+  const int big = 0x7fffffff;
+  if (hipMemcpyAsync(&S->st->max_iter, &big, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error("state initialisation failed");
+    return fail(FGA_E_DEVICE);
+  }
+  *out = S;
+  return FGA_OK;
+}
+
+static fga_status read_state(const fga_state* S, RigidState* h) {
+  FGA_HIP(hipMemcpyAsync(h, S->st, sizeof(RigidState), hipMemcpyDeviceToHost, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  return FGA_OK;
+}
+
+fga_status fga_step(fga_state* S, int n_iters) {
+  FGA_TRY(check_ptr(S, "state"));
+  if (n_iters < 0) {
+    set_error("n_iters must be >= 0");
+    return FGA_E_INVALID_ARG;
+  }
+  const int every = S->p.check_every > 0 ? S->p.check_every : 16;
+  for (int k = 0; k < n_iters; ++k) {
+    fga_status st = S->f64 ? launch_iteration<double>(S->pd, S->c, S->s)
+                           : launch_iteration<float>(S->pd, S->c, S->s);
+    if (st != FGA_OK) return st;
+    if (S->p.tol > 0 && ((k + 1) % every == 0) && k + 1 < n_iters) {
+      int conv = 0;
+      FGA_HIP(hipMemcpyAsync(&conv, &S->st->converged, sizeof(int), hipMemcpyDeviceToHost, S->s));
+      FGA_HIP(hipStreamSynchronize(S->s));
+      if (conv) break;
+    }
+  }
+  FGA_HIP(hipStreamSynchronize(S->s));
+  return FGA_OK;
+}
+
+fga_status fga_state_get_normalised(const fga_state* S, double R[9], double t[3]) {
+  FGA_TRY(check_ptr(S, "state"));
+  FGA_TRY(check_ptr(R, "R"));
+  FGA_TRY(check_ptr(t, "t"));
+  RigidState h;
+  FGA_TRY(read_state(S, &h));
+  std::memcpy(R, h.R, sizeof(double) * 9);
+  std::memcpy(t, h.t, sizeof(double) * 3);
+  return FGA_OK;
+}
+
+fga_status fga_state_get(const fga_state* S, double R[9], double t[3], fga_report* rep) {
+  FGA_TRY(check_ptr(S, "state"));
+  FGA_TRY(check_ptr(R, "R"));
+  FGA_TRY(check_ptr(t, "t"));
+  RigidState h;
+  FGA_TRY(read_state(S, &h));
+  std::memcpy(R, h.R, sizeof(double) * 9);
+  denormalise(S->norm, h.R, h.t, t);
+  if (rep) {
+    rep->iters = h.iter;
+    rep->converged = h.converged == 1;
+    rep->last_dT2 = h.dT2;
+    rep->interactions = h.interactions;
+    rep->ms_total = 0.0;
+  }
+  if (h.flags & 1) {
+    set_error("the template is collinear: the Kabsch rotation is undetermined");
+    return FGA_E_DEGENERATE;
+  }
+  return FGA_OK;
+}
+
+fga_status fga_state_save(const fga_state* S, void* buf, size_t* len) {
+  FGA_TRY(check_ptr(S, "state"));
+  FGA_TRY(check_ptr(len, "len"));
+  const size_t vb = S->V ? (S->f64 ? 8 : 4) * 3 * (size_t)S->m : 0;
+  const size_t need = sizeof(RigidState) + vb;
+  if (!buf) {
+    *len = need;
+    return FGA_OK;
+  }
+  if (*len < need) {
+    set_error("buffer too small: %zu < %zu bytes", *len, need);
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_HIP(hipMemcpyAsync(buf, S->st, sizeof(RigidState), hipMemcpyDeviceToHost, S->s));
+  if (vb) FGA_HIP(hipMemcpyAsync((char*)buf + sizeof(RigidState), S->V, vb, hipMemcpyDeviceToHost, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  *len = need;
+  return FGA_OK;
+}
+
+fga_status fga_state_load(fga_state* S, const void* buf, size_t len) {
+  FGA_TRY(check_ptr(S, "state"));
+  FGA_TRY(check_ptr(buf, "buf"));
+  const size_t vb = S->V ? (S->f64 ? 8 : 4) * 3 * (size_t)S->m : 0;
+  if (len != sizeof(RigidState) + vb) {
+    set_error("saved state has %zu bytes, this state needs %zu", len, sizeof(RigidState) + vb);
+    return FGA_E_INVALID_ARG;
+  }
+  RigidState h;
+  std::memcpy(&h, buf, sizeof h);
+  if (h.m != (int)S->m) {
+    set_error("saved state is for %d template points, this state has %lld", h.m, (long long)S->m);
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_HIP(hipMemcpyAsync(S->st, buf, sizeof(RigidState), hipMemcpyHostToDevice, S->s));
+  if (vb) FGA_HIP(hipMemcpyAsync(S->V, (const char*)buf + sizeof(RigidState), vb, hipMemcpyHostToDevice, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  return FGA_OK;
+}
+
+void fga_state_destroy(fga_state* S) { state_free(S); }
+
+fga_status fga_register(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                        const fga_params* p, double R[9], double t[3], fga_report* rep,
+                        void* stream) {
+  FGA_TRY(validate_pair(X, n, Y, m, dt, p));
+  FGA_TRY(check_ptr(R, "R"));
+  FGA_TRY(check_ptr(t, "t"));
+  const double t0 = now_ms();
+  fga_state* S = nullptr;
+  FGA_TRY(fga_state_create(X, n, Y, m, dt, p, stream, &S));
+  fga_status st = fga_step(S, p->max_iter);
+  if (st == FGA_OK) st = fga_state_get(S, R, t, rep);
+  fga_state_destroy(S);
+  if (rep) rep->ms_total = now_ms() - t0;
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BatchBufs {
+  std::vector<void*> ptrs;
+  hipStream_t own = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipEvent_t ev = nullptr;
+  ~BatchBufs() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own) {
+      (void)hipStreamSynchronize(own);
+      (void)hipStreamDestroy(own);
+    }
+    if (ev) (void)hipEventDestroy(ev);
+    for (void* q : ptrs) (void)hipFree(q);
+  }
+  template <typename P>
+  fga_status get(P** out, size_t bytes) {
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes < 16 ? 16 : bytes) != hipSuccess) {
+      set_error("hipMalloc(%zu) failed", bytes);
+      return FGA_E_NOMEM;
+    }
+    ptrs.push_back(q);
+    *out = (P*)q;
+    return FGA_OK;
+  }
+};
+
+template <typename T>
+fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const void* const* Y,
+                      const int64_t* m, fga_dtype dt, const fga_params& p, double* R, double* t,
+                      fga_report* reps, hipStream_t caller) {
+  const double t0 = now_ms();
+  BatchBufs B;
+  // private non-default stream: graph capture needs one; ordered after the caller's work
+  FGA_HIP(hipStreamCreateWithFlags(&B.own, hipStreamNonBlocking));
+  FGA_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+  FGA_HIP(hipEventRecord(B.ev, caller));
+  FGA_HIP(hipStreamWaitEvent(B.own, B.ev, 0));
+  hipStream_t s = B.own;
+  std::vector<int64_t> xoff(npairs + 1, 0), yoff(npairs + 1, 0);
+  for (int k = 0; k < npairs; ++k) {
+    xoff[k + 1] = xoff[k] + n[k];
+    yoff[k + 1] = yoff[k] + m[k];
+  }
+  const int64_t NX = xoff[npairs], NY = yoff[npairs];
+  if (NX > kMaxPoints || NY > kMaxPoints) {
+    set_error("batch too large: %lld reference and %lld template points", (long long)NX, (long long)NY);
+    return FGA_E_INVALID_ARG;
+  }
+  vec4_t<T>*Xp, *Qp;
+  RigidState* st;
+  FGA_TRY(B.get(&Xp, sizeof(vec4_t<T>) * NX));
+  FGA_TRY(B.get(&Qp, sizeof(vec4_t<T>) * NY));
+  FGA_TRY(B.get(&st, sizeof(RigidState) * npairs));
+  std::vector<CloudIn> cx(npairs), cy(npairs);
+  for (int k = 0; k < npairs; ++k) {
+    cx[k] = {X[k], n[k]};
+    cy[k] = {Y[k], m[k]};
+  }
+  std::vector<NormInfo> norm(npairs);
+  PrepOut po{Xp, Qp, st};
+  FGA_TRY(prep_pairs(npairs, cx.data(), cy.data(), dt, p, &po, norm.data(), s));
+  std::vector<TreeSeg> ys(npairs), xs(npairs);
+  for (int k = 0; k < npairs; ++k) {
+    ys[k] = {yoff[k], m[k]};
+    xs[k] = {xoff[k], n[k]};
+  }
+  FGA_TRY(sort_points_morton<T>(npairs, ys.data(), Qp, NY, nullptr, s));
+  BHNode* nodes = nullptr;
+  std::vector<int> noff(npairs + 1, 0);
+  int tstats[3];
+  if (p.theta > 0) {
+    FGA_TRY(build_trees<T>(npairs, xs.data(), Xp, NX, p.leaf_size, &nodes, noff.data(), nullptr, tstats, s));
+    B.ptrs.push_back(nodes);
+  }
+  // work items: template tiles of every pair, largest reference first
+  const bool big = NY >= 262144;
+  std::vector<PairDev> pds(npairs);
+  std::vector<int> item_off(npairs + 1, 0);
+  for (int k = 0; k < npairs; ++k) {
+    int jr = big ? 1 : (p.theta > 0 ? bh_ranges(m[k], n[k]) : direct_ranges(m[k], n[k]));
+    const int tiles = (int)((m[k] + kBlock - 1) / kBlock);
+    item_off[k + 1] = item_off[k] + tiles * jr;
+    pds[k].jr = jr;
+    pds[k].n_items = tiles * jr;
+  }
+  const int n_items = item_off[npairs];
+  double* partial;
+  unsigned *done, *queue;
+  PairDev* dpairs;
+  int2* ditems;
+  FGA_TRY(B.get(&partial, sizeof(double) * 12 * n_items));
+  FGA_TRY(B.get(&done, sizeof(unsigned) * npairs));
+  FGA_TRY(B.get(&queue, sizeof(unsigned) * 2));
+  FGA_TRY(B.get(&dpairs, sizeof(PairDev) * npairs));
+  FGA_TRY(B.get(&ditems, sizeof(int2) * n_items));
+  for (int k = 0; k < npairs; ++k) {
+    PairDev& pd = pds[k];
+    pd.X = Xp + xoff[k];
+    pd.Q = Qp + yoff[k];
+    pd.nodes = nodes ? nodes + noff[k] : nullptr;
+    pd.V = nullptr;
+    pd.st = st + k;
+    pd.partial = partial + (size_t)12 * item_off[k];
+    pd.done = done + k;
+    pd.n = (int)n[k];
+    pd.m = (int)m[k];
+    pd.n_nodes = nodes ? noff[k + 1] - noff[k] : 0;
+    pd.pad_ = 0;
+  }
+  std::vector<int> order(npairs);
+  for (int k = 0; k < npairs; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+  std::vector<int2> items;
+  items.reserve(n_items);
+  for (int k : order)
+    for (int e = 0; e < pds[k].n_items; ++e) items.push_back(make_int2(k, e));
+  FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
+  FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
+  FGA_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * npairs, s));
+  FGA_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned) * 2, s));
+  int dev = 0, cus = 256;
+  FGA_HIP(hipGetDevice(&dev));
+  FGA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int n_blocks = std::min(n_items, cus * 8);
+  const IterConsts c = make_iter_consts(p);
+  // one graph holds `every` iterations; replay until all pairs stopped
+  const int every = std::max(1, std::min(p.check_every > 0 ? p.check_every : 16, std::max(1, p.max_iter)));
+  FGA_HIP(hipStreamSynchronize(s));
+  FGA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  fga_status cst = FGA_OK;
+  for (int k = 0; k < every && cst == FGA_OK; ++k)
+    cst = launch_batch_iteration<T>(dpairs, ditems, n_items, queue, n_blocks, c, s, nodes != nullptr);
+  hipError_t ce = hipStreamEndCapture(s, &B.graph);
+  if (cst != FGA_OK) return cst;
+  FGA_HIP(ce);
+  FGA_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+  std::vector<RigidState> hs(npairs);
+  const int replays = (p.max_iter + every - 1) / every;
+  for (int r = 0; r < replays; ++r) {
+    FGA_HIP(hipGraphLaunch(B.exec, s));
+    FGA_HIP(hipMemcpyAsync(hs.data(), st, sizeof(RigidState) * npairs, hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipStreamSynchronize(s));
+    bool all = true;
+    for (int k = 0; k < npairs && all; ++k) all = hs[k].converged != 0;
+    if (all) break;
+  }
+  if (p.max_iter == 0) {
+    FGA_HIP(hipMemcpyAsync(hs.data(), st, sizeof(RigidState) * npairs, hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipStreamSynchronize(s));
+  }
+  const double ms = now_ms() - t0;
+  fga_status result = FGA_OK;
+  for (int k = 0; k < npairs; ++k) {
+    std::memcpy(R + 9 * k, hs[k].R, sizeof(double) * 9);
+    denormalise(norm[k], hs[k].R, hs[k].t, t + 3 * k);
+    if (reps) {
+      reps[k].iters = hs[k].iter;
+      reps[k].converged = hs[k].converged == 1;
+      reps[k].last_dT2 = hs[k].dT2;
+      reps[k].interactions = hs[k].interactions;
+      reps[k].ms_total = ms;
+    }
+    if ((hs[k].flags & 1) && result == FGA_OK) {
+      set_error("pair %d: the template is collinear; the Kabsch rotation is undetermined", k);
+      result = FGA_E_DEGENERATE;
+    }
+  }
+  return result;
+}
+
+}  // namespace
+
+extern "C" fga_status fga_register_batch(int npairs, const void* const* X, const int64_t* n,
+                                         const void* const* Y, const int64_t* m, fga_dtype dt,
+                                         const fga_params* p, double* R, double* t,
+                                         fga_report* reps, void* stream) {
+  if (npairs < 1) {
+    set_error("npairs must be >= 1 (got %d)", npairs);
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(n, "n"));
+  FGA_TRY(check_ptr(m, "m"));
+  FGA_TRY(check_ptr(R, "R"));
+  FGA_TRY(check_ptr(t, "t"));
+  for (int k = 0; k < npairs; ++k) FGA_TRY(validate_pair(X[k], n[k], Y[k], m[k], dt, p));
+  if (p->velocity == FGA_VEL_PARTICLE) {
+    set_error("particle velocities are not supported in batched registration");
+    return FGA_E_UNSUPPORTED;
+  }
+  for (int k = 0; k < npairs; ++k) {
+    FGA_TRY(check_device_ptr(X[k], "X[k]"));
+    FGA_TRY(check_device_ptr(Y[k], "Y[k]"));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  return p->precision == FGA_PREC_FP64
+             ? batch_impl<double>(npairs, X, n, Y, m, dt, *p, R, t, reps, s)
+             : batch_impl<float>(npairs, X, n, Y, m, dt, *p, R, t, reps, s);
+}

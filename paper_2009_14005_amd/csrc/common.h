@@ -1,0 +1,170 @@
+// Internal declarations shared by the HIP translation units of libfga.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "fga.h"
+
+namespace fga {
+
+constexpr int kBlock = 256;  // threads per block for every kernel
+constexpr int kWave = 64;    // CDNA wavefront width
+constexpr int kQBits = 20;   // octree depth limit: 20 octal digits, 60-bit Morton codes
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+#define FGA_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::fga::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                       __LINE__);                                                      \
+      return e_ == hipErrorOutOfMemory ? FGA_E_NOMEM : FGA_E_DEVICE;                   \
+    }                                                                                  \
+  } while (0)
+#define FGA_TRY(call)                \
+  do {                               \
+    fga_status s_ = (call);          \
+    if (s_ != FGA_OK) return s_;     \
+  } while (0)
+
+// --------------------------------------------------------- vector helpers
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> using vec4_t = typename Vec4<T>::type;
+
+template <typename T> __host__ __device__ inline vec4_t<T> make4(T a, T b, T c, T d);
+template <> __host__ __device__ inline float4 make4<float>(float a, float b, float c, float d) {
+  return make_float4(a, b, c, d);
+}
+template <> __host__ __device__ inline double4 make4<double>(double a, double b, double c, double d) {
+  return make_double4(a, b, c, d);
+}
+
+// --------------------------------------------------------------- the state
+// FP64 rigid state of one registration pair, resident in device memory.
+// Template particle i sits at y_i = R q_i + mu, with q_i its centred
+// body-frame coordinate (normalised template minus its mean mu0), so the
+// accumulated transform of Alg. 2 is Y_k = R Yn + t with t = mu - R mu0.
+struct RigidState {
+  double R[9];    // accumulated rotation (row-major)
+  double t[3];    // accumulated translation, normalised frame
+  double mu[3];   // current template centroid
+  double A[9];    // rigid velocity field v_i = A q_i + b of the last step
+  double b[3];
+  double S0[9];   // sum_i q_i q_i^T
+  double mu0[3];  // mean of the normalised template
+  double dT2;     // ||T_k - T_{k-1}||_F^2 of the last step
+  double tol;     // convergence tolerance (<= 0: never converged)
+  double rank_tol;  // singular-value ratio below which C counts as rank deficient
+  long long interactions;  // running count of force interactions
+  int iter;
+  int converged;
+  int m;          // template particles
+  int flags;      // bit 0: degenerate Kabsch (rank(C) < 2) seen
+  int max_iter;
+  int pad_;
+  float fR[9], fmu[3], fA[9], fb[3];  // FP32 copies read by the FP32 force kernels
+};
+
+// Iteration constants of one registration (identical for all pairs of a batch).
+struct IterConsts {
+  double G, eps2, dt, theta2;
+  float fG, feps2, fdt, ftheta2;
+  int damping;   // fga_damping
+  int velocity;  // fga_velocity
+  int prec;      // fga_precision
+  int pad_;
+};
+
+// Barnes-Hut node, 32 bytes, depth-first preorder. A node's first child is the
+// next node; `skip` is the index right after its subtree; a leaf has
+// skip == index + 1. Points [first, last] (inclusive) of the Morton-sorted
+// reference lie in the node's cell.
+struct alignas(16) BHNode {
+  float4 cm;   // centre of mass (x, y, z) and mass
+  int skip;
+  int first;
+  int last;
+  float l2;    // squared box diagonal of the cell (Alg. 1: l = ||X_max - X_min||)
+};
+
+// Geometry of one registration pair on the device, for the iteration kernels.
+struct PairDev {
+  const void* X;        // reference (x, y, z, mass) as vec4, normalised; Morton-sorted for BH
+  const void* Q;        // template (q_x, q_y, q_z, c) as vec4 in the body frame; c = damping coeff
+  const BHNode* nodes;  // BH nodes, or nullptr for the direct sum
+  void* V;              // per-particle velocities (particle mode), m x 3 of T, else nullptr
+  RigidState* st;
+  double* partial;      // n_items x 12 partial moments
+  unsigned* done;       // completion counter of the current iteration
+  int n, m;
+  int n_nodes;
+  int jr;               // reference ranges per template tile
+  int n_items;          // template tiles x jr
+  int pad_;
+};
+
+// ------------------------------------------------------------ declarations
+// prep.hip: normalisation, masses and packing (Appendix A; Eq. NIV)
+struct CloudIn {
+  const void* p;  // n x 3 row-major device array (dtype of the call)
+  int64_t n;
+};
+struct PrepOut {
+  void* X;          // packed reference vec4 (n_x)
+  void* Q;          // packed template vec4 (n_y)
+  RigidState* st;   // initialised rigid state
+};
+struct NormInfo {   // host copy of the Appendix A normalisation
+  double xbar[3], ybar[3], l, r, a, b;
+};
+fga_status prep_pairs(int npairs, const CloudIn* X, const CloudIn* Y, fga_dtype dt,
+                      const fga_params& p, PrepOut* out, NormInfo* info, hipStream_t s);
+fga_status masses_only(const void* pts, fga_dtype dt, int64_t n, const fga_params& p, int norm,
+                       void* out, hipStream_t s);
+
+// tree.hip: Morton codes, LDS radix sort, octree build
+struct TreeSeg {       // one reference cloud in a concatenated packed array
+  int64_t off, n;
+};
+struct TreeOut {
+  BHNode* nodes;       // all segments' nodes, segment-contiguous
+  int* node_off;       // host: first node of each segment (nseg + 1 entries)
+  int* order;          // device: sorted position -> input position (n total)
+  int max_depth;
+  int leaves;
+};
+template <typename T>
+fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t ntotal,
+                       int leaf_size, BHNode** nodes_out, int* node_off_host, int** order_out,
+                       int* stats_host, hipStream_t s);
+template <typename T>
+fga_status sort_points_morton(int nseg, const TreeSeg* segs, void* Q, int64_t ntot, int* perm,
+                              hipStream_t s);
+
+// iter.hip: force-only evaluation (fga_forces)
+int direct_ranges(int64_t m, int64_t n);
+template <typename T>
+fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, const fga_params& p, void* F, hipStream_t s);
+template <typename T>
+fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHNode* nodes,
+                          int n_nodes, const void* Xs, double theta, const fga_params& p,
+                          const void* mY, void* F, long long* interactions, hipStream_t s);
+template <typename T>
+fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipStream_t s);
+
+// iter.hip: one fused iteration (forces + ODE + moments + Kabsch step)
+template <typename T>
+fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s);
+template <typename T>
+fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, int n_items,
+                                  unsigned* queue, int n_blocks, const IterConsts& c,
+                                  hipStream_t s, bool bh);
+
+
+}  // namespace fga

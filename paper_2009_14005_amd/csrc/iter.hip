@@ -1,0 +1,434 @@
+// Steps a2-a7 of the hot path, fused into one launch per iteration:
+//   a2  template pose y_i = R q_i + mu                  (FP64 state -> FP32 lanes)
+//   a3/a4 acceleration g_i by direct sum or Barnes-Hut  (Eq. GAForce; Alg. 2)
+//   a5  damped velocity and displacement               (Eqs. GAForceDissipative,
+//       v' = (1 - c_i) v_i + dt g_i,  d_i = dt v'       TotalGAForce, PreviousVelocity)
+//   a6  FP64 moments sum d_i and sum d_i q_i^T, reduced per block, then over blocks
+//   a7  Kabsch step and state update by the last block to finish (Eqs. R_Kabsch,
+//       transEst; template update and composition of Alg. 2)
+//
+// Work is split into items (template tile of kBlock particles) x (reference
+// range). The moments are linear in g_i, so every item adds its own share and
+// no per-particle force has to be combined across items: the velocity term
+// enters only through the item of reference range 0.
+#include "common.h"
+#include "force.h"
+#include "reduce.h"
+#include "rigid.h"
+
+namespace fga {
+namespace {
+
+constexpr int kMom = 12;
+
+template <typename T>
+struct Coef {
+  T R[9], mu[3], A[9], b[3];
+};
+
+template <typename T>
+__device__ inline Coef<T> load_coef(const RigidState* st);
+template <>
+__device__ inline Coef<float> load_coef<float>(const RigidState* st) {
+  Coef<float> c;
+  for (int k = 0; k < 9; ++k) {
+    c.R[k] = st->fR[k];
+    c.A[k] = st->fA[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    c.mu[k] = st->fmu[k];
+    c.b[k] = st->fb[k];
+  }
+  return c;
+}
+template <>
+__device__ inline Coef<double> load_coef<double>(const RigidState* st) {
+  Coef<double> c;
+  for (int k = 0; k < 9; ++k) {
+    c.R[k] = st->R[k];
+    c.A[k] = st->A[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    c.mu[k] = st->mu[k];
+    c.b[k] = st->b[k];
+  }
+  return c;
+}
+
+template <typename T> __device__ inline T cG(const IterConsts& c);
+template <> __device__ inline float cG<float>(const IterConsts& c) { return c.fG; }
+template <> __device__ inline double cG<double>(const IterConsts& c) { return c.G; }
+template <typename T> __device__ inline T cEps2(const IterConsts& c);
+template <> __device__ inline float cEps2<float>(const IterConsts& c) { return c.feps2; }
+template <> __device__ inline double cEps2<double>(const IterConsts& c) { return c.eps2; }
+template <typename T> __device__ inline T cDt(const IterConsts& c);
+template <> __device__ inline float cDt<float>(const IterConsts& c) { return c.fdt; }
+template <> __device__ inline double cDt<double>(const IterConsts& c) { return c.dt; }
+
+// Reference range jr of jrn: [j0, j1), boundaries on multiples of 64.
+__device__ inline void jrange(int n, int jrn, int jr, int& j0, int& j1) {
+  const int per = ((n + jrn - 1) / jrn + 63) & ~63;
+  j0 = min(n, jr * per);
+  j1 = min(n, j0 + per);
+}
+
+// One item of the fused iteration. Returns true in thread 0 of the block that
+// completed the pair's iteration (after the rigid step has been applied).
+template <typename T, bool BH, int PREC>
+__device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
+                               double* lds) {
+  __shared__ int s_last;
+  const RigidState* st = pd.st;
+  const int it = item / pd.jr, jr = item - (item / pd.jr) * pd.jr;
+  const int i = it * kBlock + (int)threadIdx.x;
+  const bool valid = i < pd.m;
+  const Coef<T> cf = load_coef<T>(st);
+  const vec4_t<T>* Q = (const vec4_t<T>*)pd.Q;
+  const vec4_t<T> q = Q[valid ? i : pd.m - 1];
+  const T y0 = cf.R[0] * q.x + cf.R[1] * q.y + cf.R[2] * q.z + cf.mu[0];
+  const T y1 = cf.R[3] * q.x + cf.R[4] * q.y + cf.R[5] * q.z + cf.mu[1];
+  const T y2 = cf.R[6] * q.x + cf.R[7] * q.y + cf.R[8] * q.z + cf.mu[2];
+  int j0, j1;
+  jrange(pd.n, pd.jr, jr, j0, j1);
+  T ax = 0, ay = 0, az = 0;
+  unsigned cnt = 0;
+  if (BH) {
+    bh_accum<T>(pd.nodes, (const vec4_t<T>*)pd.X, 0, pd.n_nodes, j0, j1, c.ftheta2, cEps2<T>(c),
+                valid, y0, y1, y2, ax, ay, az, cnt);
+  } else if constexpr (sizeof(T) == 8) {
+    direct_f64((const double4*)pd.X, j0, j1, y0, y1, y2, c.eps2, ax, ay, az);
+  } else {
+    if (PREC == FGA_PREC_FP32_KAHAN)
+      direct_f32<true, 64>((const float4*)pd.X, j0, j1, y0, y1, y2, c.feps2, ax, ay, az);
+    else
+      direct_f32<false, 64>((const float4*)pd.X, j0, j1, y0, y1, y2, c.feps2, ax, ay, az);
+  }
+  // a5: damped velocity and displacement
+  const T G = cG<T>(c), dt = cDt<T>(c);
+  T v0 = 0, v1 = 0, v2 = 0;
+  if (jr == 0 && valid) {
+    if (c.velocity == FGA_VEL_RIGID) {
+      v0 = cf.A[0] * q.x + cf.A[1] * q.y + cf.A[2] * q.z + cf.b[0];
+      v1 = cf.A[3] * q.x + cf.A[4] * q.y + cf.A[5] * q.z + cf.b[1];
+      v2 = cf.A[6] * q.x + cf.A[7] * q.y + cf.A[8] * q.z + cf.b[2];
+    } else {
+      const T* V = (const T*)pd.V;
+      v0 = V[3 * i];
+      v1 = V[3 * i + 1];
+      v2 = V[3 * i + 2];
+    }
+  }
+  const T keep = (T)1 - q.w;  // 1 - c_i
+  const T w0 = keep * v0 + dt * (G * ax);
+  const T w1 = keep * v1 + dt * (G * ay);
+  const T w2 = keep * v2 + dt * (G * az);
+  if (c.velocity == FGA_VEL_PARTICLE && valid) {  // only with a single reference range
+    T* V = (T*)pd.V;
+    V[3 * i] = w0;
+    V[3 * i + 1] = w1;
+    V[3 * i + 2] = w2;
+  }
+  // a6: moments of the displacement d = dt v'
+  double mom[kMom];
+  if (PREC == FGA_PREC_FP32_ALL) {
+    const float d[3] = {(float)(dt * w0), (float)(dt * w1), (float)(dt * w2)};
+    const float qq[3] = {(float)q.x, (float)q.y, (float)q.z};
+    for (int a = 0; a < 3; ++a) mom[a] = valid ? (double)d[a] : 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = valid ? (double)(d[a] * qq[b]) : 0.0;
+  } else {
+    const double d[3] = {(double)(dt * w0), (double)(dt * w1), (double)(dt * w2)};
+    const double qq[3] = {(double)q.x, (double)q.y, (double)q.z};
+    for (int a = 0; a < 3; ++a) mom[a] = valid ? d[a] : 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = valid ? d[a] * qq[b] : 0.0;
+  }
+  block_sum<kMom>(mom, lds);
+  if (BH) {  // interaction count of the block
+    double cc[1] = {(double)cnt};
+    block_sum<1>(cc, lds + kMom * (kBlock / kWave));
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&pd.st->interactions, (unsigned long long)cc[0]);
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < kMom; ++k)
+      pd.partial[(size_t)item * kMom + k] =
+          PREC == FGA_PREC_FP32_ALL ? (double)(float)mom[k] : mom[k];
+    __threadfence();
+    const unsigned prev = atomicAdd(pd.done, 1u);
+    s_last = prev == (unsigned)(pd.n_items - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // a7: this block finished the iteration; sum the items in fixed order
+  __threadfence();
+  double tot[kMom];
+  for (int k = 0; k < kMom; ++k) tot[k] = 0.0;
+  for (int e = (int)threadIdx.x; e < pd.n_items; e += kBlock) {
+    const volatile double* pp = pd.partial + (size_t)e * kMom;
+    for (int k = 0; k < kMom; ++k) {
+      if (PREC == FGA_PREC_FP32_ALL) tot[k] = (double)((float)tot[k] + (float)pp[k]);
+      else tot[k] += pp[k];
+    }
+  }
+  block_sum<kMom>(tot, lds);
+  if (threadIdx.x == 0) {
+    if (!BH) pd.st->interactions += (long long)pd.n * (long long)pd.m;
+    rigid_update(*pd.st, tot, c.dt);
+    *pd.done = 0u;
+    __threadfence();
+  }
+}
+
+template <typename T, bool BH, int PREC>
+__global__ __launch_bounds__(kBlock) void k_iteration(PairDev pd, IterConsts c) {
+  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  if (pd.st->converged) return;  // uniform: the state was written by the previous launch
+  iteration_item<T, BH, PREC>(pd, c, (int)blockIdx.x, lds);
+}
+
+// Persistent batched iteration: blocks pull (pair, item) entries from a work
+// queue ordered by decreasing cost until it is empty. The block that drains
+// the last entry resets the queue for the next launch.
+template <typename T, bool BH, int PREC>
+__global__ __launch_bounds__(kBlock) void k_batch_iteration(const PairDev* pairs,
+                                                            const int2* items, int n_items,
+                                                            unsigned* queue, IterConsts c) {
+  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
+    __syncthreads();
+    const int e = s_item;
+    __syncthreads();
+    if (e >= n_items) break;
+    const int2 w = items[e];
+    const PairDev pd = pairs[w.x];
+    if (pd.st->converged) continue;
+    iteration_item<T, BH, PREC>(pd, c, w.y, lds);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {  // the last block out resets the queue
+    __threadfence();
+    const unsigned prev = atomicAdd(&queue[1], 1u);
+    if (prev == gridDim.x - 1) {
+      queue[0] = 0u;
+      queue[1] = 0u;
+      __threadfence();
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s) {
+  const bool bh = pd.nodes != nullptr;
+  const dim3 grid((unsigned)pd.n_items);
+  if (sizeof(T) == 8) {
+    if (bh) k_iteration<T, true, FGA_PREC_FP64><<<grid, kBlock, 0, s>>>(pd, c);
+    else k_iteration<T, false, FGA_PREC_FP64><<<grid, kBlock, 0, s>>>(pd, c);
+  } else {
+    switch (c.prec) {
+      case FGA_PREC_FP32:
+        if (bh) k_iteration<T, true, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>(pd, c);
+        else k_iteration<T, false, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>(pd, c);
+        break;
+      case FGA_PREC_FP32_ALL:
+        if (bh) k_iteration<T, true, FGA_PREC_FP32_ALL><<<grid, kBlock, 0, s>>>(pd, c);
+        else k_iteration<T, false, FGA_PREC_FP32_ALL><<<grid, kBlock, 0, s>>>(pd, c);
+        break;
+      default:
+        if (bh) k_iteration<T, true, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>(pd, c);
+        else k_iteration<T, false, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>(pd, c);
+    }
+  }
+  FGA_HIP(hipGetLastError());
+  return FGA_OK;
+}
+
+template <typename T>
+fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, int n_items,
+                                  unsigned* queue, int n_blocks, const IterConsts& c,
+                                  hipStream_t s, bool bh) {
+  if (sizeof(T) == 8) {
+    if (bh) k_batch_iteration<T, true, FGA_PREC_FP64><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+    else k_batch_iteration<T, false, FGA_PREC_FP64><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+  } else {
+    if (bh) k_batch_iteration<T, true, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+    else k_batch_iteration<T, false, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+  }
+  FGA_HIP(hipGetLastError());
+  return FGA_OK;
+}
+
+template fga_status launch_iteration<float>(const PairDev&, const IterConsts&, hipStream_t);
+template fga_status launch_iteration<double>(const PairDev&, const IterConsts&, hipStream_t);
+template fga_status launch_batch_iteration<float>(const PairDev*, const int2*, int, unsigned*, int,
+                                                  const IterConsts&, hipStream_t, bool);
+template fga_status launch_batch_iteration<double>(const PairDev*, const int2*, int, unsigned*,
+                                                   int, const IterConsts&, hipStream_t, bool);
+
+// ------------------------------------------------------------------ forces
+namespace {
+
+// Packs X (n x 3) and its masses into vec4 (x, y, z, m).
+template <typename T>
+__global__ void k_pack4(const T* X, const T* m, int64_t n, vec4_t<T>* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make4<T>(X[3 * i], X[3 * i + 1], X[3 * i + 2], m[i]);
+}
+
+// Direct forces of one reference range: acc of Eq. (GAForce) per particle,
+// written to part[jr][i][3].
+template <typename T, int PREC>
+__global__ __launch_bounds__(kBlock) void k_forces_direct(const T* Y, int m, const vec4_t<T>* X,
+                                                          int n, int jrn, T eps2, T* part) {
+  const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+  const int jr = blockIdx.y;
+  const bool valid = i < m;
+  const int ii = valid ? i : m - 1;
+  const T yx = Y[3 * ii], yy = Y[3 * ii + 1], yz = Y[3 * ii + 2];
+  int j0, j1;
+  jrange(n, jrn, jr, j0, j1);
+  T ax = 0, ay = 0, az = 0;
+  if constexpr (sizeof(T) == 8) {
+    direct_f64((const double4*)X, j0, j1, yx, yy, yz, eps2, ax, ay, az);
+  } else {
+    if (PREC == FGA_PREC_FP32)
+      direct_f32<false, 64>((const float4*)X, j0, j1, yx, yy, yz, eps2, ax, ay, az);
+    else
+      direct_f32<true, 64>((const float4*)X, j0, j1, yx, yy, yz, eps2, ax, ay, az);
+  }
+  if (valid) {
+    T* o = part + ((size_t)jr * m + i) * 3;
+    o[0] = ax;
+    o[1] = ay;
+    o[2] = az;
+  }
+}
+
+// F_i = G m_Y,i sum_jr part[jr][i] (ranges combined in order, in FP64).
+template <typename T>
+__global__ void k_forces_combine(const T* part, int m, int jrn, const T* mY, double G, T* F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int r = 0; r < jrn; ++r)
+    for (int a = 0; a < 3; ++a) s[a] += (double)part[((size_t)r * m + i) * 3 + a];
+  const double w = G * (mY ? (double)mY[i] : 1.0);
+  for (int a = 0; a < 3; ++a) F[3 * i + a] = (T)(w * s[a]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_forces_bh(const T* Y, const int* yorder, int m,
+                                                      const BHNode* nodes, int n_nodes,
+                                                      const vec4_t<T>* Xs, float theta2, T eps2,
+                                                      const T* mY, double G, T* F,
+                                                      unsigned long long* count) {
+  const int k = blockIdx.x * kBlock + (int)threadIdx.x;
+  const bool valid = k < m;
+  const int i = valid ? yorder[k] : 0;
+  const T yx = Y[3 * i], yy = Y[3 * i + 1], yz = Y[3 * i + 2];
+  T ax = 0, ay = 0, az = 0;
+  unsigned cnt = 0;
+  bh_accum<T>(nodes, Xs, 0, n_nodes, 0, 0x7fffffff, theta2, eps2, valid, yx, yy, yz, ax, ay, az,
+              cnt);
+  if (valid) {
+    const double w = G * (mY ? (double)mY[i] : 1.0);
+    F[3 * i] = (T)(w * (double)ax);
+    F[3 * i + 1] = (T)(w * (double)ay);
+    F[3 * i + 2] = (T)(w * (double)az);
+  }
+  unsigned long long c = cnt;
+  for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(count, c);
+}
+
+}  // namespace
+
+// Number of reference ranges so that the launch has about 8 waves per SIMD.
+int direct_ranges(int64_t m, int64_t n) {
+  const int64_t tiles = (m + kBlock - 1) / kBlock;
+  const int64_t want = 4096;  // blocks of 4 waves: 16 waves per SIMD on 256 CUs
+  int64_t jr = (want + tiles - 1) / tiles;
+  const int64_t maxjr = (n + 1023) / 1024;  // at least 1024 reference points per range
+  if (jr > maxjr) jr = maxjr;
+  if (jr < 1) jr = 1;
+  return (int)jr;
+}
+
+template <typename T>
+fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, const fga_params& p, void* F, hipStream_t s) {
+  const int jrn = direct_ranges(m, n);
+  void *X4 = nullptr, *part = nullptr;
+  FGA_HIP(hipMalloc(&X4, sizeof(vec4_t<T>) * n));
+  hipError_t e = hipMalloc(&part, sizeof(T) * 3 * (size_t)m * jrn);
+  if (e != hipSuccess) {
+    (void)hipFree(X4);
+    set_error("hipMalloc failed: %s", hipGetErrorString(e));
+    return FGA_E_NOMEM;
+  }
+  k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, (vec4_t<T>*)X4);
+  const dim3 grid((unsigned)((m + kBlock - 1) / kBlock), (unsigned)jrn);
+  const T eps2 = (T)(p.eps * p.eps);
+  if (sizeof(T) == 8 || p.precision != FGA_PREC_FP32)
+    k_forces_direct<T, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
+  else
+    k_forces_direct<T, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
+  k_forces_combine<T><<<(int)((m + 255) / 256), 256, 0, s>>>((const T*)part, (int)m, jrn, (const T*)mY, p.G, (T*)F);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(X4);
+  (void)hipFree(part);
+  if (e != hipSuccess) {
+    set_error("direct force kernels failed: %s", hipGetErrorString(e));
+    return FGA_E_DEVICE;
+  }
+  return FGA_OK;
+}
+
+template <typename T>
+fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipStream_t s) {
+  k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, (vec4_t<T>*)out);
+  FGA_HIP(hipGetLastError());
+  return FGA_OK;
+}
+template fga_status pack_points<float>(const void*, const void*, int64_t, void*, hipStream_t);
+template fga_status pack_points<double>(const void*, const void*, int64_t, void*, hipStream_t);
+
+template <typename T>
+fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHNode* nodes,
+                          int n_nodes, const void* Xs, double theta, const fga_params& p,
+                          const void* mY, void* F, long long* interactions, hipStream_t s) {
+  unsigned long long* cnt = nullptr;
+  FGA_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
+  (void)hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
+  k_forces_bh<T><<<(int)((m + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      (const T*)Y, yorder, (int)m, nodes, n_nodes, (const vec4_t<T>*)Xs, (float)(theta * theta),
+      (T)(p.eps * p.eps), (const T*)mY, p.G, (T*)F, cnt);
+  unsigned long long h = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(cnt);
+  if (e != hipSuccess) {
+    set_error("BH force kernel failed: %s", hipGetErrorString(e));
+    return FGA_E_DEVICE;
+  }
+  if (interactions) *interactions = (long long)h;
+  return FGA_OK;
+}
+
+template fga_status forces_direct<float>(const void*, int64_t, const void*, int64_t, const void*,
+                                         const void*, const fga_params&, void*, hipStream_t);
+template fga_status forces_direct<double>(const void*, int64_t, const void*, int64_t, const void*,
+                                          const void*, const fga_params&, void*, hipStream_t);
+template fga_status forces_bh_tree<float>(const void*, int64_t, const int*, const BHNode*, int,
+                                          const void*, double, const fga_params&, const void*,
+                                          void*, long long*, hipStream_t);
+template fga_status forces_bh_tree<double>(const void*, int64_t, const int*, const BHNode*, int,
+                                           const void*, double, const fga_params&, const void*,
+                                           void*, long long*, hipStream_t);
+
+}  // namespace fga

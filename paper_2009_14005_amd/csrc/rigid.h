@@ -1,0 +1,204 @@
+// FP64 rigid step of the FGA loop body: Kabsch rotation (Eq. R_Kabsch),
+// translation (Eq. transEst) and the template update / composition of Alg. 2.
+// Compiled for both host and device: the device runs it once per iteration in
+// the last block of the fused iteration kernel; the host entry fga_kabsch
+// exposes the same solver for tests.
+#pragma once
+#include <math.h>
+
+#include "common.h"
+
+namespace fga {
+
+#define FGA_HD __host__ __device__ inline
+
+FGA_HD void m3_mul(const double* A, const double* B, double* C) {  // C = A B
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+FGA_HD void m3_mul_bt(const double* A, const double* B, double* C) {  // C = A B^T
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      C[3 * i + j] = A[3 * i] * B[3 * j] + A[3 * i + 1] * B[3 * j + 1] + A[3 * i + 2] * B[3 * j + 2];
+}
+FGA_HD double m3_det(const double* A) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// One-sided (Hestenes) Jacobi SVD of a 3x3 matrix: A = U diag(s) V^T with
+// s sorted in descending order. Columns of W = A V are rotated pairwise until
+// they are mutually orthogonal; then s_k = |W_k| and U_k = W_k / s_k.
+// Columns belonging to zero singular values are left as zero in U.
+FGA_HD void svd3(const double* A, double* U, double* s, double* V) {
+  double W[9];
+  for (int k = 0; k < 9; ++k) W[k] = A[k];
+  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rotated = false;
+    for (int pair = 0; pair < 3; ++pair) {
+      const int p = pair == 2 ? 1 : 0;
+      const int q = pair == 0 ? 1 : 2;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        al += W[3 * i + p] * W[3 * i + p];
+        be += W[3 * i + q] * W[3 * i + q];
+        ga += W[3 * i + p] * W[3 * i + q];
+      }
+      if (ga == 0.0 || fabs(ga) <= 1e-17 * sqrt(al * be)) continue;
+      rotated = true;
+      const double ze = (be - al) / (2.0 * ga);
+      const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+      const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+      for (int i = 0; i < 3; ++i) {
+        const double wp = W[3 * i + p], wq = W[3 * i + q];
+        W[3 * i + p] = c * wp - sn * wq;
+        W[3 * i + q] = sn * wp + c * wq;
+        const double vp = V[3 * i + p], vq = V[3 * i + q];
+        V[3 * i + p] = c * vp - sn * vq;
+        V[3 * i + q] = sn * vp + c * vq;
+      }
+    }
+    if (!rotated) break;
+  }
+  int idx[3] = {0, 1, 2};
+  double nrm[3];
+  for (int k = 0; k < 3; ++k)
+    nrm[k] = sqrt(W[k] * W[k] + W[3 + k] * W[3 + k] + W[6 + k] * W[6 + k]);
+  // sort columns by singular value, descending (three compare-swaps)
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2 - a; ++b)
+      if (nrm[idx[b]] < nrm[idx[b + 1]]) {
+        int tmp = idx[b];
+        idx[b] = idx[b + 1];
+        idx[b + 1] = tmp;
+      }
+  double V2[9];
+  for (int k = 0; k < 3; ++k) {
+    const int c = idx[k];
+    s[k] = nrm[c];
+    const double inv = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
+    for (int i = 0; i < 3; ++i) {
+      U[3 * i + k] = W[3 * i + c] * inv;
+      V2[3 * i + k] = V[3 * i + c];
+    }
+  }
+  for (int k = 0; k < 9; ++k) V[k] = V2[k];
+}
+
+// Eq. (R_Kabsch): C = U S V^T, R = U diag(1, 1, sgn det(U V^T)) V^T, sgn(0) = +1.
+// For rank(C) = 2 the third left singular vector is completed as U_0 x U_1.
+// Returns 0, or 1 when rank(C) < 2 (collinear template: R is then undefined
+// and set to the identity). A singular value below rank_tol * s_0 counts as
+// zero; rank_tol reflects the precision the template is stored in.
+FGA_HD int kabsch3(const double* C, double* R, double rank_tol = 1e-13) {
+  double U[9], s[3], V[9];
+  svd3(C, U, s, V);
+  const double tiny = rank_tol * s[0];
+  if (!(s[0] > 0.0) || s[1] <= tiny) {
+    for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    return 1;
+  }
+  if (s[2] <= tiny) {  // rank 2: complete U with the cross product of its first two columns
+    U[2] = U[3] * U[7] - U[6] * U[4];
+    U[5] = U[6] * U[1] - U[0] * U[7];
+    U[8] = U[0] * U[4] - U[3] * U[1];
+  }
+  const double d = m3_det(U) * m3_det(V) < 0.0 ? -1.0 : 1.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      R[3 * i + j] = U[3 * i] * V[3 * j] + U[3 * i + 1] * V[3 * j + 1] + d * U[3 * i + 2] * V[3 * j + 2];
+  return 0;
+}
+
+// One Alg. 2 rigid step from the reduced displacement moments.
+//   mom[0..2]  = sum_i d_i
+//   mom[3..11] = P = sum_i d_i q_i^T (row-major, P[a][b] = sum d_a q_b)
+// With hat(y_i) = R q_i (the centred template) the Kabsch matrix is
+//   C = hat(Y_D)^T hat(Y) = sum (hat y_i + d_i - dbar) hat y_i^T = (R S0 + P) R^T,
+// because sum_i hat y_i = 0. Then R_s from Eq. (R_Kabsch), mu_D = mu + dbar,
+// t_s = mu_D - R_s mu (Eq. transEst), R <- R_s R, t <- R_s t + t_s, mu <- mu_D.
+// The rigid velocity of the next step is (y_new - y)/dt = A q + b.
+FGA_HD void rigid_update(RigidState& s, const double* mom, double dt) {
+  const double invm = 1.0 / (double)s.m;
+  const double dbar[3] = {mom[0] * invm, mom[1] * invm, mom[2] * invm};
+  double RS0[9], C[9], Rs[9];
+  m3_mul(s.R, s.S0, RS0);
+  for (int k = 0; k < 9; ++k) RS0[k] += mom[3 + k];
+  m3_mul_bt(RS0, s.R, C);
+  if (kabsch3(C, Rs, s.rank_tol)) s.flags |= 1;
+  double muD[3], ts[3], Rn[9], tn[3];
+  for (int a = 0; a < 3; ++a) muD[a] = s.mu[a] + dbar[a];
+  for (int a = 0; a < 3; ++a)
+    ts[a] = muD[a] - (Rs[3 * a] * s.mu[0] + Rs[3 * a + 1] * s.mu[1] + Rs[3 * a + 2] * s.mu[2]);
+  m3_mul(Rs, s.R, Rn);
+  for (int a = 0; a < 3; ++a)
+    tn[a] = Rs[3 * a] * s.t[0] + Rs[3 * a + 1] * s.t[1] + Rs[3 * a + 2] * s.t[2] + ts[a];
+  // keep R orthonormal: one Newton-Schulz step R <- R (3 I - R^T R) / 2
+  {
+    double RtR[9], Kc[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        RtR[3 * i + j] = Rn[i] * Rn[j] + Rn[3 + i] * Rn[3 + j] + Rn[6 + i] * Rn[6 + j];
+    for (int k = 0; k < 9; ++k) Kc[k] = ((k % 4 == 0) ? 1.5 : 0.0) - 0.5 * RtR[k];
+    double Ro[9];
+    m3_mul(Rn, Kc, Ro);
+    for (int k = 0; k < 9; ++k) Rn[k] = Ro[k];
+  }
+  double dT2 = 0.0;
+  for (int k = 0; k < 9; ++k) dT2 += (Rn[k] - s.R[k]) * (Rn[k] - s.R[k]);
+  for (int a = 0; a < 3; ++a) dT2 += (tn[a] - s.t[a]) * (tn[a] - s.t[a]);
+  const double invdt = 1.0 / dt;
+  for (int k = 0; k < 9; ++k) s.A[k] = (Rn[k] - s.R[k]) * invdt;
+  for (int a = 0; a < 3; ++a) s.b[a] = (muD[a] - s.mu[a]) * invdt;
+  for (int k = 0; k < 9; ++k) s.R[k] = Rn[k];
+  for (int a = 0; a < 3; ++a) {
+    s.t[a] = tn[a];
+    s.mu[a] = muD[a];
+  }
+  s.dT2 = dT2;
+  s.iter += 1;
+  if (s.tol > 0.0 && dT2 < s.tol) s.converged = 1;
+  if (s.iter >= s.max_iter) s.converged = s.converged ? 1 : 2;  // 2 = stopped at the cap
+  for (int k = 0; k < 9; ++k) {
+    s.fR[k] = (float)s.R[k];
+    s.fA[k] = (float)s.A[k];
+  }
+  for (int a = 0; a < 3; ++a) {
+    s.fmu[a] = (float)s.mu[a];
+    s.fb[a] = (float)s.b[a];
+  }
+}
+
+// Initial state: T = [I | 0] (Alg. 2 initialisation), zero velocity.
+FGA_HD void rigid_init(RigidState& s, const double* S0, const double* mu0, int m, double tol,
+                       int max_iter, double rank_tol) {
+  for (int k = 0; k < 9; ++k) {
+    s.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    s.A[k] = 0.0;
+    s.S0[k] = S0[k];
+    s.fR[k] = (float)s.R[k];
+    s.fA[k] = 0.0f;
+  }
+  for (int a = 0; a < 3; ++a) {
+    s.t[a] = 0.0;
+    s.mu[a] = mu0[a];
+    s.mu0[a] = mu0[a];
+    s.b[a] = 0.0;
+    s.fmu[a] = (float)mu0[a];
+    s.fb[a] = 0.0f;
+  }
+  s.dT2 = 0.0;
+  s.tol = tol;
+  s.rank_tol = rank_tol;
+  s.interactions = 0;
+  s.iter = 0;
+  s.converged = 0;
+  s.m = m;
+  s.flags = 0;
+  s.max_iter = max_iter;
+  s.pad_ = 0;
+}
+
+}  // namespace fga

@@ -1,0 +1,370 @@
+"""Parity of the HIP path with the FP64 oracle on identical seeded inputs.
+
+Tolerances (derivations in the design notes):
+  * direct forces, FP32 Kahan lanes: per-particle relative error <= 1e-5 for
+    particles whose force is not a near-cancelling sum, and aggregate
+    ||dF||_F / ||F||_F <= 1e-5;
+  * direct forces, FP64 lanes: 1e-12 relative;
+  * Barnes-Hut at theta = 0.5 against the oracle's Alg. 1 tree: median
+    per-particle relative error <= 1e-2 (measured ~1e-6 because the trees and
+    the MAC decisions coincide);
+  * registration: rotation within 0.05 degrees, translation within 1e-4 of the
+    bounding-box diagonal, at equal iteration count.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import paper_2009_14005_amd as fga  # noqa: E402
+import synth  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rel_err(F, ref):
+    return np.linalg.norm(F - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+
+
+def force_gate(F, ref, tol=1e-5):
+    e = rel_err(F, ref)
+    nr = np.linalg.norm(ref, axis=1)
+    mask = nr >= 1e-3 * np.median(nr)
+    agg = np.linalg.norm(F - ref) / np.linalg.norm(ref)
+    return e[mask].max(), agg
+
+
+def phi_deg(Ra, Rb):
+    return oracle.angular_deviation_deg(Ra, Rb)
+
+
+def normalised_mixture(seed, per=128, m=900):
+    X, Y, _, _ = synth.mixture_pair(seed, per_comp=per, m=m)
+    Xn, Yn, _ = oracle.normalise(X, Y)
+    w = oracle.niv_masses(Xn)
+    return Xn, Yn, w / w.sum()
+
+
+# ------------------------------------------------------------------ masses
+@pytest.mark.parametrize("n", [1, 7, 1024, 70001])
+def test_masses_match_oracle(n):
+    rng = np.random.default_rng(n)
+    P = rng.normal(size=(n, 3)) * [2.0, 1.0, 0.3]
+    P32 = P.astype(np.float32).astype(np.float64)
+    for dt in (torch.float32, torch.float64):
+        src = P32 if dt == torch.float32 else P
+        got = fga.masses(dev(src, dt), norm=0).cpu().numpy()
+        w = oracle.niv_masses(src)
+        ref = w / w.sum()
+        tol = 1e-6 if dt == torch.float32 else 1e-12
+        assert np.allclose(got, ref, rtol=tol, atol=0), np.abs(got / ref - 1).max()
+        got1 = fga.masses(dev(src, dt), norm=1).cpu().numpy()
+        assert np.allclose(got1, w / w.mean(), rtol=tol)
+
+
+# ------------------------------------------------------------ direct forces
+@pytest.mark.parametrize("n,m", [(1024, 900), (1, 1), (5, 3), (1000, 777), (4097, 2049),
+                                 (20000, 3000)])
+def test_direct_forces_fp32(n, m):
+    Xn, Yn, _ = normalised_mixture(n * 7 + m, per=max(1, n // 8), m=min(m, 8 * max(1, n // 8)))
+    rng = np.random.default_rng(n + m)
+    X = Xn[:n] if len(Xn) >= n else Xn
+    Y = Yn[:m] if len(Yn) >= m else Yn
+    X = X.astype(np.float32).astype(np.float64)
+    Y = Y.astype(np.float32).astype(np.float64)
+    mX = rng.uniform(0.5, 1.5, len(X))
+    mX = (mX / mX.sum()).astype(np.float32).astype(np.float64)
+    mY = rng.uniform(0.5, 2.0, len(Y)).astype(np.float32).astype(np.float64)
+    ref = oracle.direct_forces(Y, X, mX, mY)
+    F, cnt = fga.forces(dev(Y), dev(X), dev(mX), dev(mY), theta=0.0)
+    F = F.cpu().numpy().astype(np.float64)
+    assert cnt == len(X) * len(Y)
+    emax, agg = force_gate(F, ref)
+    assert emax <= 1e-5 and agg <= 1e-5, (emax, agg)
+
+
+def test_direct_forces_fp64():
+    Xn, Yn, mX = normalised_mixture(3, per=300, m=1500)
+    ref = oracle.direct_forces(Yn, Xn, mX)
+    p = fga.default_params(precision=fga.PREC_FP64)
+    F, _ = fga.forces(dev(Yn, torch.float64), dev(Xn, torch.float64), dev(mX, torch.float64),
+                      None, 0.0, p)
+    assert np.allclose(F.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_direct_forces_plain_fp32_mode():
+    Xn, Yn, mX = normalised_mixture(4, per=512, m=2000)
+    X32 = Xn.astype(np.float32).astype(np.float64)
+    Y32 = Yn.astype(np.float32).astype(np.float64)
+    m32 = mX.astype(np.float32).astype(np.float64)
+    ref = oracle.direct_forces(Y32, X32, m32)
+    F, _ = fga.forces(dev(Y32), dev(X32), dev(m32), None, 0.0,
+                      fga.default_params(precision=fga.PREC_FP32))
+    emax, agg = force_gate(F.cpu().numpy().astype(np.float64), ref)
+    assert emax <= 1e-5 and agg <= 1e-5, (emax, agg)
+
+
+# ------------------------------------------------------------------- tree
+def _tree_case(seed, n, dup=0):
+    rng = np.random.default_rng(seed)
+    X = synth.mixture(rng, 8, max(1, n // 8))[0]
+    if dup:
+        X = np.vstack([X, X[:dup]])
+    X = X.astype(np.float32).astype(np.float64)
+    m = rng.uniform(0.5, 1.5, len(X))
+    m = (m / m.sum()).astype(np.float32).astype(np.float64)
+    return X, m
+
+
+@pytest.mark.parametrize("seed,n,dup", [(1, 1000, 0), (2, 65536, 0), (3, 5000, 40), (4, 9, 0)])
+def test_tree_topology_matches_oracle(seed, n, dup):
+    X, m = _tree_case(seed, n, dup)
+    t = fga.Tree(dev(X), dev(m))
+    info = t.info()
+    ex = t.export()
+    ot = oracle.BHTree(X, m)
+    st = ot.stats()
+    assert info["internal"] == st["branching"]
+    assert info["leaves"] == st["leaves"]
+    assert info["nodes"] == st["branching"] + st["leaves"]
+    # leaf point sets identical (GPU leaves index sorted points, mapped through order)
+    nl, ids = ot.leaves()
+    ref = sorted(tuple(sorted(np.flatnonzero(ids == k))) for k in range(nl))
+    leaf = ex["skip"] == np.arange(info["nodes"]) + 1
+    got = sorted(tuple(sorted(ex["order"][f:l + 1])) for f, l in zip(ex["first"][leaf], ex["last"][leaf]))
+    assert got == ref
+    # root: total mass and centre of mass
+    M, com = ot.root()
+    assert np.isclose(ex["com_mass"][0, 3], M, rtol=1e-6)
+    assert np.allclose(ex["com_mass"][0, :3], com, rtol=1e-5, atol=1e-6)
+    # preorder invariants: skip pointers nest, ranges nest
+    sk = ex["skip"]
+    assert sk[0] == info["nodes"]
+    assert np.all(sk > np.arange(info["nodes"]))
+
+
+# ------------------------------------------------------------ BH forces
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.5, 0.8])
+def test_bh_forces_match_oracle_tree(theta):
+    X, m = _tree_case(7, 20000)
+    rng = np.random.default_rng(8)
+    Y = (X[rng.choice(len(X), 3000, replace=False)] + rng.normal(size=(3000, 3)) * 0.01)
+    Y = Y.astype(np.float32).astype(np.float64)
+    ot = oracle.BHTree(X, m)
+    ref, cref = ot.forces(Y, None, 66.7, 0.2, theta, count=True)
+    F, cnt = fga.forces(dev(Y), dev(X), dev(m), None, theta)
+    e = rel_err(F.cpu().numpy().astype(np.float64), ref)
+    assert np.median(e) <= 1e-2
+    assert np.median(e) <= 1e-5, np.median(e)  # same tree, same decisions
+    assert abs(cnt - cref) <= 1e-3 * cref, (cnt, cref)
+    if theta == 0.0:
+        assert cnt == len(X) * len(Y)
+
+
+def test_bh_duplicates_count_twice():
+    X = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 1, 1]])
+    m = np.array([0.25, 0.25, 0.5])
+    Y = np.array([[3.0, 0, 0], [0.5, 0.5, 0.5]])
+    ref = oracle.direct_forces(Y, X, m)
+    F, _ = fga.forces(dev(Y), dev(X), dev(m), None, 1e-6)
+    assert np.allclose(F.cpu().numpy(), ref, rtol=1e-5)
+
+
+# ------------------------------------------------------------ registration
+def oracle_run(X, Y, theta=0.0, iters=200, **kw):
+    return oracle.register(X, Y, oracle.Params(theta=theta, max_iter=iters, **kw))
+
+
+def fga_run(X, Y, dtype=torch.float32, **kw):
+    p = fga.default_params(tol=0.0, **kw)
+    return fga.register(dev(X, dtype), dev(Y, dtype), p)
+
+
+def check_transform(R, t, ref, X):
+    diag = np.linalg.norm(X.max(0) - X.min(0))
+    phi = phi_deg(ref["R"], R)
+    dtn = np.linalg.norm(t - ref["t"]) / diag
+    assert phi < 0.05 and dtn < 1e-4, (phi, dtn)
+    return phi, dtn
+
+
+def test_register_config0_fp64_direct():
+    X, Y, _, _ = synth.mixture_pair()
+    ref = oracle_run(X, Y, 0.0, 200)
+    R, t, rep = fga_run(X, Y, torch.float64, theta=0.0, max_iter=200, precision=fga.PREC_FP64)
+    assert rep.iters == 200
+    phi, dtn = check_transform(R, t, ref, X)
+    # arccos cannot resolve angles below ~1e-6 deg; compare the matrices directly
+    assert np.abs(R - ref["R"]).max() < 1e-11 and dtn < 1e-10, (np.abs(R - ref["R"]).max(), dtn)
+
+
+@pytest.mark.parametrize("prec", [fga.PREC_FP32_KAHAN, fga.PREC_FP32, fga.PREC_FP32_ALL])
+def test_register_config0_fp32_direct(prec):
+    X, Y, _, _ = synth.mixture_pair()
+    ref = oracle_run(X, Y, 0.0, 200)
+    R, t, rep = fga_run(X, Y, theta=0.0, max_iter=200, precision=prec)
+    check_transform(R, t, ref, X)
+
+
+def test_register_config0_bh():
+    X, Y, _, _ = synth.mixture_pair()
+    ref = oracle_run(X, Y, 0.5, 200)
+    R, t, rep = fga_run(X, Y, theta=0.5, max_iter=200)
+    check_transform(R, t, ref, X)
+    assert rep.interactions > 0
+
+
+@pytest.mark.parametrize("kw", [dict(damping=fga.DAMP_LITERAL), dict(velocity=fga.VEL_PARTICLE),
+                                dict(mass_mode=fga.MASS_UNIFORM)])
+def test_register_modes(kw):
+    X, Y, _, _ = synth.mixture_pair(9, per_comp=64, m=400)
+    okw = {}
+    if kw.get("damping") == fga.DAMP_LITERAL:
+        okw["damping"] = "literal"
+    if kw.get("velocity") == fga.VEL_PARTICLE:
+        okw["velocity"] = "particle"
+    if kw.get("mass_mode") == fga.MASS_UNIFORM:
+        okw["masses"] = "uniform"
+    ref = oracle_run(X, Y, 0.0, 60, **okw)
+    R, t, rep = fga_run(X, Y, torch.float64, theta=0.0, max_iter=60, precision=fga.PREC_FP64, **kw)
+    phi, dtn = check_transform(R, t, ref, X)
+    assert np.abs(R - ref["R"]).max() < 1e-10 and dtn < 1e-9, (np.abs(R - ref["R"]).max(), dtn)
+
+
+def test_exact_recovery_full_overlap():
+    X, Y, R_gt, t_gt = synth.uniform_grid_pair(24, n_side=7)
+    R, t, rep = fga_run(X, Y, torch.float64, theta=0.0, max_iter=400, precision=fga.PREC_FP64,
+                        mass_mode=fga.MASS_UNIFORM)
+    assert phi_deg(R_gt, R) < 1e-3 and np.linalg.norm(t - t_gt) < 1e-4
+
+
+def test_convergence_stops_early():
+    X, Y, _, _ = synth.uniform_grid_pair(25, n_side=6)
+    p = fga.default_params(theta=0.0, max_iter=1000, tol=1e-10, check_every=4)
+    R, t, rep = fga.register(dev(X), dev(Y), p)
+    assert rep.converged and rep.iters < 1000 and rep.last_dT2 < 1e-10
+
+
+# ------------------------------------------------- state, resume, determinism
+def test_step_resume_is_bit_identical():
+    X, Y, _, _ = synth.mixture_pair(12, per_comp=64, m=300)
+    p = fga.default_params(theta=0.5, tol=0.0)
+    a = fga.State(dev(X), dev(Y), p)
+    a.step(30)
+    blob = a.save()
+    a.step(20)
+    Ra, ta, _ = a.get()
+    b = fga.State(dev(X), dev(Y), p)
+    b.load(blob)
+    b.step(20)
+    Rb, tb, rb = b.get()
+    assert rb.iters == 50
+    assert np.array_equal(Ra, Rb) and np.array_equal(ta, tb)
+
+
+def test_deterministic_repeat():
+    X, Y, _, _ = synth.mixture_pair(13, per_comp=512, m=3000)
+    out = [fga_run(X, Y, theta=0.5, max_iter=40)[:2] for _ in range(2)]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_stepwise_trajectory_matches_oracle():
+    X, Y, _, _ = synth.mixture_pair(14, per_comp=64, m=400)
+    Xn, Yn, info = oracle.normalise(X, Y)
+    mX, mY = oracle.masses(Xn, Yn, oracle.Params())
+    st = oracle.Stepper(Xn, Yn, mX, mY, oracle.Params())
+    g = fga.State(dev(X, torch.float64), dev(Y, torch.float64),
+                  fga.default_params(theta=0.0, tol=0.0, precision=fga.PREC_FP64))
+    for k in range(5):
+        st.step()
+        g.step(1)
+        Rn, tn = g.get_normalised()
+        assert np.allclose(Rn, st.R, atol=1e-12) and np.allclose(tn, st.t, atol=1e-11), k
+
+
+# ------------------------------------------------------------ batch
+def test_batch_matches_plain():
+    pairs = [synth.mixture_pair(100 + k, per_comp=64 + 16 * k, m=300 + 40 * k) for k in range(6)]
+    Xs = [dev(p[0]) for p in pairs]
+    Ys = [dev(p[1]) for p in pairs]
+    prm = fga.default_params(theta=0.5, max_iter=100, tol=1e-4)
+    R, t, reps = fga.register_batch(Xs, Ys, prm)
+    for k, (X, Y, _, _) in enumerate(pairs):
+        R1, t1, rep1 = fga.register(dev(X), dev(Y), prm)
+        assert reps[k].iters == rep1.iters
+        assert phi_deg(R1, R[k]) < 0.05
+        assert np.linalg.norm(t1 - t[k]) / np.linalg.norm(X.max(0) - X.min(0)) < 1e-4
+
+
+def test_batch_matches_oracle_fixed_iterations():
+    pairs = [synth.batch_pair(k) for k in range(3)]
+    prm = fga.default_params(theta=0.5, max_iter=30, tol=0.0)
+    R, t, reps = fga.register_batch([dev(p[0]) for p in pairs], [dev(p[1]) for p in pairs], prm)
+    for k, (X, Y, _, _) in enumerate(pairs):
+        ref = oracle_run(X, Y, 0.5, 30)
+        assert reps[k].iters == 30
+        check_transform(R[k], t[k], ref, X)
+
+
+# ------------------------------------------------------------ edge cases
+def test_edge_single_points():
+    # one reference point pulling a proper template: well defined
+    rng = np.random.default_rng(30)
+    X = np.array([[0.3, 0.1, 0.2]])
+    Y = rng.normal(size=(10, 3))
+    for theta in (0.0, 0.5):
+        R, t, rep = fga_run(X, Y, theta=theta, max_iter=5)
+        ref = oracle_run(X, Y, theta, 5)
+        check_transform(R, t, ref, np.vstack([X, Y]))
+    # a one-point template has no rotation (rank-0 Kabsch matrix)
+    with pytest.raises(fga.FGAError) as e:
+        fga_run(Y, X, theta=0.0, max_iter=5)
+    assert e.value.name == "DEGENERATE"
+
+
+def test_edge_nonfinite_and_degenerate_inputs():
+    X, Y, _, _ = synth.mixture_pair(15, per_comp=16, m=50)
+    Xb = X.copy()
+    Xb[3, 1] = np.nan
+    with pytest.raises(fga.FGAError) as e:
+        fga_run(Xb, Y, theta=0.0, max_iter=5)
+    assert e.value.name == "NONFINITE"
+    Z = np.ones((20, 3))
+    with pytest.raises(fga.FGAError) as e:
+        fga_run(Z, Z, theta=0.0, max_iter=5)
+    assert e.value.name == "DEGENERATE"
+    with pytest.raises(fga.FGAError) as e:
+        fga.forces(torch.zeros(3, 3, device="cuda"), torch.zeros(3, 3, device="cuda"),
+                   torch.ones(3, device="cuda"), None, 0.0, fga.default_params(eps=0.0))
+    assert e.value.name == "INVALID_ARG"
+
+
+def test_edge_collinear_template_reports_degenerate():
+    X, _, _, _ = synth.mixture_pair(16, per_comp=16, m=10)
+    Y = np.outer(np.linspace(0, 1, 30), [1.0, 2.0, 3.0])
+    with pytest.raises(fga.FGAError) as e:
+        fga_run(X, Y, theta=0.0, max_iter=3)
+    assert e.value.name == "DEGENERATE"
+
+
+def test_host_pointer_rejected():
+    import ctypes
+    L = fga.lib()
+    host = (ctypes.c_float * 30)()
+    p = fga.default_params()
+    F = torch.empty(10, 3, device="cuda")
+    st = L.fga_forces(ctypes.cast(host, ctypes.c_void_p), 10, ctypes.cast(host, ctypes.c_void_p), 10,
+                      ctypes.cast(host, ctypes.c_void_p), None, 0, 0.0, ctypes.byref(p),
+                      ctypes.c_void_p(F.data_ptr()), None, None)
+    assert st == 1
