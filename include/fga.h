@@ -83,13 +83,18 @@ typedef struct {
   int rho;                /* NIV lattice cells per axis, 16 */
   int max_depth;          /* octree depth limit, 20 (Sec. BH tree, step iii) */
   int max_iter;           /* iteration cap */
-  double tol;             /* stop when ||T_k - T_{k-1}||_F^2 < tol; tol <= 0 runs max_iter */
+  double tol;             /* stop when ||T_k - T_{k-1}||_F^2 < tol on a shrinking step
+                             (Alg. 2, threshold 1e-4 on the norm: tol = 1e-8);
+                             tol <= 0 runs exactly max_iter iterations */
   int damping;            /* fga_damping */
   int velocity;           /* fga_velocity */
   int mass_mode;          /* fga_mass_mode */
   int precision;          /* fga_precision */
-  int leaf_size;          /* points per BH leaf: 1 = Alg. 1 exactly; 0 = autotuned */
-  int tile;               /* reference points per Kahan tile; 0 = autotuned */
+  int leaf_size;          /* BH leaf size L: cells with at most L points are not split.
+                             0 or 1 = Alg. 1 exactly (singleton leaves); 2..64 trade
+                             accuracy within the BH error for fewer node visits */
+  int tile;               /* reference ranges per template tile of 256 particles (work split of
+                             one iteration); 0 = autotuned per shape class and cached */
   int check_every;        /* host checks the convergence flag every k iterations (0 = 16) */
   int reserved[5];
 } fga_params;
@@ -107,7 +112,7 @@ typedef struct fga_tree fga_tree;
 
 /* Fills *p with the paper's parameter settings (G = 66.7, eps = 0.2,
  * eta = 0.2, dt = 0.1, theta = 0.6, [a,b] = [-5,5], rho = 16, depth 20), 200
- * iterations, tol = 1e-4, fraction damping, rigid velocity, NIV masses,
+ * iterations, tol = 1e-8, fraction damping, rigid velocity, NIV masses,
  * FP32 with Kahan tiles, leaf size 1. */
 fga_status fga_default_params(fga_params* p);
 

@@ -25,8 +25,10 @@ the design notes):
   * Velocity "rigid" (default): after each Kabsch step the velocity state is
     the realised rigid displacement divided by dt. "particle": the
     unconstrained per-particle velocity v' is kept.
-  * Stop rule: iterate while ||T_k - T_{k-1}||_F^2 >= tol (tol <= 0 runs
-    exactly max_iter steps).
+  * Stop rule: iterate until ||T_k - T_{k-1}||_F^2 < tol on a step smaller
+    than the one before (the motion starts from rest, so the first steps are
+    small too); tol <= 0 runs exactly max_iter steps. The paper's threshold
+    1e-4 is read as a bound on the norm, i.e. tol = 1e-8 on its square.
   * dnorm(t): the centroid term that has to be added is (mean X - mean Y).
 """
 from __future__ import annotations
@@ -339,13 +341,18 @@ def register(X, Y, p: Params = None, trace=False):
     st = Stepper(Xn, Yn, mX, mY, p)
     hist = []
     converged = False
+    prev = np.inf
     while st.iters < p.max_iter:
         dT2 = st.step()
         if trace:
             hist.append((st.R.copy(), st.t.copy(), dT2))
-        if p.tol > 0 and dT2 < p.tol:
+        # stop rule of Alg. 2 (reading): the step has fallen below tol while
+        # shrinking; the test is skipped while the motion is still speeding up
+        # from rest, where the first steps are also small
+        if p.tol > 0 and dT2 < p.tol and dT2 < prev:
             converged = True
             break
+        prev = dT2
     t = denormalise_t(st.R, st.t, info)
     return dict(R=st.R, t=t, R_n=st.R, t_n=st.t, iters=st.iters, converged=converged,
                 info=info, mX=mX, mY=mY, Xn=Xn, Yn=Yn, history=hist,

@@ -10,6 +10,9 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -97,9 +100,9 @@ fga_status check_params(const fga_params* p) {
     set_error("unknown precision %d", p->precision);
     return FGA_E_INVALID_ARG;
   }
-  if (p->leaf_size < 0 || p->leaf_size > 1) {
-    set_error("leaf_size %d: this build builds the paper's singleton leaves (0 or 1)", p->leaf_size);
-    return FGA_E_UNSUPPORTED;
+  if (p->leaf_size < 0 || p->leaf_size > 64) {
+    set_error("leaf_size must be in [0, 64] (got %d)", p->leaf_size);
+    return FGA_E_INVALID_ARG;
   }
   if (p->tile < 0 || p->check_every < 0) {
     set_error("tile and check_every must be >= 0");
@@ -180,6 +183,50 @@ int bh_ranges(int64_t m, int64_t n) {
   return jr < 1 ? 1 : (int)jr;
 }
 
+// ---------------------------------------------------------------- autotuner
+// The number of reference ranges per template tile trades parallelism (more
+// waves to hide scalar-load latency) against repeated work at the top of the
+// tree (BH) or extra partial moments (direct). It is chosen by timing a few
+// iterations of the real kernel on a copy of the state, once per shape class;
+// results are kept for the process and, if FGA_TUNE_CACHE names a file, on disk.
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(bool bh, bool f64, int64_t m, int64_t n, int prec) {
+  auto lg = [](int64_t v) {
+    int k = 0;
+    while ((int64_t(1) << (k + 1)) <= v) ++k;
+    return k;
+  };
+  char buf[96];
+  snprintf(buf, sizeof buf, "%s_%s_p%d_m%d_n%d", bh ? "bh" : "direct", f64 ? "f64" : "f32", prec,
+           lg(m), lg(n));
+  return buf;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("FGA_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char key[128];
+  int v;
+  while (fscanf(f, " \"%127[^\"]\" : %d ,", key, &v) == 2) g_tune[key] = v;
+  fclose(f);
+}
+
+void tune_save_locked() {
+  const char* path = getenv("FGA_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_tune) fprintf(f, "\"%s\": %d,\n", kv.first.c_str(), kv.second);
+  fclose(f);
+}
+
 void denormalise(const NormInfo& ni, const double* R, const double* tn, double* t) {
   // X = s (Xn - a) + mean(X) + l, Y = s (Yn - a) + mean(Y) + l with
   // s = (r - l)/(b - a) (inverse of Eq. A.3); Xn = R Yn + tn then gives
@@ -249,6 +296,52 @@ static void state_free(fga_state* s) {
   delete s;
 }
 
+// Times each candidate number of reference ranges on the state's own kernel,
+// restoring the FP64 state after every trial.
+static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands, int* best) {
+  RigidState saved;
+  FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  hipEvent_t e0, e1;
+  FGA_HIP(hipEventCreate(&e0));
+  FGA_HIP(hipEventCreate(&e1));
+  const int tiles = (int)((S->m + kBlock - 1) / kBlock);
+  float best_ms = 1e30f;
+  fga_status st = FGA_OK;
+  for (int c : cands) {
+    PairDev pd = S->pd;
+    pd.jr = c;
+    pd.n_items = tiles * c;
+    auto launch = [&]() {
+      return S->f64 ? launch_iteration<double>(pd, S->c, S->s) : launch_iteration<float>(pd, S->c, S->s);
+    };
+    st = launch();
+    if (st != FGA_OK) break;
+    if (hipEventRecord(e0, S->s) != hipSuccess) { st = FGA_E_DEVICE; break; }
+    for (int r = 0; r < 2 && st == FGA_OK; ++r) st = launch();
+    if (st != FGA_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, S->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = FGA_E_DEVICE;
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = c;
+    }
+    if (hipMemcpyAsync(S->st, &saved, sizeof saved, hipMemcpyHostToDevice, S->s) != hipSuccess ||
+        hipStreamSynchronize(S->s) != hipSuccess) {
+      st = FGA_E_DEVICE;
+      break;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FGA_OK) set_error("autotuning the reference ranges failed");
+  return st;
+}
+
 extern "C" {
 
 fga_status fga_default_params(fga_params* p) {
@@ -267,7 +360,7 @@ fga_status fga_default_params(fga_params* p) {
   p->rho = 16;
   p->max_depth = 20;
   p->max_iter = 200;
-  p->tol = 1e-4;
+  p->tol = 1e-8;
   p->damping = FGA_DAMP_FRACTION;
   p->velocity = FGA_VEL_RIGID;
   p->mass_mode = FGA_MASS_NIV;
@@ -366,7 +459,7 @@ fga_status fga_tree_export(const fga_tree* t, float* com_mass, int32_t* ints, in
   std::vector<BHNode> h(t->n_nodes);
   FGA_HIP(hipMemcpy(h.data(), t->nodes, sizeof(BHNode) * t->n_nodes, hipMemcpyDeviceToHost));
   // node depth from the stored squared diagonal relative to the root's
-  const double l2root = h.empty() ? 0.0 : (double)h[0].l2;
+  const double l2root = h.empty() ? 0.0 : std::fabs((double)h[0].l2);
   for (int k = 0; k < t->n_nodes; ++k) {
     if (com_mass) {
       com_mass[4 * k] = h[k].cm.x;
@@ -379,8 +472,8 @@ fga_status fga_tree_export(const fga_tree* t, float* com_mass, int32_t* ints, in
       ints[4 * k + 1] = h[k].first;
       ints[4 * k + 2] = h[k].last;
       int d = 0;
-      if (l2root > 0.0 && h[k].l2 > 0.0)
-        d = (int)std::lround(0.5 * std::log2(l2root / (double)h[k].l2));
+      const double l2k = std::fabs((double)h[k].l2);
+      if (l2root > 0.0 && l2k > 0.0) d = (int)std::lround(0.5 * std::log2(l2root / l2k));
       ints[4 * k + 3] = d;
     }
   }
@@ -506,11 +599,25 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
     if (st != FGA_OK) return fail(st);
     S->n_nodes = off[1] - off[0];
   }
-  int jr = p->theta > 0 ? bh_ranges(m, n) : direct_ranges(m, n);
-  if (p->velocity == FGA_VEL_PARTICLE) jr = 1;
+  const bool bh = p->theta > 0;
+  int jr = bh ? bh_ranges(m, n) : direct_ranges(m, n);
+  std::vector<int> cands;
+  if (p->velocity == FGA_VEL_PARTICLE) {
+    jr = 1;
+  } else if (p->tile > 0) {
+    jr = p->tile;
+  } else {
+    for (int c = 1; c <= (bh ? 16 : 64); c *= 2) {
+      const int64_t per = n / c;
+      if (c == 1 || (per >= (bh ? 256 : 1024) && ((m + kBlock - 1) / kBlock) * c <= 65536))
+        cands.push_back(c);
+    }
+  }
+  int max_jr = jr;
+  for (int c : cands) max_jr = std::max(max_jr, c);
   const int tiles = (int)((m + kBlock - 1) / kBlock);
   const int items = tiles * jr;
-  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * items) != hipSuccess ||
+  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * (size_t)tiles * max_jr) != hipSuccess ||
       hipMalloc((void**)&S->done, sizeof(unsigned)) != hipSuccess) {
     set_error("hipMalloc of the iteration buffers failed");
     return fail(FGA_E_NOMEM);
@@ -545,6 +652,28 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
       hipStreamSynchronize(s) != hipSuccess) {
     set_error("state initialisation failed");
     return fail(FGA_E_DEVICE);
+  }
+  if (!cands.empty() && cands.size() > 1) {
+    const std::string key = tune_key(bh, S->f64, m, n, p->precision);
+    int found = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_load_locked();
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) found = it->second;
+    }
+    if (found > 0 && std::find(cands.begin(), cands.end(), found) != cands.end()) {
+      pd.jr = found;
+    } else {
+      int best = jr;
+      fga_status tst = tune_ranges(S, cands, &best);
+      if (tst != FGA_OK) return fail(tst);
+      pd.jr = best;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[key] = best;
+      tune_save_locked();
+    }
+    pd.n_items = tiles * pd.jr;
   }
   *out = S;
   return FGA_OK;

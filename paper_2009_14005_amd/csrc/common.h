@@ -89,7 +89,9 @@ struct alignas(16) BHNode {
   int skip;
   int first;
   int last;
-  float l2;    // squared box diagonal of the cell (Alg. 1: l = ||X_max - X_min||)
+  float l2;    // squared box diagonal of the cell (Alg. 1: l = ||X_max - X_min||);
+               // the sign bit marks a twig (an internal node whose children are
+               // all singleton leaves)
 };
 
 // Geometry of one registration pair on the device, for the iteration kernels.

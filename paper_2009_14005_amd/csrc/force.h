@@ -86,6 +86,17 @@ __device__ inline double rsqrt3_mass<double>(double m, double r2) {
   return m / (r2 * sqrt(r2));
 }
 
+// One exact term of Eq. (GAForce) (per unit G and template mass).
+template <typename T>
+__device__ inline void accum_point(const vec4_t<T>& x, T yx, T yy, T yz, T eps2, T& ax, T& ay,
+                                   T& az) {
+  const T ex = x.x - yx, ey = x.y - yy, ez = x.z - yz;
+  const T s = rsqrt3_mass<T>(x.w, ex * ex + ey * ey + ez * ez + eps2);
+  ax += ex * s;
+  ay += ey * s;
+  az += ez * s;
+}
+
 // ------------------------------------------------------------- Barnes-Hut
 // Wavefront-cooperative traversal with per-lane decisions. Nodes are in
 // depth-first preorder, so every lane's walk is a sequence of increasing node
@@ -111,53 +122,72 @@ __device__ inline void bh_accum(const BHNode* __restrict__ nodes,
                                 T& ax, T& ay, T& az, unsigned& count) {
   unsigned next = active ? (unsigned)root : 0xFFFFFFFFu;
   const unsigned uend = (unsigned)end;
+  unsigned n = wave_min_u32(next);
+  if (n >= uend) return;
+  BHNode nd = nodes[n];
   // a correct walk visits every node at most once; the cap only bounds the loop
   for (unsigned visits = 0; visits <= uend; ++visits) {
-    const unsigned n = wave_min_u32(next);
-    if (n >= uend) break;
-    const BHNode nd = nodes[n];
+    // the next node in preorder is the most likely successor: fetch it early
+    const unsigned nn = n + 1 < uend ? n + 1 : n;
+    const BHNode ahead = nodes[nn];
     const bool here = next == n;
     const unsigned after = (unsigned)nd.skip > n ? (unsigned)nd.skip : n + 1;
-    if (nd.first >= j1 || nd.last < j0) {  // no point of the range below this node
-      if (here) next = after;
-      continue;
-    }
-    const bool leaf = (unsigned)nd.skip == n + 1;
-    const bool single = leaf && nd.first == nd.last;
-    bool open_leaf = false;
-    if (here) {
+    if (nd.first < j1 && nd.last >= j0) {  // some point of the range lies below this node
+      const bool leaf = (unsigned)nd.skip == n + 1;
+      // A twig is an internal node whose children are all singleton leaves
+      // (its subtree holds one node per point). Opening it evaluates every
+      // child exactly, whatever the children's own MAC outcome, so it is
+      // walked like a leaf: the same terms without visiting the children.
+      const bool twig = __float_as_uint(nd.l2) >> 31;
+      const float l2 = fabsf(nd.l2);
       const T dx = (T)nd.cm.x - yx, dy = (T)nd.cm.y - yy, dz = (T)nd.cm.z - yz;
       const T r2 = dx * dx + dy * dy + dz * dz;
-      const bool direct_single = single && sizeof(T) == 4;
-      if (direct_single || nd.l2 < theta2 * (float)r2) {
-        if (nd.first >= j0) {  // this range owns the node
-          const T s = rsqrt3_mass<T>((T)nd.cm.w, r2 + eps2);
-          ax += dx * s;
-          ay += dy * s;
-          az += dz * s;
-          ++count;
-        }
-        next = after;
-      } else if (leaf) {
-        open_leaf = true;
-        next = after;
-      } else {
-        next = n + 1;
+      // singleton leaves are taken directly in FP32 lanes (the node is the point)
+      const bool take_node =
+          (sizeof(T) == 4 && leaf && nd.first == nd.last) || l2 < theta2 * (float)r2;
+      if (here && take_node && nd.first >= j0) {  // this range owns the node
+        const T s = rsqrt3_mass<T>((T)nd.cm.w, r2 + eps2);
+        ax += dx * s;
+        ay += dy * s;
+        az += dz * s;
+        ++count;
       }
+      const bool exact = leaf || twig;
+      const bool open_pts = here && !take_node && exact;
+      if (here) next = (take_node || exact) ? after : n + 1;
+      if (exact && __ballot(open_pts) != 0ull) {
+        const int p0 = max(nd.first, j0), p1 = min(nd.last, j1 - 1);
+        int p = p0;
+        for (; p + 3 <= p1; p += 4) {  // four points per round: loads issued together
+          const vec4_t<T> x0 = X[p], x1 = X[p + 1], x2 = X[p + 2], x3 = X[p + 3];
+          if (open_pts) {
+            accum_point<T>(x0, yx, yy, yz, eps2, ax, ay, az);
+            accum_point<T>(x1, yx, yy, yz, eps2, ax, ay, az);
+            accum_point<T>(x2, yx, yy, yz, eps2, ax, ay, az);
+            accum_point<T>(x3, yx, yy, yz, eps2, ax, ay, az);
+            count += 4;
+          }
+        }
+        for (; p <= p1; ++p) {
+          const vec4_t<T> x = X[p];
+          if (open_pts) {
+            accum_point<T>(x, yx, yy, yz, eps2, ax, ay, az);
+            ++count;
+          }
+        }
+      }
+    } else if (here) {
+      next = after;
     }
-    if (leaf && __ballot(open_leaf) != 0ull) {
-      const int p0 = max(nd.first, j0), p1 = min(nd.last, j1 - 1);
-      for (int p = p0; p <= p1; ++p) {
-        const vec4_t<T> x = X[p];
-        if (open_leaf) {
-          const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
-          const T s = rsqrt3_mass<T>(x.w, dx * dx + dy * dy + dz * dz + eps2);
-          ax += dx * s;
-          ay += dy * s;
-          az += dz * s;
-          ++count;
-        }
-      }
+    // successor: n + 1 whenever some lane opened n, else the smallest wanted index
+    if (__ballot(next == n + 1) != 0ull) {
+      n = n + 1;
+      if (n >= uend) break;
+      nd = ahead;
+    } else {
+      n = wave_min_u32(next);
+      if (n >= uend) break;
+      nd = nodes[n];
     }
   }
 }

@@ -180,7 +180,7 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
 }
 
 template <typename T, bool BH, int PREC>
-__global__ __launch_bounds__(kBlock) void k_iteration(PairDev pd, IterConsts c) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_iteration(PairDev pd, IterConsts c) {
   __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
   iteration_item<T, BH, PREC>(pd, c, (int)blockIdx.x, lds);
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_iteration(PairDev pd, IterConsts c) 
 // queue ordered by decreasing cost until it is empty. The block that drains
 // the last entry resets the queue for the next launch.
 template <typename T, bool BH, int PREC>
-__global__ __launch_bounds__(kBlock) void k_batch_iteration(const PairDev* pairs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_iteration(const PairDev* pairs,
                                                             const int2* items, int n_items,
                                                             unsigned* queue, IterConsts c) {
   __shared__ double lds[(kMom + 1) * (kBlock / kWave)];

@@ -157,9 +157,11 @@ FGA_HD void rigid_update(RigidState& s, const double* mom, double dt) {
     s.t[a] = tn[a];
     s.mu[a] = muD[a];
   }
+  // stop rule of Alg. 2: the step fell below tol while shrinking (the motion
+  // starts from rest, so the first, accelerating steps are small as well)
+  if (s.tol > 0.0 && dT2 < s.tol && s.iter > 0 && dT2 < s.dT2) s.converged = 1;
   s.dT2 = dT2;
   s.iter += 1;
-  if (s.tol > 0.0 && dT2 < s.tol) s.converged = 1;
   if (s.iter >= s.max_iter) s.converged = s.converged ? 1 : 2;  // 2 = stopped at the cap
   for (int k = 0; k < 9; ++k) {
     s.fR[k] = (float)s.R[k];

@@ -442,15 +442,70 @@ fga_status exclusive_scan(Load ld, int64_t n, V* out, V* bsum_scratch, hipStream
   return FGA_OK;
 }
 
+// ------------------------------------------------------------ leaf size L > 1
+// With leaf size L a cell is split only while it holds more than L points, so
+// the tree keeps exactly the cells whose parent cell holds more than L points;
+// a kept cell with at most L points is a leaf at one level below its parent.
+// The parent of the cell holding sorted points [a, b] branches at the larger
+// of the two boundary LCPs (the neighbours outside the range), and its points
+// are the run around [a, b] sharing that many digits.
+__device__ inline void prune_mark(const u64* codes, const SegRange& s, int64_t a, int64_t b,
+                                  int L, double lroot, BHNode* nd, unsigned* keep) {
+  const int dl = a > s.s0 ? lcp_digits(codes[a - 1], codes[a]) : -1;
+  const int dr = b + 1 < s.s1 ? lcp_digits(codes[b], codes[b + 1]) : -1;
+  const int dp = dl > dr ? dl : dr;
+  const int64_t count = b - a + 1;
+  if (dp < 0) {  // the root
+    *keep = 1u;
+    return;
+  }
+  const int64_t ap = search_left(codes, s.s0, a, dp);
+  const int64_t bp = search_right(codes, b, s.s1 - 1, dp);
+  const bool kept = bp - ap + 1 > L;
+  *keep = kept ? 1u : 0u;
+  if (kept && count <= L && count > 1) {  // becomes (or stays) a leaf one level below its parent
+    const double l = ldexp(lroot, -(dp + 1));
+    nd->l2 = (float)(l * l);
+  }
+}
+
+// Copies the kept nodes to their compacted preorder positions; skip pointers
+// and segment offsets map through the exclusive scan NI of the keep flags.
+__global__ __launch_bounds__(kBlock) void k_compact(const BHNode* in, const unsigned* keep,
+                                                    const unsigned* NI, const int* node_off,
+                                                    int nseg, unsigned total, BHNode* out,
+                                                    unsigned* stats) {
+  const unsigned i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total || !keep[i]) return;
+  int lo = 0, hi = nseg - 1;  // segment of node i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((unsigned)node_off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  const unsigned base = (unsigned)node_off[lo];
+  BHNode nd = in[i];
+  const unsigned skip_g = base + (unsigned)nd.skip;
+  const unsigned ni = NI[i];
+  nd.skip = (int)(NI[skip_g] - NI[base]);
+  if ((unsigned)nd.skip == ni - NI[base] + 1) {
+    atomicAdd(&stats[1], 1u);
+    nd.l2 = fabsf(nd.l2);  // a leaf is walked point by point anyway: no twig flag
+  } else {
+    atomicAdd(&stats[2], 1u);
+  }
+  out[ni] = nd;
+}
+
 // ------------------------------------------------------------ node emission
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const SegRange* sr,
+__global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const u64* codes, const SegRange* sr,
                                                  const SegBox* box, int nseg, int64_t n,
                                                  const unsigned* mask,
                                                  const unsigned char* leaf0, const int* own_d,
                                                  const int* own_a, const int* own_b,
                                                  const unsigned* P, const D4* W, BHNode* nodes,
-                                                 unsigned* stats) {
+                                                 unsigned* stats, int L, unsigned* keep) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
   const int sg = find_seg(sr, nseg, k);
@@ -471,6 +526,14 @@ __global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const SegR
     nd.last = b - s0;
     const double l = ldexp(lroot, -d);
     nd.l2 = (float)(l * l);
+    // twig: every point of the cell is its own child (all separators inside
+    // branch at depth d); flagged by the sign bit of l2. At most 8 points.
+    if (b - a < 8) {
+      bool twig = true;
+      for (int q = a; q < b && twig; ++q) twig = lcp_digits(codes[q], codes[q + 1]) == d;
+      if (twig) nd.l2 = -nd.l2;
+    }
+    if (L > 1) prune_mark(codes, sr[sg], a, b, L, lroot, &nd, keep + idx);
     nodes[idx] = nd;
     atomicMax(&stats[0], (unsigned)d);
     atomicAdd(&stats[2], 1u);
@@ -493,6 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const SegR
     nd.last = (int)e - s0;
     const double l = ldexp(lroot, -kQBits);  // a leaf of several points is a depth-20 cell
     nd.l2 = (float)(l * l);
+    if (L > 1) prune_mark(codes, sr[sg], k, e, L, lroot, &nd, keep + idx);
     nodes[idx] = nd;
     atomicAdd(&stats[1], 1u);
   }
@@ -502,6 +566,11 @@ __global__ void k_seg_nodes(const SegRange* sr, int nseg, const unsigned* P, int
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < nseg) node_off[s] = (int)P[sr[s].s0];
   if (s == nseg - 1) node_off[nseg] = (int)P[sr[s].s1];
+}
+
+__global__ void k_remap_off(const unsigned* NI, int nseg, int* node_off) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= nseg) node_off[s] = (int)NI[node_off[s]];
 }
 
 // ------------------------------------------------------------ host driver
@@ -597,7 +666,6 @@ template <typename T>
 fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t ntot,
                        int leaf_size, BHNode** nodes_out, int* node_off_host, int** order_out,
                        int* stats_host, hipStream_t s) {
-  (void)leaf_size;
   Scratch sc;
   vec4_t<T>* X = (vec4_t<T>*)Xpacked;
   vec4_t<T>* Xs;
@@ -663,9 +731,39 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
     }
     nodes = (BHNode*)p;
   }
-  k_emit<T><<<nb, kBlock, 0, s>>>(X, sr, box, nseg, ntot, mask, leaf0, own_d, own_a, own_b, P, W,
-                                  nodes, stats);
+  const int L = leaf_size > 1 ? leaf_size : 1;
+  unsigned* keep = nullptr;
+  if (L > 1) {
+    FGA_TRY(sc.get(&keep, sizeof(unsigned) * (total + 1)));
+    FGA_HIP(hipMemsetAsync(keep, 0, sizeof(unsigned) * (total + 1), s));
+  }
+  k_emit<T><<<nb, kBlock, 0, s>>>(X, codes, sr, box, nseg, ntot, mask, leaf0, own_d, own_a, own_b, P, W,
+                                  nodes, stats, L, keep);
   k_seg_nodes<<<(nseg + 63) / 64, 64, 0, s>>>(sr, nseg, P, node_off);
+  if (L > 1) {  // drop the cells below the leaf size and compact the preorder
+    unsigned *NI, *bsumK;
+    const int nbK = (int)(((int64_t)total + kScanTile) / kScanTile);
+    FGA_TRY(sc.get(&NI, sizeof(unsigned) * (total + 1)));
+    FGA_TRY(sc.get(&bsumK, sizeof(unsigned) * nbK));
+    FGA_TRY((exclusive_scan<unsigned, LoadCnt>(LoadCnt{keep}, (int64_t)total, NI, bsumK, s)));
+    unsigned kept = 0;
+    FGA_HIP(hipMemcpyAsync(&kept, NI + total, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipStreamSynchronize(s));
+    BHNode* packed = nullptr;
+    if (hipMalloc((void**)&packed, sizeof(BHNode) * (kept ? kept : 1)) != hipSuccess) {
+      (void)hipFree(nodes);
+      if (perm) (void)hipFree(perm);
+      set_error("hipMalloc of %u tree nodes failed", kept);
+      return FGA_E_NOMEM;
+    }
+    FGA_HIP(hipMemsetAsync(stats + 1, 0, sizeof(unsigned) * 2, s));
+    k_compact<<<(int)((total + kBlock - 1) / kBlock), kBlock, 0, s>>>(nodes, keep, NI, node_off, nseg,
+                                                                      total, packed, stats);
+    k_remap_off<<<(nseg + 64) / 64, 64, 0, s>>>(NI, nseg, node_off);
+    FGA_HIP(hipStreamSynchronize(s));
+    (void)hipFree(nodes);
+    nodes = packed;
+  }
   unsigned hstats[4];
   hipError_t e1 = hipGetLastError();
   if (e1 == hipSuccess)

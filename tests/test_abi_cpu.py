@@ -56,7 +56,7 @@ def call_forces(**over):
     (dict(p=fga.default_params(dt=0.0)), 1), (dict(p=fga.default_params(eta=1.5)), 1),
     (dict(p=fga.default_params(rho=0)), 1), (dict(p=fga.default_params(a=5.0, b=-5.0)), 1),
     (dict(p=fga.default_params(max_depth=12)), 6), (dict(p=fga.default_params(precision=9)), 1),
-    (dict(p=fga.default_params(leaf_size=8)), 6),
+    (dict(p=fga.default_params(leaf_size=65)), 1), (dict(p=fga.default_params(leaf_size=-1)), 1),
     (dict(dt=0, p=fga.default_params(precision=2)), 1),
 ])
 def test_forces_argument_validation(over, code):

@@ -1,0 +1,103 @@
+"""Parity at the benchmark workloads' full sizes, on outputs the oracle can
+compute one by one (sampled template particles against the full reference),
+and for the fused iteration kernel in the launch configuration bench.py times
+(whole registrations at equal iteration counts).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import paper_2009_14005_amd as fga  # noqa: E402
+import synth  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build(force=False)
+
+
+def f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32).astype(np.float64)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rel(F, ref):
+    return np.linalg.norm(F - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+def prepared(X, Y):
+    """Normalised clouds and NIV masses as the registration computes them,
+    rounded to FP32 so both sides read identical inputs."""
+    Xn, Yn, _ = oracle.normalise(X, Y)
+    w = oracle.niv_masses(Xn)
+    return f32(Xn), f32(Yn), f32(w / w.sum())
+
+
+def test_lidar_bh_forces_sampled():
+    X, Y, _, _ = synth.lidar_pair()
+    Xn, Yn, mX = prepared(X, Y)
+    F, cnt = fga.forces(dev(Yn), dev(Xn), dev(mX), None, 0.5)
+    F = F.cpu().numpy().astype(np.float64)
+    idx = np.random.default_rng(0).choice(len(Yn), 2000, replace=False)
+    tree = oracle.BHTree(Xn, mX)
+    ref = tree.forces(Yn[idx], None, 66.7, 0.2, 0.5)
+    e = rel(F[idx], ref)
+    assert np.median(e) <= 1e-2 and np.median(e) <= 1e-5, np.median(e)
+    assert np.percentile(e, 99) <= 1e-3
+    dref = oracle.direct_forces(Yn[idx], Xn, mX)
+    eb = rel(ref, dref)  # the method's own BH error, for scale
+    assert np.median(eb) < 1e-2
+
+
+def test_precision_study_direct_sampled():
+    X, Y, _, _ = synth.precision_pair()
+    X, Y = f32(X), f32(Y)
+    n = len(X)
+    mX = np.full(n, 1.0 / n)
+    idx = np.random.default_rng(1).choice(len(Y), 512, replace=False)
+    ref = oracle.direct_forces(Y[idx], X, mX)
+    for prec in (fga.PREC_FP32_KAHAN, fga.PREC_FP32):
+        F, cnt = fga.forces(dev(Y), dev(X), dev(mX), None, 0.0, fga.default_params(precision=prec))
+        assert cnt == n * len(Y)
+        e = rel(F.cpu().numpy().astype(np.float64)[idx], ref)
+        agg = np.linalg.norm(F.cpu().numpy()[idx] - ref) / np.linalg.norm(ref)
+        assert agg <= 1e-5 and np.median(e) <= 1e-5, (prec, agg, np.median(e), e.max())
+
+
+def test_mesh_bh_and_direct_sampled():
+    X, Y, _, _ = synth.mesh_pair()
+    Xn, Yn, mX = prepared(X, Y)
+    idx = np.random.default_rng(2).choice(len(Yn), 256, replace=False)
+    dref = oracle.direct_forces(Yn[idx], Xn, mX)
+    F, _ = fga.forces(dev(Yn), dev(Xn), dev(mX), None, 0.0)
+    e = rel(F.cpu().numpy().astype(np.float64)[idx], dref)
+    assert np.linalg.norm(F.cpu().numpy()[idx] - dref) / np.linalg.norm(dref) <= 1e-5, e.max()
+    tree = oracle.BHTree(Xn, mX)
+    for theta in (0.3, 0.5, 0.8):
+        ref = tree.forces(Yn[idx], None, 66.7, 0.2, theta)
+        Fb, _ = fga.forces(dev(Yn), dev(Xn), dev(mX), None, theta)
+        eb = rel(Fb.cpu().numpy().astype(np.float64)[idx], ref)
+        assert np.median(eb) <= 1e-5, (theta, np.median(eb))
+
+
+def test_lidar_registration_bench_config():
+    """The benchmark's registration (BH theta 0.5, FP32 Kahan, NIV masses) for
+    a few iterations against the oracle's Alg. 2 on the same pair."""
+    X, Y, _, _ = synth.lidar_pair()
+    iters = 6
+    ref = oracle.register(X, Y, oracle.Params(theta=0.5, max_iter=iters))
+    R, t, rep = fga.register(dev(X), dev(Y), fga.default_params(theta=0.5, max_iter=iters, tol=0.0))
+    diag = np.linalg.norm(X.max(0) - X.min(0))
+    phi = oracle.angular_deviation_deg(ref["R"], R)
+    assert rep.iters == iters
+    assert phi < 0.05 and np.linalg.norm(t - ref["t"]) / diag < 1e-4
+    assert np.abs(R - ref["R"]).max() < 1e-5
+    assert abs(rep.interactions - ref["interactions"]) <= 1e-3 * ref["interactions"]

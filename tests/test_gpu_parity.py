@@ -298,7 +298,7 @@ def test_batch_matches_plain():
     pairs = [synth.mixture_pair(100 + k, per_comp=64 + 16 * k, m=300 + 40 * k) for k in range(6)]
     Xs = [dev(p[0]) for p in pairs]
     Ys = [dev(p[1]) for p in pairs]
-    prm = fga.default_params(theta=0.5, max_iter=100, tol=1e-4)
+    prm = fga.default_params(theta=0.5, max_iter=200)
     R, t, reps = fga.register_batch(Xs, Ys, prm)
     for k, (X, Y, _, _) in enumerate(pairs):
         R1, t1, rep1 = fga.register(dev(X), dev(Y), prm)
@@ -368,3 +368,72 @@ def test_host_pointer_rejected():
                       ctypes.cast(host, ctypes.c_void_p), None, 0, 0.0, ctypes.byref(p),
                       ctypes.c_void_p(F.data_ptr()), None, None)
     assert st == 1
+
+
+# ------------------------------------------------------------ leaf size
+def _literal_leaf_tree_forces(X, m, Y, theta, L):
+    """Alg. 2 BHForce on the Alg. 1 tree with leaf size L (cells of at most L
+    points are not split), written out in Python from the quantised codes."""
+    q = oracle.BHTree(X, m).quant().astype(np.int64)
+    lo, hi = X.min(0), X.max(0)
+    lroot = np.linalg.norm(hi - lo)
+    digits = np.stack([((q[:, 0] >> (19 - k)) & 1) * 4 + ((q[:, 1] >> (19 - k)) & 1) * 2
+                       + ((q[:, 2] >> (19 - k)) & 1) for k in range(20)], 1)
+
+    def build(idx, depth):
+        node = dict(idx=idx, l=lroot / 2 ** depth, mass=m[idx].sum(),
+                    com=(m[idx, None] * X[idx]).sum(0) / m[idx].sum(), kids=[])
+        if len(idx) > L and depth < 20:
+            for dgt in range(8):
+                sub = idx[digits[idx, depth] == dgt]
+                if len(sub):
+                    node["kids"].append(build(sub, depth + 1))
+        return node
+
+    root = build(np.arange(len(X)), 0)
+    out = np.zeros_like(Y)
+    for i, y in enumerate(Y):
+        acc = np.zeros(3)
+        stack = [root]
+        while stack:
+            nd = stack.pop()
+            d = y - nd["com"]
+            r = np.sqrt(d @ d)
+            if r > 0 and nd["l"] / r < theta:
+                acc -= nd["mass"] * d / (d @ d + 0.04) ** 1.5
+            elif not nd["kids"]:
+                e = y - X[nd["idx"]]
+                acc -= (m[nd["idx"], None] * e / ((e * e).sum(1) + 0.04)[:, None] ** 1.5).sum(0)
+            else:
+                stack.extend(nd["kids"])
+        out[i] = 66.7 * acc
+    return out
+
+
+@pytest.mark.parametrize("L", [4, 16])
+def test_leaf_size_matches_literal_tree(L):
+    X, m = _tree_case(17, 3000)
+    rng = np.random.default_rng(18)
+    Y = (X[rng.choice(len(X), 200, replace=False)] + rng.normal(size=(200, 3)) * 0.02)
+    Y = Y.astype(np.float32).astype(np.float64)
+    ref = _literal_leaf_tree_forces(X, m, Y, 0.5, L)
+    F, _ = fga.forces(dev(Y), dev(X), dev(m), None, 0.5, fga.default_params(leaf_size=L))
+    e = rel_err(F.cpu().numpy().astype(np.float64), ref)
+    assert np.median(e) <= 1e-5, np.median(e)
+    t = fga.Tree(dev(X), dev(m), fga.default_params(leaf_size=L))
+    ex = t.export()
+    leaf = ex["skip"] == np.arange(t.info()["nodes"]) + 1
+    # every point is in exactly one leaf
+    cover = np.zeros(len(X), int)
+    for f, l in zip(ex["first"][leaf], ex["last"][leaf]):
+        cover[f:l + 1] += 1
+    assert np.all(cover == 1)
+
+
+def test_stop_rule_iteration_count_matches_oracle():
+    X, Y, _, _ = synth.mixture_pair()
+    ref = oracle.register(X, Y, oracle.Params(max_iter=300, tol=1e-8))
+    p = fga.default_params(theta=0.0, max_iter=300, tol=1e-8, precision=fga.PREC_FP64, check_every=1)
+    R, t, rep = fga.register(dev(X, torch.float64), dev(Y, torch.float64), p)
+    assert rep.converged and rep.iters == ref["iters"]
+    assert np.abs(R - ref["R"]).max() < 1e-10

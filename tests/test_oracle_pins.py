@@ -408,3 +408,15 @@ def test_planted_mistakes_are_caught(oracle_lib, monkeypatch):
     F_noeps = oracle.direct_forces(np.array([c["y"]]), np.array([c["x"]]), np.array([1.0]),
                                    np.array([1.0]), 66.7, 0.0)[0]
     assert not np.isclose(F_noeps[0], float(c["F"][0]), rtol=1e-6)
+
+
+def test_stop_rule_waits_for_shrinking_steps(oracle_lib):
+    """Alg. 2's stop rule with the motion starting from rest: the first steps
+    are below the threshold too, so the test only fires on a shrinking step."""
+    X, Y, _, _ = synth.mixture_pair()
+    res = oracle.register(X, Y, oracle.Params(max_iter=300, tol=1e-8), trace=True)
+    h = [x[2] for x in res["history"]]
+    assert res["converged"] and 20 < res["iters"] < 150
+    assert h[0] < h[5]                       # accelerating start
+    assert h[-1] < 1e-8 and h[-1] < h[-2]    # stopped on a shrinking, small step
+    assert all(not (h[k] < 1e-8 and h[k] < h[k - 1]) for k in range(1, len(h) - 1))
