@@ -33,7 +33,9 @@ void set_error(const char* fmt, ...) {
 
 namespace {
 
-constexpr int64_t kMaxPoints = (int64_t)1 << 30;  // 32-bit indices inside the kernels
+// point and node indices are 32-bit inside the kernels and child-block
+// indices use 28 bits (a tree has fewer than 2 nodes per point)
+constexpr int64_t kMaxPoints = (int64_t)1 << 27;
 
 fga_status check_params(const fga_params* p) {
   if (!p) {
@@ -121,7 +123,7 @@ fga_status check_dtype(fga_dtype dt) {
 
 fga_status check_count(int64_t n, const char* what) {
   if (n < 1 || n > kMaxPoints) {
-    set_error("%s must be in [1, 2^30] (got %lld)", what, (long long)n);
+    set_error("%s must be in [1, 2^27] (got %lld)", what, (long long)n);
     return FGA_E_INVALID_ARG;
   }
   return FGA_OK;
@@ -263,7 +265,7 @@ struct fga_state {
   int64_t n, m;
   void* X = nullptr;        // packed reference (Morton-sorted for BH)
   void* Q = nullptr;        // packed template (Morton-sorted)
-  BHNode* nodes = nullptr;
+  BHWide* nodes = nullptr;  // BH tree in child-block layout
   int n_nodes = 0;
   RigidState* st = nullptr;
   double* partial = nullptr;
@@ -277,7 +279,8 @@ struct fga_state {
 
 struct fga_tree {
   int64_t n;
-  BHNode* nodes = nullptr;
+  BHNode* nodes = nullptr;  // preorder (exported)
+  BHWide* wide = nullptr;   // child-block layout (traversed)
   int n_nodes = 0;
   int* order = nullptr;
   void* Xs = nullptr;
@@ -305,13 +308,14 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands, int* 
   hipEvent_t e0, e1;
   FGA_HIP(hipEventCreate(&e0));
   FGA_HIP(hipEventCreate(&e1));
-  const int tiles = (int)((S->m + kBlock - 1) / kBlock);
   float best_ms = 1e30f;
   fga_status st = FGA_OK;
   for (int c : cands) {
     PairDev pd = S->pd;
-    pd.jr = c;
-    pd.n_items = tiles * c;
+    pd.slots = c >> 8;
+    pd.jr = c & 255;
+    pd.tile = kBlock / pd.slots;
+    pd.n_items = (int)((S->m + pd.tile - 1) / pd.tile) * pd.jr;
     auto launch = [&]() {
       return S->f64 ? launch_iteration<double>(pd, S->c, S->s) : launch_iteration<float>(pd, S->c, S->s);
     };
@@ -440,6 +444,11 @@ fga_status fga_tree_create(const void* X, const void* mX, int64_t n, fga_dtype d
     return st;
   }
   t->n_nodes = off[1] - off[0];
+  st = relayout_wide(t->nodes, t->n_nodes, 1, off, &t->wide, s);
+  if (st != FGA_OK) {
+    fga_tree_destroy(t);
+    return st;
+  }
   *out = t;
   return FGA_OK;
 }
@@ -484,6 +493,7 @@ fga_status fga_tree_export(const fga_tree* t, float* com_mass, int32_t* ints, in
 void fga_tree_destroy(fga_tree* t) {
   if (!t) return;
   if (t->nodes) (void)hipFree(t->nodes);
+  if (t->wide) (void)hipFree(t->wide);
   if (t->order) (void)hipFree(t->order);
   if (t->Xs) (void)hipFree(t->Xs);
   delete t;
@@ -539,8 +549,8 @@ fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const 
                        : sort_points_morton<float>(1, &seg, Y4, m, yorder, s);
   if (st == FGA_OK)
     st = dt == FGA_F64
-             ? forces_bh_tree<double>(Y, m, yorder, tr->nodes, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s)
-             : forces_bh_tree<float>(Y, m, yorder, tr->nodes, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s);
+             ? forces_bh_tree<double>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s)
+             : forces_bh_tree<float>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s);
   if (Y4) (void)hipFree(Y4);
   if (yorder) (void)hipFree(yorder);
   fga_tree_destroy(tr);
@@ -594,30 +604,42 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
   if (p->theta > 0) {
     TreeSeg sx{0, n};
     int off[2] = {0, 0};
-    st = S->f64 ? build_trees<double>(1, &sx, S->X, n, p->leaf_size, &S->nodes, off, nullptr, S->tree_stats, s)
-                : build_trees<float>(1, &sx, S->X, n, p->leaf_size, &S->nodes, off, nullptr, S->tree_stats, s);
+    BHNode* pre = nullptr;
+    st = S->f64 ? build_trees<double>(1, &sx, S->X, n, p->leaf_size, &pre, off, nullptr, S->tree_stats, s)
+                : build_trees<float>(1, &sx, S->X, n, p->leaf_size, &pre, off, nullptr, S->tree_stats, s);
     if (st != FGA_OK) return fail(st);
     S->n_nodes = off[1] - off[0];
+    st = relayout_wide(pre, S->n_nodes, 1, off, &S->nodes, s);
+    (void)hipFree(pre);
+    if (st != FGA_OK) return fail(st);
   }
   const bool bh = p->theta > 0;
   int jr = bh ? bh_ranges(m, n) : direct_ranges(m, n);
+  int slots = 1;
+  // candidate work splits: (lanes per particle, reference ranges) encoded slots << 8 | ranges
   std::vector<int> cands;
+  const bool tunable_slots = bh && !S->f64 && p->precision == FGA_PREC_FP32_KAHAN;
   if (p->velocity == FGA_VEL_PARTICLE) {
     jr = 1;
   } else if (p->tile > 0) {
     jr = p->tile;
   } else {
-    for (int c = 1; c <= (bh ? 16 : 64); c *= 2) {
-      const int64_t per = n / c;
-      if (c == 1 || (per >= (bh ? 256 : 1024) && ((m + kBlock - 1) / kBlock) * c <= 65536))
-        cands.push_back(c);
-    }
+    for (int sl = 1; sl <= (tunable_slots ? 8 : 1); sl *= 2)
+      for (int c = 1; c <= (bh ? 16 : 64); c *= 2) {
+        const int64_t per = n / c;
+        const int64_t tl = (m + kBlock / sl - 1) / (kBlock / sl);
+        if ((c == 1 || (per >= (bh ? 256 : 1024) && tl * c <= 65536)) && tl * c <= 262144)
+          cands.push_back(sl << 8 | c);
+      }
   }
-  int max_jr = jr;
-  for (int c : cands) max_jr = std::max(max_jr, c);
-  const int tiles = (int)((m + kBlock - 1) / kBlock);
+  size_t max_items = 0;
+  for (int c : cands)
+    max_items = std::max(max_items, (size_t)((m + kBlock / (c >> 8) - 1) / (kBlock / (c >> 8))) * (c & 255));
+  const int tp = kBlock / slots;  // template particles per tile
+  const int tiles = (int)((m + tp - 1) / tp);
   const int items = tiles * jr;
-  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * (size_t)tiles * max_jr) != hipSuccess ||
+  max_items = std::max(max_items, (size_t)items);
+  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * max_items) != hipSuccess ||
       hipMalloc((void**)&S->done, sizeof(unsigned)) != hipSuccess) {
     set_error("hipMalloc of the iteration buffers failed");
     return fail(FGA_E_NOMEM);
@@ -644,6 +666,8 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
   pd.n_nodes = S->n_nodes;
   pd.jr = jr;
   pd.n_items = items;
+  pd.tile = tp;
+  pd.slots = slots;
   pd.pad_ = 0;
   S->c = make_iter_consts(*p);
   // manual stepping has no iteration cap; fga_register applies max_iter itself
@@ -662,18 +686,19 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
       auto it = g_tune.find(key);
       if (it != g_tune.end()) found = it->second;
     }
-    if (found > 0 && std::find(cands.begin(), cands.end(), found) != cands.end()) {
-      pd.jr = found;
-    } else {
-      int best = jr;
+    int best = found;
+    if (!(found > 0 && std::find(cands.begin(), cands.end(), found) != cands.end())) {
+      best = cands[0];
       fga_status tst = tune_ranges(S, cands, &best);
       if (tst != FGA_OK) return fail(tst);
-      pd.jr = best;
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[key] = best;
       tune_save_locked();
     }
-    pd.n_items = tiles * pd.jr;
+    pd.slots = best >> 8;
+    pd.jr = best & 255;
+    pd.tile = kBlock / pd.slots;
+    pd.n_items = (int)((m + pd.tile - 1) / pd.tile) * pd.jr;
   }
   *out = S;
   return FGA_OK;
@@ -872,11 +897,14 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     xs[k] = {xoff[k], n[k]};
   }
   FGA_TRY(sort_points_morton<T>(npairs, ys.data(), Qp, NY, nullptr, s));
-  BHNode* nodes = nullptr;
+  BHWide* nodes = nullptr;
   std::vector<int> noff(npairs + 1, 0);
   int tstats[3];
   if (p.theta > 0) {
-    FGA_TRY(build_trees<T>(npairs, xs.data(), Xp, NX, p.leaf_size, &nodes, noff.data(), nullptr, tstats, s));
+    BHNode* pre = nullptr;
+    FGA_TRY(build_trees<T>(npairs, xs.data(), Xp, NX, p.leaf_size, &pre, noff.data(), nullptr, tstats, s));
+    B.ptrs.push_back(pre);
+    FGA_TRY(relayout_wide(pre, noff[npairs], npairs, noff.data(), &nodes, s));
     B.ptrs.push_back(nodes);
   }
   // work items: template tiles of every pair, largest reference first
@@ -885,10 +913,14 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
   std::vector<int> item_off(npairs + 1, 0);
   for (int k = 0; k < npairs; ++k) {
     int jr = big ? 1 : (p.theta > 0 ? bh_ranges(m[k], n[k]) : direct_ranges(m[k], n[k]));
-    const int tiles = (int)((m[k] + kBlock - 1) / kBlock);
+    const int tp = kBlock;
+    const int tiles = (int)((m[k] + tp - 1) / tp);
     item_off[k + 1] = item_off[k] + tiles * jr;
     pds[k].jr = jr;
     pds[k].n_items = tiles * jr;
+    pds[k].tile = tp;
+    pds[k].slots = 1;
+    pds[k].pad_ = 0;
   }
   const int n_items = item_off[npairs];
   double* partial;
@@ -912,7 +944,6 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pd.n = (int)n[k];
     pd.m = (int)m[k];
     pd.n_nodes = nodes ? noff[k + 1] - noff[k] : 0;
-    pd.pad_ = 0;
   }
   std::vector<int> order(npairs);
   for (int k = 0; k < npairs; ++k) order[k] = k;

@@ -94,11 +94,25 @@ struct alignas(16) BHNode {
                // all singleton leaves)
 };
 
+// The same tree laid out for the traversal kernels: the children of every
+// internal node are stored contiguously (a "child block"), blocks of the
+// parents in preorder, so opening a node fetches all its children at once.
+// 32 bytes. Indices are local to the node's segment.
+struct alignas(16) BHWide {
+  float4 cm;   // centre of mass (x, y, z) and mass
+  int first;   // points [first, last] of the Morton-sorted reference
+  int last;
+  int child;   // internal: index of the first child | (children - 1) << 29 (as unsigned
+               // bits; the index is below 2^28, so the field is never -1); leaf: -1
+  float l2;    // squared box diagonal; sign bit: twig (all children singleton leaves)
+};
+constexpr int kChildShift = 29;
+
 // Geometry of one registration pair on the device, for the iteration kernels.
 struct PairDev {
   const void* X;        // reference (x, y, z, mass) as vec4, normalised; Morton-sorted for BH
   const void* Q;        // template (q_x, q_y, q_z, c) as vec4 in the body frame; c = damping coeff
-  const BHNode* nodes;  // BH nodes, or nullptr for the direct sum
+  const BHWide* nodes;  // BH nodes in child-block layout, or nullptr for the direct sum
   void* V;              // per-particle velocities (particle mode), m x 3 of T, else nullptr
   RigidState* st;
   double* partial;      // n_items x 12 partial moments
@@ -107,6 +121,8 @@ struct PairDev {
   int n_nodes;
   int jr;               // reference ranges per template tile
   int n_items;          // template tiles x jr
+  int tile;             // template particles per tile (kBlock / slots)
+  int slots;            // lanes per template particle in the Barnes-Hut traversal (1, 2, 4, 8)
   int pad_;
 };
 
@@ -144,6 +160,10 @@ template <typename T>
 fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t ntotal,
                        int leaf_size, BHNode** nodes_out, int* node_off_host, int** order_out,
                        int* stats_host, hipStream_t s);
+// Child-block layout of preorder trees (all segments); node_off_host bounds
+// each segment's nodes, which keep their count and offsets.
+fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node_off_host,
+                         BHWide** out, hipStream_t s);
 template <typename T>
 fga_status sort_points_morton(int nseg, const TreeSeg* segs, void* Q, int64_t ntot, int* perm,
                               hipStream_t s);
@@ -154,7 +174,7 @@ template <typename T>
 fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
                          const void* mY, const fga_params& p, void* F, hipStream_t s);
 template <typename T>
-fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHNode* nodes,
+fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
                           int n_nodes, const void* Xs, double theta, const fga_params& p,
                           const void* mY, void* F, long long* interactions, hipStream_t s);
 template <typename T>

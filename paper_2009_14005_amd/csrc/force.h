@@ -86,6 +86,36 @@ __device__ inline double rsqrt3_mass<double>(double m, double r2) {
   return m / (r2 * sqrt(r2));
 }
 
+
+// ------------------------------------------------------------- Barnes-Hut
+// Wavefront-cooperative traversal with per-lane decisions. Lanes are template
+// particles; the wave walks the union of the nodes its lanes need, and every
+// lane makes exactly the accept/open decisions of Alg. 2 for its own particle,
+// whatever its neighbours do. The walk is a depth-first stack of child blocks
+// kept in LDS: an entry is (first child, number of children, mask of the lanes
+// that opened the parent). Popping an entry fetches the whole block (the
+// children are contiguous), so one round trip to memory serves up to eight
+// nodes. For every node of the block each active lane
+//   - accepts it when l^2 < theta^2 r^2 (Eq. MAC with l / r < theta; r = 0
+//     never accepts) and adds the node's Eq. (GAForce) term;
+//   - otherwise evaluates a leaf, or a twig (an internal node whose children
+//     are all singleton leaves, whose opening evaluates every child exactly),
+//     point by point;
+//   - otherwise opens it: the lanes that open a node push its child block.
+// Singleton leaves are always evaluated directly in FP32 lanes: the node holds
+// the point and its mass, so acceptance and opening give the same term.
+//
+// A traversal may be restricted to reference points [j0, j1): subtrees outside
+// the range are skipped, an accepted node is counted only by the range that
+// holds its first point, and a leaf contributes only its points inside the
+// range. The ranges of one particle together give exactly its Alg. 2 sum.
+constexpr int kStack = 192;  // entries per wave; a walk needs at most 8 per tree level
+struct StackEntry {
+  int start;
+  int count;
+  unsigned long long mask;
+};
+
 // One exact term of Eq. (GAForce) (per unit G and template mass).
 template <typename T>
 __device__ inline void accum_point(const vec4_t<T>& x, T yx, T yy, T yz, T eps2, T& ax, T& ay,
@@ -97,99 +127,105 @@ __device__ inline void accum_point(const vec4_t<T>& x, T yx, T yy, T yz, T eps2,
   az += ez * s;
 }
 
-// ------------------------------------------------------------- Barnes-Hut
-// Wavefront-cooperative traversal with per-lane decisions. Nodes are in
-// depth-first preorder, so every lane's walk is a sequence of increasing node
-// indices: after visiting node n a lane continues at n + 1 (node opened) or
-// at skip(n) (node accepted, leaf done, or subtree irrelevant). The wave
-// visits the smallest index any lane wants next; lanes that do not want that
-// node idle. Each lane therefore makes exactly the accept/open decisions of
-// Alg. 2 for its own particle, whatever its neighbours do.
-//
-// A traversal may be restricted to reference points [j0, j1): subtrees outside
-// the range are skipped, an accepted node is counted only by the range that
-// holds its first point, and an opened leaf contributes only its points inside
-// the range. The ranges of one particle together give exactly its Alg. 2 sum.
-//
-// theta2 = theta^2; a node is accepted when l^2 < theta^2 r^2 (Eq. MAC with
-// l / r < theta; r = 0 never accepts). Singleton leaves are always evaluated
-// directly: the node holds the point and its mass, so acceptance and opening
-// give the same term.
-template <typename T>
-__device__ inline void bh_accum(const BHNode* __restrict__ nodes,
-                                const vec4_t<T>* __restrict__ X, int root, int end, int j0,
-                                int j1, float theta2, T eps2, bool active, T yx, T yy, T yz,
-                                T& ax, T& ay, T& az, unsigned& count) {
-  unsigned next = active ? (unsigned)root : 0xFFFFFFFFu;
-  const unsigned uend = (unsigned)end;
-  unsigned n = wave_min_u32(next);
-  if (n >= uend) return;
-  BHNode nd = nodes[n];
-  // a correct walk visits every node at most once; the cap only bounds the loop
-  for (unsigned visits = 0; visits <= uend; ++visits) {
-    // the next node in preorder is the most likely successor: fetch it early
-    const unsigned nn = n + 1 < uend ? n + 1 : n;
-    const BHNode ahead = nodes[nn];
-    const bool here = next == n;
-    const unsigned after = (unsigned)nd.skip > n ? (unsigned)nd.skip : n + 1;
-    if (nd.first < j1 && nd.last >= j0) {  // some point of the range lies below this node
-      const bool leaf = (unsigned)nd.skip == n + 1;
-      // A twig is an internal node whose children are all singleton leaves
-      // (its subtree holds one node per point). Opening it evaluates every
-      // child exactly, whatever the children's own MAC outcome, so it is
-      // walked like a leaf: the same terms without visiting the children.
-      const bool twig = __float_as_uint(nd.l2) >> 31;
-      const float l2 = fabsf(nd.l2);
-      const T dx = (T)nd.cm.x - yx, dy = (T)nd.cm.y - yy, dz = (T)nd.cm.z - yz;
-      const T r2 = dx * dx + dy * dy + dz * dz;
-      // singleton leaves are taken directly in FP32 lanes (the node is the point)
-      const bool take_node =
-          (sizeof(T) == 4 && leaf && nd.first == nd.last) || l2 < theta2 * (float)r2;
-      if (here && take_node && nd.first >= j0) {  // this range owns the node
-        const T s = rsqrt3_mass<T>((T)nd.cm.w, r2 + eps2);
-        ax += dx * s;
-        ay += dy * s;
-        az += dz * s;
-        ++count;
-      }
-      const bool exact = leaf || twig;
-      const bool open_pts = here && !take_node && exact;
-      if (here) next = (take_node || exact) ? after : n + 1;
-      if (exact && __ballot(open_pts) != 0ull) {
-        const int p0 = max(nd.first, j0), p1 = min(nd.last, j1 - 1);
-        int p = p0;
-        for (; p + 3 <= p1; p += 4) {  // four points per round: loads issued together
-          const vec4_t<T> x0 = X[p], x1 = X[p + 1], x2 = X[p + 2], x3 = X[p + 3];
-          if (open_pts) {
-            accum_point<T>(x0, yx, yy, yz, eps2, ax, ay, az);
-            accum_point<T>(x1, yx, yy, yz, eps2, ax, ay, az);
-            accum_point<T>(x2, yx, yy, yz, eps2, ax, ay, az);
-            accum_point<T>(x3, yx, yy, yz, eps2, ax, ay, az);
-            count += 4;
+// Lanes per particle in the traversal. Each particle is held by S lanes
+// ("slots"); the S lanes of a particle evaluate S nodes of a child block at
+// once, so a wave walks the union of only 64 / S particles' trees and every
+// instruction of the walk serves S nodes. The slots' partial sums are added
+// at the end.
+template <int S>
+struct SlotMask;  // bits of the slot-0 lanes, one per particle of the wave
+template <> struct SlotMask<1> { static constexpr unsigned long long v = ~0ull; };
+template <> struct SlotMask<2> { static constexpr unsigned long long v = 0x5555555555555555ull; };
+template <> struct SlotMask<4> { static constexpr unsigned long long v = 0x1111111111111111ull; };
+template <> struct SlotMask<8> { static constexpr unsigned long long v = 0x0101010101010101ull; };
+
+template <typename T, int S>
+__device__ inline void bh_accum(const BHWide* __restrict__ nodes,
+                                const vec4_t<T>* __restrict__ X, int j0, int j1, float theta2,
+                                T eps2, bool active, T yx, T yy, T yz, T& ax, T& ay, T& az,
+                                unsigned& count, StackEntry* stk) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = lane & (S - 1);
+  const int pbit = lane & ~(S - 1);  // bit of this lane's particle in the lane masks
+  constexpr unsigned long long kRep = SlotMask<S>::v;
+  const unsigned long long amask = __ballot(active) & kRep;
+  T bx = 0, by = 0, bz = 0;  // this slot's share of the particle's sum
+  if (amask != 0ull) {
+    if (lane == 0) stk[0] = StackEntry{0, 1, amask};
+    int sp = 1;
+    while (sp > 0) {
+      --sp;
+      const int start = __builtin_amdgcn_readfirstlane(stk[sp].start);
+      const int cnt = __builtin_amdgcn_readfirstlane(stk[sp].count);
+      const unsigned long long emask =
+          ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(stk[sp].mask >> 32)) << 32) |
+          (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)stk[sp].mask);
+      const bool mine = (emask >> pbit) & 1ull;
+      BHWide nd = nodes[start + (slot < cnt ? slot : 0)];
+      for (int base = 0; base < cnt; base += S) {
+        const int k = base + slot;
+        const bool has = k < cnt;
+        // the next round's node is fetched before this one is processed
+        const int kn = k + S < cnt ? k + S : (has ? k : 0);
+        const BHWide nxt = nodes[start + kn];
+        // some point of the range lies below this node
+        const bool on = has && mine && nd.first < j1 && nd.last >= j0;
+        const bool leaf = nd.child == -1;
+        const bool twig = __float_as_uint(nd.l2) >> 31;
+        const float l2 = fabsf(nd.l2);
+        const T dx = (T)nd.cm.x - yx, dy = (T)nd.cm.y - yy, dz = (T)nd.cm.z - yz;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const bool take =
+            (sizeof(T) == 4 && leaf && nd.first == nd.last) || l2 < theta2 * (float)r2;
+        {  // the node's term, kept only where this lane takes it and this range owns it
+          const bool own = on && take && nd.first >= j0;
+          const T s = rsqrt3_mass<T>((T)nd.cm.w, r2 + eps2);
+          const T sk = own ? s : (T)0;
+          bx += dx * sk;
+          by += dy * sk;
+          bz += dz * sk;
+          count += own ? 1u : 0u;
+        }
+        const bool exact = leaf || twig;
+        const bool open_pts = on && !take && exact;
+        if (__ballot(open_pts) != 0ull) {
+          const int p0 = max(nd.first, j0);
+          const int np = open_pts ? min(nd.last, j1 - 1) - p0 + 1 : 0;
+          for (int t = 0;; ++t) {  // every slot walks its own leaf
+            const bool go = t < np;
+            if (__ballot(go) == 0ull) break;
+            if (go) {
+              accum_point<T>(X[p0 + t], yx, yy, yz, eps2, bx, by, bz);
+              ++count;
+            }
           }
         }
-        for (; p <= p1; ++p) {
-          const vec4_t<T> x = X[p];
-          if (open_pts) {
-            accum_point<T>(x, yx, yy, yz, eps2, ax, ay, az);
-            ++count;
+        const unsigned long long ob = __ballot(on && !take && !exact);
+        if (ob != 0ull) {
+          for (int s = 0; s < S; ++s) {  // the particles that opened slot s's node
+            const unsigned long long om = (ob >> s) & kRep;
+            if (om != 0ull && sp < kStack) {
+              const int ch = __builtin_amdgcn_readlane(nd.child, s);
+              if (lane == 0)
+                stk[sp] = StackEntry{ch & ((1 << kChildShift) - 1),
+                                     (int)((unsigned)ch >> kChildShift) + 1, om};
+              ++sp;
+            }
           }
         }
+        nd = nxt;
       }
-    } else if (here) {
-      next = after;
-    }
-    // successor: n + 1 whenever some lane opened n, else the smallest wanted index
-    if (__ballot(next == n + 1) != 0ull) {
-      n = n + 1;
-      if (n >= uend) break;
-      nd = ahead;
-    } else {
-      n = wave_min_u32(next);
-      if (n >= uend) break;
-      nd = nodes[n];
     }
   }
+#pragma unroll
+  for (int o = 1; o < S; o <<= 1) {  // add the slots of each particle
+    bx += __shfl_xor(bx, o, kWave);
+    by += __shfl_xor(by, o, kWave);
+    bz += __shfl_xor(bz, o, kWave);
+  }
+  ax += bx;
+  ay += by;
+  az += bz;
 }
 
 }  // namespace fga

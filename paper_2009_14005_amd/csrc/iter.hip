@@ -74,14 +74,16 @@ __device__ inline void jrange(int n, int jrn, int jr, int& j0, int& j1) {
 
 // One item of the fused iteration. Returns true in thread 0 of the block that
 // completed the pair's iteration (after the rigid step has been applied).
-template <typename T, bool BH, int PREC>
+template <typename T, bool BH, int PREC, int S>
 __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
-                               double* lds) {
+                               double* lds, StackEntry* stk) {
   __shared__ int s_last;
   const RigidState* st = pd.st;
+  // S lanes per particle (Barnes-Hut traversal width; 1 for the direct sum)
   const int it = item / pd.jr, jr = item - (item / pd.jr) * pd.jr;
-  const int i = it * kBlock + (int)threadIdx.x;
+  const int i = it * (kBlock / S) + (int)threadIdx.x / S;
   const bool valid = i < pd.m;
+  const bool owner = valid && (threadIdx.x & (S - 1)) == 0;  // writes the particle's results
   const Coef<T> cf = load_coef<T>(st);
   const vec4_t<T>* Q = (const vec4_t<T>*)pd.Q;
   const vec4_t<T> q = Q[valid ? i : pd.m - 1];
@@ -93,8 +95,8 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   T ax = 0, ay = 0, az = 0;
   unsigned cnt = 0;
   if (BH) {
-    bh_accum<T>(pd.nodes, (const vec4_t<T>*)pd.X, 0, pd.n_nodes, j0, j1, c.ftheta2, cEps2<T>(c),
-                valid, y0, y1, y2, ax, ay, az, cnt);
+    bh_accum<T, S>(pd.nodes, (const vec4_t<T>*)pd.X, j0, j1, c.ftheta2, cEps2<T>(c), valid, y0,
+                   y1, y2, ax, ay, az, cnt, stk + (threadIdx.x / kWave) * kStack);
   } else if constexpr (sizeof(T) == 8) {
     direct_f64((const double4*)pd.X, j0, j1, y0, y1, y2, c.eps2, ax, ay, az);
   } else {
@@ -122,7 +124,7 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   const T w0 = keep * v0 + dt * (G * ax);
   const T w1 = keep * v1 + dt * (G * ay);
   const T w2 = keep * v2 + dt * (G * az);
-  if (c.velocity == FGA_VEL_PARTICLE && valid) {  // only with a single reference range
+  if (c.velocity == FGA_VEL_PARTICLE && owner) {  // only with a single reference range
     T* V = (T*)pd.V;
     V[3 * i] = w0;
     V[3 * i + 1] = w1;
@@ -133,15 +135,15 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   if (PREC == FGA_PREC_FP32_ALL) {
     const float d[3] = {(float)(dt * w0), (float)(dt * w1), (float)(dt * w2)};
     const float qq[3] = {(float)q.x, (float)q.y, (float)q.z};
-    for (int a = 0; a < 3; ++a) mom[a] = valid ? (double)d[a] : 0.0;
+    for (int a = 0; a < 3; ++a) mom[a] = owner ? (double)d[a] : 0.0;
     for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = valid ? (double)(d[a] * qq[b]) : 0.0;
+      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = owner ? (double)(d[a] * qq[b]) : 0.0;
   } else {
     const double d[3] = {(double)(dt * w0), (double)(dt * w1), (double)(dt * w2)};
     const double qq[3] = {(double)q.x, (double)q.y, (double)q.z};
-    for (int a = 0; a < 3; ++a) mom[a] = valid ? d[a] : 0.0;
+    for (int a = 0; a < 3; ++a) mom[a] = owner ? d[a] : 0.0;
     for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = valid ? d[a] * qq[b] : 0.0;
+      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = owner ? d[a] * qq[b] : 0.0;
   }
   block_sum<kMom>(mom, lds);
   if (BH) {  // interaction count of the block
@@ -179,11 +181,12 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   }
 }
 
-template <typename T, bool BH, int PREC>
+template <typename T, bool BH, int PREC, int S>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_iteration(PairDev pd, IterConsts c) {
   __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ StackEntry stk[BH ? (kBlock / kWave) * kStack : 1];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
-  iteration_item<T, BH, PREC>(pd, c, (int)blockIdx.x, lds);
+  iteration_item<T, BH, PREC, S>(pd, c, (int)blockIdx.x, lds, stk);
 }
 
 // Persistent batched iteration: blocks pull (pair, item) entries from a work
@@ -194,6 +197,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
                                                             const int2* items, int n_items,
                                                             unsigned* queue, IterConsts c) {
   __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ StackEntry stk[BH ? (kBlock / kWave) * kStack : 1];
   __shared__ int s_item;
   while (true) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int2 w = items[e];
     const PairDev pd = pairs[w.x];
     if (pd.st->converged) continue;
-    iteration_item<T, BH, PREC>(pd, c, w.y, lds);
+    iteration_item<T, BH, PREC, 1>(pd, c, w.y, lds, stk);
     __syncthreads();
   }
   if (threadIdx.x == 0) {  // the last block out resets the queue
@@ -225,21 +229,29 @@ fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t 
   const bool bh = pd.nodes != nullptr;
   const dim3 grid((unsigned)pd.n_items);
   if (sizeof(T) == 8) {
-    if (bh) k_iteration<T, true, FGA_PREC_FP64><<<grid, kBlock, 0, s>>>(pd, c);
-    else k_iteration<T, false, FGA_PREC_FP64><<<grid, kBlock, 0, s>>>(pd, c);
+    if (bh) k_iteration<T, true, FGA_PREC_FP64, 1><<<grid, kBlock, 0, s>>>(pd, c);
+    else k_iteration<T, false, FGA_PREC_FP64, 1><<<grid, kBlock, 0, s>>>(pd, c);
   } else {
     switch (c.prec) {
       case FGA_PREC_FP32:
-        if (bh) k_iteration<T, true, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>(pd, c);
-        else k_iteration<T, false, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>(pd, c);
+        if (bh) k_iteration<T, true, FGA_PREC_FP32, 1><<<grid, kBlock, 0, s>>>(pd, c);
+        else k_iteration<T, false, FGA_PREC_FP32, 1><<<grid, kBlock, 0, s>>>(pd, c);
         break;
       case FGA_PREC_FP32_ALL:
-        if (bh) k_iteration<T, true, FGA_PREC_FP32_ALL><<<grid, kBlock, 0, s>>>(pd, c);
-        else k_iteration<T, false, FGA_PREC_FP32_ALL><<<grid, kBlock, 0, s>>>(pd, c);
+        if (bh) k_iteration<T, true, FGA_PREC_FP32_ALL, 1><<<grid, kBlock, 0, s>>>(pd, c);
+        else k_iteration<T, false, FGA_PREC_FP32_ALL, 1><<<grid, kBlock, 0, s>>>(pd, c);
         break;
       default:
-        if (bh) k_iteration<T, true, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>(pd, c);
-        else k_iteration<T, false, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>(pd, c);
+        if (!bh) {
+          k_iteration<T, false, FGA_PREC_FP32_KAHAN, 1><<<grid, kBlock, 0, s>>>(pd, c);
+        } else {
+          switch (pd.slots) {  // traversal width chosen by the autotuner
+            case 2: k_iteration<T, true, FGA_PREC_FP32_KAHAN, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
+            case 4: k_iteration<T, true, FGA_PREC_FP32_KAHAN, 4><<<grid, kBlock, 0, s>>>(pd, c); break;
+            case 8: k_iteration<T, true, FGA_PREC_FP32_KAHAN, 8><<<grid, kBlock, 0, s>>>(pd, c); break;
+            default: k_iteration<T, true, FGA_PREC_FP32_KAHAN, 1><<<grid, kBlock, 0, s>>>(pd, c);
+          }
+        }
     }
   }
   FGA_HIP(hipGetLastError());
@@ -321,19 +333,23 @@ __global__ void k_forces_combine(const T* part, int m, int jrn, const T* mY, dou
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_forces_bh(const T* Y, const int* yorder, int m,
-                                                      const BHNode* nodes, int n_nodes,
+                                                      const BHWide* nodes, int n_nodes,
                                                       const vec4_t<T>* Xs, float theta2, T eps2,
                                                       const T* mY, double G, T* F,
                                                       unsigned long long* count) {
-  const int k = blockIdx.x * kBlock + (int)threadIdx.x;
+  __shared__ StackEntry stk[(kBlock / kWave) * kStack];
+  constexpr int S = 1;
+  const int k = blockIdx.x * (kBlock / S) + (int)threadIdx.x / S;
   const bool valid = k < m;
+  const bool owner = valid && (threadIdx.x & (S - 1)) == 0;
   const int i = valid ? yorder[k] : 0;
   const T yx = Y[3 * i], yy = Y[3 * i + 1], yz = Y[3 * i + 2];
   T ax = 0, ay = 0, az = 0;
   unsigned cnt = 0;
-  bh_accum<T>(nodes, Xs, 0, n_nodes, 0, 0x7fffffff, theta2, eps2, valid, yx, yy, yz, ax, ay, az,
-              cnt);
-  if (valid) {
+  (void)n_nodes;
+  bh_accum<T, S>(nodes, Xs, 0, 0x7fffffff, theta2, eps2, valid, yx, yy, yz, ax, ay, az, cnt,
+                 stk + (threadIdx.x / kWave) * kStack);
+  if (owner) {
     const double w = G * (mY ? (double)mY[i] : 1.0);
     F[3 * i] = (T)(w * (double)ax);
     F[3 * i + 1] = (T)(w * (double)ay);
@@ -398,13 +414,14 @@ template fga_status pack_points<float>(const void*, const void*, int64_t, void*,
 template fga_status pack_points<double>(const void*, const void*, int64_t, void*, hipStream_t);
 
 template <typename T>
-fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHNode* nodes,
+fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
                           int n_nodes, const void* Xs, double theta, const fga_params& p,
                           const void* mY, void* F, long long* interactions, hipStream_t s) {
   unsigned long long* cnt = nullptr;
   FGA_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
   (void)hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
-  k_forces_bh<T><<<(int)((m + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+  constexpr int tp = kBlock;
+  k_forces_bh<T><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
       (const T*)Y, yorder, (int)m, nodes, n_nodes, (const vec4_t<T>*)Xs, (float)(theta * theta),
       (T)(p.eps * p.eps), (const T*)mY, p.G, (T*)F, cnt);
   unsigned long long h = 0;
@@ -424,10 +441,10 @@ template fga_status forces_direct<float>(const void*, int64_t, const void*, int6
                                          const void*, const fga_params&, void*, hipStream_t);
 template fga_status forces_direct<double>(const void*, int64_t, const void*, int64_t, const void*,
                                           const void*, const fga_params&, void*, hipStream_t);
-template fga_status forces_bh_tree<float>(const void*, int64_t, const int*, const BHNode*, int,
+template fga_status forces_bh_tree<float>(const void*, int64_t, const int*, const BHWide*, int,
                                           const void*, double, const fga_params&, const void*,
                                           void*, long long*, hipStream_t);
-template fga_status forces_bh_tree<double>(const void*, int64_t, const int*, const BHNode*, int,
+template fga_status forces_bh_tree<double>(const void*, int64_t, const int*, const BHWide*, int,
                                            const void*, double, const fga_params&, const void*,
                                            void*, long long*, hipStream_t);
 

@@ -783,6 +783,102 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   return FGA_OK;
 }
 
+// ------------------------------------------------------------ child blocks
+namespace {
+
+__device__ inline int seg_of_node(const int* node_off, int nseg, int i) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (node_off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Number of children of every internal node: its children are n + 1 and then
+// successive skip pointers until the node's own skip (at most 8).
+__global__ __launch_bounds__(kBlock) void k_nchild(const BHNode* pre, int total,
+                                                   const int* node_off, int nseg,
+                                                   unsigned* nch) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i > total) return;
+  if (i == total) {
+    nch[i] = 0;
+    return;
+  }
+  const int off = node_off[seg_of_node(node_off, nseg, i)];
+  const int loc = i - off;
+  const int skip = pre[i].skip;
+  unsigned k = 0;
+  if (skip > loc + 1)
+    for (int c = loc + 1; c < skip && k < 9; c = pre[off + c].skip) ++k;
+  nch[i] = k;
+}
+
+__device__ inline BHWide to_wide(const BHNode& nd, int child_field) {
+  BHWide w;
+  w.cm = nd.cm;
+  w.first = nd.first;
+  w.last = nd.last;
+  w.child = child_field;
+  w.l2 = nd.l2;
+  return w;
+}
+
+// Every internal node writes its children's records into its child block
+// (block start = 1 + number of children of the segment's earlier nodes);
+// segment roots write themselves at their segment's first slot.
+__global__ __launch_bounds__(kBlock) void k_relayout(const BHNode* pre, int total,
+                                                     const int* node_off, int nseg,
+                                                     const unsigned* nch, const unsigned* G,
+                                                     BHWide* out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= total) return;
+  const int off = node_off[seg_of_node(node_off, nseg, i)];
+  const int loc = i - off;
+  auto child_field = [&](int g) -> int {  // g: global preorder index of a node
+    if (nch[g] == 0) return -1;
+    const int start = 1 + (int)(G[g] - G[off]);
+    return start | (int)((nch[g] - 1u) << kChildShift);
+  };
+  if (loc == 0) out[off] = to_wide(pre[i], child_field(i));
+  if (nch[i] == 0) return;
+  const int start = 1 + (int)(G[i] - G[off]);
+  int r = 0;
+  for (int c = loc + 1; c < pre[i].skip && r < 8; c = pre[off + c].skip, ++r)
+    out[off + start + r] = to_wide(pre[off + c], child_field(off + c));
+}
+
+}  // namespace
+
+fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node_off_host,
+                         BHWide** out, hipStream_t s) {
+  Scratch sc;
+  int* doff;
+  unsigned *nch, *G, *bsum;
+  const int nb = (int)(((int64_t)total + kScanTile) / kScanTile);
+  FGA_TRY(sc.get(&doff, sizeof(int) * (nseg + 1)));
+  FGA_TRY(sc.get(&nch, sizeof(unsigned) * (total + 1)));
+  FGA_TRY(sc.get(&G, sizeof(unsigned) * (total + 1)));
+  FGA_TRY(sc.get(&bsum, sizeof(unsigned) * nb));
+  FGA_HIP(hipMemcpyAsync(doff, node_off_host, sizeof(int) * (nseg + 1), hipMemcpyHostToDevice, s));
+  k_nchild<<<(total + kBlock) / kBlock, kBlock, 0, s>>>(pre, total, doff, nseg, nch);
+  FGA_TRY((exclusive_scan<unsigned, LoadCnt>(LoadCnt{nch}, (int64_t)total, G, bsum, s)));
+  BHWide* w = nullptr;
+  FGA_HIP(hipMalloc((void**)&w, sizeof(BHWide) * (total ? total : 1)));
+  k_relayout<<<(total + kBlock - 1) / kBlock, kBlock, 0, s>>>(pre, total, doff, nseg, nch, G, w);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(w);
+    set_error("child-block relayout failed: %s", hipGetErrorString(e));
+    return FGA_E_DEVICE;
+  }
+  *out = w;
+  return FGA_OK;
+}
+
 // Sorts the template (vec4, one segment per pair) by Morton code in its own
 // box, so that a wavefront's particles are spatially close.
 template <typename T>

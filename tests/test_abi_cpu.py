@@ -50,7 +50,7 @@ def call_forces(**over):
 
 @pytest.mark.parametrize("over,code", [
     (dict(Y=None), 1), (dict(X=None), 1), (dict(mX=None), 1), (dict(F=None), 1),
-    (dict(m=0), 1), (dict(n=-3), 1), (dict(n=(1 << 30) + 1), 1), (dict(dt=7), 1),
+    (dict(m=0), 1), (dict(n=-3), 1), (dict(n=(1 << 27) + 1), 1), (dict(dt=7), 1),
     (dict(theta=-0.5), 1), (dict(theta=float("nan")), 1),
     (dict(p=fga.default_params(eps=0.0)), 1), (dict(p=fga.default_params(G=-1.0)), 1),
     (dict(p=fga.default_params(dt=0.0)), 1), (dict(p=fga.default_params(eta=1.5)), 1),
