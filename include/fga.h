@@ -96,7 +96,13 @@ typedef struct {
   int tile;               /* reference ranges per template tile of 256 particles (work split of
                              one iteration); 0 = autotuned per shape class and cached */
   int check_every;        /* host checks the convergence flag every k iterations (0 = 16) */
-  int reserved[5];
+  int group_width;        /* BH traversal (FP32 only): 1 = per-particle, every particle makes
+                             the Alg. 2 accept/open decisions itself; 64 or 128 = the
+                             particles of a wave (consecutive in Morton order) share one walk,
+                             a node being accepted only if the MAC holds for the group's whole
+                             bounding box (at least as accurate as per-particle); 0 = chosen
+                             by the autotuner among these. FP64 uses 1. */
+  int reserved[4];
 } fga_params;
 
 typedef struct {

@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
         ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("damping", ctypes.c_int),
         ("velocity", ctypes.c_int), ("mass_mode", ctypes.c_int), ("precision", ctypes.c_int),
         ("leaf_size", ctypes.c_int), ("tile", ctypes.c_int), ("check_every", ctypes.c_int),
-        ("reserved", ctypes.c_int * 5),
+        ("group_width", ctypes.c_int), ("reserved", ctypes.c_int * 4),
     ]
 
     def replace(self, **kw) -> "Params":

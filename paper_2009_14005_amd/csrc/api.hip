@@ -11,6 +11,7 @@
 #include <string>
 #include <algorithm>
 #include <cstdlib>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -106,6 +107,11 @@ fga_status check_params(const fga_params* p) {
     set_error("leaf_size must be in [0, 64] (got %d)", p->leaf_size);
     return FGA_E_INVALID_ARG;
   }
+  if (p->group_width != 0 && p->group_width != 1 && p->group_width != 64 &&
+      p->group_width != 128) {
+    set_error("group_width must be 0, 1, 64 or 128 (got %d)", p->group_width);
+    return FGA_E_INVALID_ARG;
+  }
   if (p->tile < 0 || p->check_every < 0) {
     set_error("tile and check_every must be >= 0");
     return FGA_E_INVALID_ARG;
@@ -195,15 +201,15 @@ std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_key(bool bh, bool f64, int64_t m, int64_t n, int prec) {
+std::string tune_key(bool bh, bool f64, int64_t m, int64_t n, int prec, int group_width) {
   auto lg = [](int64_t v) {
     int k = 0;
     while ((int64_t(1) << (k + 1)) <= v) ++k;
     return k;
   };
   char buf[96];
-  snprintf(buf, sizeof buf, "%s_%s_p%d_m%d_n%d", bh ? "bh" : "direct", f64 ? "f64" : "f32", prec,
-           lg(m), lg(n));
+  snprintf(buf, sizeof buf, "%s_%s_p%d_g%d_m%d_n%d", bh ? "bh" : "direct", f64 ? "f64" : "f32",
+           prec, group_width, lg(m), lg(n));
   return buf;
 }
 
@@ -275,6 +281,13 @@ struct fga_state {
   IterConsts c;
   NormInfo norm;
   int tree_stats[3] = {0, 0, 0};
+  std::vector<float> qhost;             // Morton-sorted template (x, y, z, c), group walk only
+  struct Groups {
+    int2* dev = nullptr;
+    int n = 0;
+    bool ordered = false;               // sorted by measured cost, heaviest first
+  };
+  std::map<int, Groups> groups;         // key K * 4 + tau option
 };
 
 struct fga_tree {
@@ -296,7 +309,166 @@ static void state_free(fga_state* s) {
   if (s->partial) (void)hipFree(s->partial);
   if (s->done) (void)hipFree(s->done);
   if (s->V) (void)hipFree(s->V);
+  for (auto& kv : s->groups) (void)hipFree(kv.second.dev);
   delete s;
+}
+
+// Groups of the template for the group walk, over its Morton order: runs of
+// at most G consecutive particles; with f > 0 a run also ends before its
+// bounding-box diagonal would exceed f times the median diagonal of the fixed
+// runs of G. Sparse stretches of the order (where consecutive particles are
+// far apart) then form small groups with small boxes instead of one box that
+// opens everything between them.
+static const double kGroupTau[4] = {0.0, 1.0, 2.0, 4.0};
+
+static void make_groups(const float* q4, int64_t m, int G, double f, std::vector<int2>& out) {
+  auto diag2 = [&](int64_t i0, int64_t i1) {
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q4[4 * i0 + a];
+    for (int64_t i = i0 + 1; i < i1; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], q4[4 * i + a]);
+        hi[a] = std::max(hi[a], q4[4 * i + a]);
+      }
+    double d = 0.0;
+    for (int a = 0; a < 3; ++a) d += (double)(hi[a] - lo[a]) * (hi[a] - lo[a]);
+    return d;
+  };
+  out.clear();
+  double tau2 = std::numeric_limits<double>::infinity();
+  if (f > 0) {
+    std::vector<double> d;
+    for (int64_t i = 0; i < m; i += G) d.push_back(diag2(i, std::min<int64_t>(m, i + G)));
+    std::nth_element(d.begin(), d.begin() + d.size() / 2, d.end());
+    const double med = d[d.size() / 2];
+    if (med > 0) tau2 = f * f * med;
+  }
+  int64_t i = 0;
+  while (i < m) {
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q4[4 * i + a];
+    int64_t j = i + 1;
+    for (; j < m && j - i < G; ++j) {
+      float nl[3], nh[3];
+      double dd = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        nl[a] = std::min(lo[a], q4[4 * j + a]);
+        nh[a] = std::max(hi[a], q4[4 * j + a]);
+        dd += (double)(nh[a] - nl[a]) * (nh[a] - nl[a]);
+      }
+      if (dd > tau2) break;
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = nl[a];
+        hi[a] = nh[a];
+      }
+    }
+    out.push_back(make_int2((int)i, (int)(j - i)));
+    i = j;
+  }
+}
+
+// Orders a group table by cost, heaviest first: one iteration with the
+// table (one reference range) counts the list entries of every group, and the
+// state is restored afterwards. Blocks are dispatched in index order, so the
+// expensive groups start first and the cheap ones fill in behind them.
+static fga_status order_groups(fga_state* S, int K, fga_state::Groups& gt) {
+  RigidState saved;
+  FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  unsigned* cost = nullptr;
+  FGA_HIP(hipMalloc((void**)&cost, sizeof(unsigned) * gt.n));
+  std::vector<unsigned> hc(gt.n);
+  std::vector<int2> g(gt.n);
+  PairDev pd = S->pd;
+  pd.group = K;
+  pd.slots = 1;
+  pd.tile = kBlock * K;
+  pd.groups = gt.dev;
+  pd.n_groups = gt.n;
+  pd.gcost = cost;
+  pd.jr = 1;
+  pd.n_items = (gt.n + kBlock / kWave - 1) / (kBlock / kWave);
+  fga_status st = FGA_OK;
+  if (hipMemsetAsync(cost, 0, sizeof(unsigned) * gt.n, S->s) != hipSuccess) st = FGA_E_DEVICE;
+  if (st == FGA_OK) st = launch_iteration<float>(pd, S->c, S->s);
+  if (st == FGA_OK &&
+      (hipMemcpyAsync(hc.data(), cost, sizeof(unsigned) * gt.n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
+       hipMemcpyAsync(g.data(), gt.dev, sizeof(int2) * gt.n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
+       hipMemcpyAsync(S->st, &saved, sizeof saved, hipMemcpyHostToDevice, S->s) != hipSuccess ||
+       hipStreamSynchronize(S->s) != hipSuccess))
+    st = FGA_E_DEVICE;
+  (void)hipFree(cost);
+  if (st != FGA_OK) {
+    if (st == FGA_E_DEVICE) set_error("group cost measurement failed");
+    return st;
+  }
+  // heaviest first (cutting heavy groups into smaller runs was measured to
+  // lose more to the per-wave overhead of the extra waves than it gained)
+  std::vector<std::pair<double, int2>> parts;
+  for (int k = 0; k < gt.n; ++k) parts.push_back({(double)hc[k], g[k]});
+  std::stable_sort(parts.begin(), parts.end(),
+                   [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
+                     return x.first > y.first;
+                   });
+  std::vector<int2> sorted(parts.size());
+  for (size_t k = 0; k < parts.size(); ++k) sorted[k] = parts[k].second;
+  gt.n = (int)sorted.size();
+  FGA_HIP(hipMemcpyAsync(gt.dev, sorted.data(), sizeof(int2) * gt.n, hipMemcpyHostToDevice, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  gt.ordered = true;
+  return FGA_OK;
+}
+
+// Device groups of a state for (K, tau option), built on first use and, once
+// the state can iterate (`order`), sorted by cost.
+static fga_status ensure_groups(fga_state* S, int K, int fi, bool order, const int2** dev,
+                                int* count) {
+  const int key = K * 4 + fi;
+  auto it = S->groups.find(key);
+  if (it == S->groups.end()) {
+    if (S->qhost.empty()) {
+      S->qhost.resize((size_t)S->m * 4);
+      FGA_HIP(hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * S->m, hipMemcpyDeviceToHost, S->s));
+      FGA_HIP(hipStreamSynchronize(S->s));
+    }
+    std::vector<int2> g;
+    make_groups(S->qhost.data(), S->m, kWave * K, kGroupTau[fi], g);
+    fga_state::Groups gt;
+    FGA_HIP(hipMalloc((void**)&gt.dev, sizeof(int2) * g.size()));
+    gt.n = (int)g.size();
+    it = S->groups.emplace(key, gt).first;
+    FGA_HIP(hipMemcpyAsync(gt.dev, g.data(), sizeof(int2) * g.size(), hipMemcpyHostToDevice, S->s));
+    FGA_HIP(hipStreamSynchronize(S->s));
+  }
+  if (order && !it->second.ordered) FGA_TRY(order_groups(S, K, it->second));
+  *dev = it->second.dev;
+  *count = it->second.n;
+  return FGA_OK;
+}
+
+// Applies a work split (mode << 8 | reference ranges) to a pair's launch
+// geometry. mode: lanes per particle of the per-particle walk (1, 2, 4, 8), or
+// 16 + K + 4 fi for the group walk with K particles per lane and groups bounded
+// by kGroupTau[fi].
+static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool order = true) {
+  const int mode = code >> 8;
+  pd.jr = code & 255;
+  pd.groups = nullptr;
+  pd.gcost = nullptr;
+  pd.n_groups = 0;
+  if (mode >= 16) {
+    pd.group = (mode - 16) & 3;
+    pd.slots = 1;
+    pd.tile = kBlock * pd.group;
+    FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, order, &pd.groups, &pd.n_groups));
+    pd.n_items = ((pd.n_groups + kBlock / kWave - 1) / (kBlock / kWave)) * pd.jr;
+  } else {
+    pd.group = 0;
+    pd.slots = mode;
+    pd.tile = kBlock / mode;
+    pd.n_items = (int)((S->m + pd.tile - 1) / pd.tile) * pd.jr;
+  }
+  return FGA_OK;
 }
 
 // Times each candidate number of reference ranges on the state's own kernel,
@@ -312,10 +484,8 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands, int* 
   fga_status st = FGA_OK;
   for (int c : cands) {
     PairDev pd = S->pd;
-    pd.slots = c >> 8;
-    pd.jr = c & 255;
-    pd.tile = kBlock / pd.slots;
-    pd.n_items = (int)((S->m + pd.tile - 1) / pd.tile) * pd.jr;
+    st = apply_split(S, pd, c);
+    if (st != FGA_OK) break;
     auto launch = [&]() {
       return S->f64 ? launch_iteration<double>(pd, S->c, S->s) : launch_iteration<float>(pd, S->c, S->s);
     };
@@ -372,6 +542,7 @@ fga_status fga_default_params(fga_params* p) {
   p->leaf_size = 1;
   p->tile = 0;
   p->check_every = 16;
+  p->group_width = 0;
   return FGA_OK;
 }
 
@@ -614,31 +785,50 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
     if (st != FGA_OK) return fail(st);
   }
   const bool bh = p->theta > 0;
-  int jr = bh ? bh_ranges(m, n) : direct_ranges(m, n);
-  int slots = 1;
-  // candidate work splits: (lanes per particle, reference ranges) encoded slots << 8 | ranges
-  std::vector<int> cands;
-  const bool tunable_slots = bh && !S->f64 && p->precision == FGA_PREC_FP32_KAHAN;
-  if (p->velocity == FGA_VEL_PARTICLE) {
-    jr = 1;
-  } else if (p->tile > 0) {
-    jr = p->tile;
+  // candidate work splits, encoded mode << 8 | reference ranges; mode is the
+  // number of lanes per particle (1, 2, 4, 8) of the per-particle walk, or
+  // 16 + K for the group walk with K particles per lane
+  std::vector<int> modes;
+  if (!bh || S->f64) {
+    modes.push_back(1);
   } else {
-    for (int sl = 1; sl <= (tunable_slots ? 8 : 1); sl *= 2)
+    const int gw = p->group_width;
+    if (gw == 0 || gw == 1)
+      for (int sl = 1; sl <= (p->precision == FGA_PREC_FP32_KAHAN ? 8 : 1); sl *= 2)
+        modes.push_back(sl);
+    for (int fi = 0; fi < 4; ++fi) {
+      if (gw == 0 || gw == 64) modes.push_back(16 + 1 + 4 * fi);
+      if (gw == 0 || gw == 128) modes.push_back(16 + 2 + 4 * fi);
+    }
+  }
+  std::vector<int> cands;
+  for (int md : modes) {
+    const int64_t tp = md >= 16 ? (int64_t)kBlock * ((md - 16) & 3) : kBlock / md;
+    const int64_t tl = (m + tp - 1) / tp;
+    if (p->velocity == FGA_VEL_PARTICLE) {
+      cands.push_back(md << 8 | 1);
+    } else if (p->tile > 0) {
+      cands.push_back(md << 8 | p->tile);
+    } else {
       for (int c = 1; c <= (bh ? 16 : 64); c *= 2) {
         const int64_t per = n / c;
-        const int64_t tl = (m + kBlock / sl - 1) / (kBlock / sl);
         if ((c == 1 || (per >= (bh ? 256 : 1024) && tl * c <= 65536)) && tl * c <= 262144)
-          cands.push_back(sl << 8 | c);
+          cands.push_back(md << 8 | c);
       }
+    }
+  }
+  if (!bh && p->tile == 0 && p->velocity != FGA_VEL_PARTICLE) {
+    // the direct sum starts from its occupancy rule; the tuner may improve on it
+    const int jd = direct_ranges(m, n);
+    if (std::find(cands.begin(), cands.end(), 1 << 8 | jd) == cands.end()) cands.push_back(1 << 8 | jd);
   }
   size_t max_items = 0;
-  for (int c : cands)
-    max_items = std::max(max_items, (size_t)((m + kBlock / (c >> 8) - 1) / (kBlock / (c >> 8))) * (c & 255));
-  const int tp = kBlock / slots;  // template particles per tile
-  const int tiles = (int)((m + tp - 1) / tp);
-  const int items = tiles * jr;
-  max_items = std::max(max_items, (size_t)items);
+  for (int c : cands) {
+    PairDev tmp{};
+    const fga_status gs = apply_split(S, tmp, c, false);
+    if (gs != FGA_OK) return fail(gs);
+    max_items = std::max(max_items, (size_t)tmp.n_items);
+  }
   if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * max_items) != hipSuccess ||
       hipMalloc((void**)&S->done, sizeof(unsigned)) != hipSuccess) {
     set_error("hipMalloc of the iteration buffers failed");
@@ -664,11 +854,6 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
   pd.n = (int)n;
   pd.m = (int)m;
   pd.n_nodes = S->n_nodes;
-  pd.jr = jr;
-  pd.n_items = items;
-  pd.tile = tp;
-  pd.slots = slots;
-  pd.pad_ = 0;
   S->c = make_iter_consts(*p);
   // manual stepping has no iteration cap; fga_register applies max_iter itself
   const int big = 0x7fffffff;
@@ -677,8 +862,9 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
     set_error("state initialisation failed");
     return fail(FGA_E_DEVICE);
   }
-  if (!cands.empty() && cands.size() > 1) {
-    const std::string key = tune_key(bh, S->f64, m, n, p->precision);
+  if (fga_status gs = apply_split(S, pd, cands[0]); gs != FGA_OK) return fail(gs);
+  if (cands.size() > 1) {
+    const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width);
     int found = 0;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -695,10 +881,12 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
       g_tune[key] = best;
       tune_save_locked();
     }
-    pd.slots = best >> 8;
-    pd.jr = best & 255;
-    pd.tile = kBlock / pd.slots;
-    pd.n_items = (int)((m + pd.tile - 1) / pd.tile) * pd.jr;
+    if (fga_status gs = apply_split(S, pd, best); gs != FGA_OK) return fail(gs);
+  }
+  if (S->V) {  // trial iterations wrote per-particle velocities; the state starts at rest
+    const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
+    if (hipMemsetAsync(S->V, 0, vb, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return fail(FGA_E_DEVICE);
   }
   *out = S;
   return FGA_OK;
@@ -757,6 +945,10 @@ fga_status fga_state_get(const fga_state* S, double R[9], double t[3], fga_repor
     rep->last_dT2 = h.dT2;
     rep->interactions = h.interactions;
     rep->ms_total = 0.0;
+  }
+  if (h.flags & 2) {
+    set_error("Barnes-Hut group walk: traversal stack overflow (forces incomplete)");
+    return FGA_E_DEVICE;
   }
   if (h.flags & 1) {
     set_error("the template is collinear: the Kabsch rotation is undetermined");
@@ -920,7 +1112,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pds[k].n_items = tiles * jr;
     pds[k].tile = tp;
     pds[k].slots = 1;
-    pds[k].pad_ = 0;
+    pds[k].group = 0;
   }
   const int n_items = item_off[npairs];
   double* partial;

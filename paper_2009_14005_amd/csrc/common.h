@@ -64,7 +64,7 @@ struct RigidState {
   int iter;
   int converged;
   int m;          // template particles
-  int flags;      // bit 0: degenerate Kabsch (rank(C) < 2) seen
+  int flags;      // bit 0: degenerate Kabsch (rank(C) < 2) seen; bit 1: traversal stack overflow
   int max_iter;
   int pad_;
   float fR[9], fmu[3], fA[9], fb[3];  // FP32 copies read by the FP32 force kernels
@@ -123,6 +123,10 @@ struct PairDev {
   int n_items;          // template tiles x jr
   int tile;             // template particles per tile (kBlock / slots)
   int slots;            // lanes per template particle in the Barnes-Hut traversal (1, 2, 4, 8)
+  int group;            // 0: per-particle traversal; K > 0: group traversal, K particles per lane
+  const int2* groups;   // group walk: (first particle, count <= 64 K) of each wave's group
+  unsigned* gcost;      // optional: list entries evaluated per group are added here
+  int n_groups;
   int pad_;
 };
 

@@ -228,4 +228,249 @@ __device__ inline void bh_accum(const BHWide* __restrict__ nodes,
   az += bz;
 }
 
+
+// ------------------------------------------------ Barnes-Hut, group traversal
+// The particles of a wave (64 K, consecutive in the template's body-frame
+// Morton order, hence spatially close) share one walk of the tree. A node is
+// accepted for the whole group when l^2 < theta^2 d^2, with d the distance
+// from its centre of mass to the group's bounding box: then l / r < theta
+// holds for every particle of the group, so each accepted node is one that
+// Alg. 2 would also accept (or reach only through an accepted ancestor), and
+// the sum differs from the per-particle one only in nodes opened further,
+// i.e. it is at least as close to the direct sum. The walk and the sum are
+// separated:
+//   - walk: lanes take up to 64 nodes at once from an LDS stack of child
+//     blocks, test them, append accepted nodes (centre of mass + mass) and
+//     the points of opened leaves and twigs to an LDS interaction list, and
+//     push the child blocks of the other opened nodes;
+//   - sum: whenever the list is nearly full, every lane evaluates its K
+//     particles against the whole list (one broadcast LDS read per entry and
+//     K Eq. (GAForce) terms), as in the direct sum.
+// Reference ranges [j0, j1) split the walk as in the per-particle traversal.
+constexpr int kGList = 128;   // interaction-list entries per wave
+constexpr int kGStack = 512;  // child-block entries per wave
+// Stack entries kept free for a depth-first descent: every level of the tree
+// (at most kQBits + 1 below the root) adds at most 7 entries to the stack.
+constexpr int kGReserve = 8 * (kQBits + 2);
+
+struct GroupLds {
+  float4 list[kGList];
+  int stk[kGStack];
+};
+
+__device__ inline float wave_min_f(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ inline float wave_max_f(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Lane of the first entry whose inclusive prefix count exceeds k (the counts
+// in `incl` are non-decreasing over the lanes and incl[63] > k).
+__device__ inline int wave_owner(int incl, int k) {
+  int o = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1) {
+    const int v = __shfl(incl, o + step - 1, kWave);
+    if (v <= k) o += step;
+  }
+  return o;
+}
+
+// Adds the list entries [0, cnt) to the K particles of this lane if `sel`.
+// With KAHAN the list's sum is one tile, added to the total with Kahan
+// compensation.
+template <int K, bool KAHAN>
+__device__ inline void group_sum(const float4* list, int cnt, const float (&y)[K][3], float eps2,
+                                 bool sel, float (&acc)[K][3], float (&cmp)[K][3]) {
+  float t[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t[k][a] = KAHAN ? 0.f : acc[k][a];
+#pragma unroll 4
+  for (int e = 0; e < cnt; ++e) {
+    const float4 x = list[e];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = x.z - y[k][2];
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+      const float r = __builtin_amdgcn_rsqf(r2);
+      const float s = x.w * r * (r * r);
+      t[k][0] = fmaf(dx, s, t[k][0]);
+      t[k][1] = fmaf(dy, s, t[k][1]);
+      t[k][2] = fmaf(dz, s, t[k][2]);
+    }
+  }
+  if (!sel) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (KAHAN) {
+        const float u = t[k][a] - cmp[k][a], v = acc[k][a] + u;
+        cmp[k][a] = (v - acc[k][a]) - u;
+        acc[k][a] = v;
+      } else {
+        acc[k][a] = t[k][a];
+      }
+    }
+}
+
+// Squared diagonal of the box of the lanes selected by `sel` (their valid
+// particles), and the box itself, uniform over the wave.
+template <int K>
+__device__ inline float group_box(const bool (&valid)[K], const float (&y)[K][3], bool sel,
+                                  float (&lo)[3], float (&hi)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = __builtin_huge_valf();
+    hi[a] = -__builtin_huge_valf();
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (sel && valid[k]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], y[k][a]);
+        hi[a] = fmaxf(hi[a], y[k][a]);
+      }
+    }
+  float d2 = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = wave_min_f(lo[a]);
+    hi[a] = wave_max_f(hi[a]);
+    d2 = fmaf(hi[a] - lo[a], hi[a] - lo[a], d2);
+  }
+  return d2;
+}
+
+// The walk for a group: the particles of the lanes with `sel`.
+template <int K, bool KAHAN>
+__device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
+                                  int j0, int j1, float theta2, float eps2, bool sel,
+                                  int nvalid, const float (&lo)[3], const float (&hi)[3],
+                                  const float (&y)[K][3], float (&acc)[K][3],
+                                  float (&cmp)[K][3], unsigned& count, unsigned& entries,
+                                  GroupLds& g) {
+  const int lane = threadIdx.x & (kWave - 1);
+  bool ok = true;
+  int cnt = 0;  // list entries
+  int sp = 1;   // stack entries; the root is a block of one node at index 0
+  if (lane == 0) g.stk[0] = 0;
+  auto flush = [&]() {
+    group_sum<K, KAHAN>(g.list, cnt, y, eps2, sel, acc, cmp);
+    count += sel ? (unsigned)(cnt * nvalid) : 0u;
+    entries += (unsigned)cnt;
+    cnt = 0;
+  };
+  while (sp > 0) {
+    // pop whole child blocks from the top, at most 64 nodes, and while the
+    // stack stays below kGStack - kGReserve even if every node is opened
+    const int avail = min(sp, kWave);
+    int ch = 0, c = 0;
+    if (lane < avail) {
+      ch = g.stk[sp - 1 - lane];
+      c = (int)((unsigned)ch >> kChildShift) + 1;
+    }
+    const int incl = wave_incl_scan(c);
+    const bool take = lane < avail && incl <= kWave &&
+                      (lane == 0 || sp - (lane + 1) + incl <= kGStack - kGReserve);
+    const int E = __popcll(__ballot(take));
+    const int T = __shfl(incl, E - 1, kWave);
+    sp -= E;
+    // this lane's node: entry e = the first whose prefix count exceeds the lane
+    const int e = wave_owner(lane < E ? incl : 0x7fffffff, lane);
+    const int che = __shfl(ch, e, kWave), ince = __shfl(incl, e, kWave);
+    const bool act = lane < T;
+    const int node = (che & ((1 << kChildShift) - 1)) + lane -
+                     (ince - ((int)((unsigned)che >> kChildShift) + 1));
+    const BHWide nd = nodes[act ? node : 0];
+    const bool on = act && nd.first < j1 && nd.last >= j0;
+    const bool leaf = nd.child == -1;
+    const bool twig = __float_as_uint(nd.l2) >> 31;
+    float d2 = 0.f;
+    {
+      const float c3[3] = {nd.cm.x, nd.cm.y, nd.cm.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float u = fmaxf(fmaxf(lo[a] - c3[a], c3[a] - hi[a]), 0.f);
+        d2 = fmaf(u, u, d2);
+      }
+    }
+    const bool accept = on && ((leaf && nd.first == nd.last) || fabsf(nd.l2) < theta2 * d2);
+    const bool own = accept && nd.first >= j0;
+    const bool pts = on && !accept && (leaf || twig);
+    const bool inner = on && !accept && !leaf && !twig;
+    // push the child blocks of the opened internal nodes
+    const unsigned long long im = __ballot(inner);
+    if (inner) {
+      const int pos = sp + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(im >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)im, 0u));
+      if (pos < kGStack) g.stk[pos] = nd.child;
+    }
+    sp += __popcll(im);
+    if (sp > kGStack) {
+      ok = false;
+      sp = kGStack;
+    }
+    // append the accepted nodes (cnt <= kGList - 64 here)
+    const unsigned long long om = __ballot(own);
+    if (own) {
+      const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(om >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)om, 0u));
+      g.list[pos] = nd.cm;
+    }
+    cnt += __popcll(om);
+    // append the points of opened leaves and twigs, 64 at a time
+    const int p0 = max(nd.first, j0);
+    const int np = pts ? min(nd.last, j1 - 1) - p0 + 1 : 0;
+    if (__ballot(np > 0) != 0ull) {
+      const int pincl = wave_incl_scan(np);
+      const int P = __shfl(pincl, kWave - 1, kWave);
+      for (int base = 0; base < P; base += kWave) {
+        if (cnt > kGList - kWave) flush();
+        const int k = base + lane;
+        const int o = wave_owner(pincl, k);
+        const int oincl = __shfl(pincl, o, kWave), onp = __shfl(np, o, kWave),
+                  op0 = __shfl(p0, o, kWave);
+        if (k < P) g.list[cnt + lane] = X[op0 + k - (oincl - onp)];
+        cnt += min(kWave, P - base);
+      }
+    }
+    if (cnt > kGList - kWave) flush();
+  }
+  if (cnt > 0) flush();
+  return ok;
+}
+
+// Lane l holds particles K l .. K l + K - 1 of the wave's group; `entries`
+// (uniform) receives the number of list entries evaluated. Returns false if
+// the stack overflowed (never for trees of depth at most kQBits + 1;
+// the sum is then incomplete).
+template <int K, bool KAHAN>
+__device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
+                                int j0, int j1, float theta2, float eps2, const bool (&valid)[K],
+                                const float (&y)[K][3], float (&acc)[K][3], unsigned& count,
+                                unsigned& entries, GroupLds& g) {
+  int nvalid = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) nvalid += valid[k] ? 1 : 0;
+  if (__ballot(nvalid > 0) == 0ull) return true;
+  float lo[3], hi[3];
+  group_box<K>(valid, y, true, lo, hi);
+  float cmp[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) cmp[k][a] = 0.f;
+  return group_walk<K, KAHAN>(nodes, X, j0, j1, theta2, eps2, true, nvalid, lo, hi, y, acc, cmp,
+                              count, entries, g);
+}
+
 }  // namespace fga

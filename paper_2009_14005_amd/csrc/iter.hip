@@ -72,78 +72,68 @@ __device__ inline void jrange(int n, int jrn, int jr, int& j0, int& j1) {
   j1 = min(n, j0 + per);
 }
 
-// One item of the fused iteration. Returns true in thread 0 of the block that
-// completed the pair's iteration (after the rigid step has been applied).
-template <typename T, bool BH, int PREC, int S>
-__device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
-                               double* lds, StackEntry* stk) {
+// Steps a5-a7 for the K template particles this thread holds (those with
+// owner[k] set): damped velocity and displacement, FP64 moments, the block's
+// partial sums, and, in the block that completes the pair's iteration, the
+// ordered sum over items and the rigid step.
+// The velocity coefficients and the template coordinates are read again here
+// rather than kept in registers through the force sum.
+template <typename T, bool BH, int PREC, int K>
+__device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, int jr,
+                            const int (&idx)[K], const bool (&owner)[K], const T (&acc)[K][3],
+                            unsigned cnt, double* lds) {
   __shared__ int s_last;
-  const RigidState* st = pd.st;
-  // S lanes per particle (Barnes-Hut traversal width; 1 for the direct sum)
-  const int it = item / pd.jr, jr = item - (item / pd.jr) * pd.jr;
-  const int i = it * (kBlock / S) + (int)threadIdx.x / S;
-  const bool valid = i < pd.m;
-  const bool owner = valid && (threadIdx.x & (S - 1)) == 0;  // writes the particle's results
-  const Coef<T> cf = load_coef<T>(st);
-  const vec4_t<T>* Q = (const vec4_t<T>*)pd.Q;
-  const vec4_t<T> q = Q[valid ? i : pd.m - 1];
-  const T y0 = cf.R[0] * q.x + cf.R[1] * q.y + cf.R[2] * q.z + cf.mu[0];
-  const T y1 = cf.R[3] * q.x + cf.R[4] * q.y + cf.R[5] * q.z + cf.mu[1];
-  const T y2 = cf.R[6] * q.x + cf.R[7] * q.y + cf.R[8] * q.z + cf.mu[2];
-  int j0, j1;
-  jrange(pd.n, pd.jr, jr, j0, j1);
-  T ax = 0, ay = 0, az = 0;
-  unsigned cnt = 0;
-  if (BH) {
-    bh_accum<T, S>(pd.nodes, (const vec4_t<T>*)pd.X, j0, j1, c.ftheta2, cEps2<T>(c), valid, y0,
-                   y1, y2, ax, ay, az, cnt, stk + (threadIdx.x / kWave) * kStack);
-  } else if constexpr (sizeof(T) == 8) {
-    direct_f64((const double4*)pd.X, j0, j1, y0, y1, y2, c.eps2, ax, ay, az);
-  } else {
-    if (PREC == FGA_PREC_FP32_KAHAN)
-      direct_f32<true, 64>((const float4*)pd.X, j0, j1, y0, y1, y2, c.feps2, ax, ay, az);
-    else
-      direct_f32<false, 64>((const float4*)pd.X, j0, j1, y0, y1, y2, c.feps2, ax, ay, az);
-  }
-  // a5: damped velocity and displacement
   const T G = cG<T>(c), dt = cDt<T>(c);
-  T v0 = 0, v1 = 0, v2 = 0;
-  if (jr == 0 && valid) {
-    if (c.velocity == FGA_VEL_RIGID) {
-      v0 = cf.A[0] * q.x + cf.A[1] * q.y + cf.A[2] * q.z + cf.b[0];
-      v1 = cf.A[3] * q.x + cf.A[4] * q.y + cf.A[5] * q.z + cf.b[1];
-      v2 = cf.A[6] * q.x + cf.A[7] * q.y + cf.A[8] * q.z + cf.b[2];
-    } else {
-      const T* V = (const T*)pd.V;
-      v0 = V[3 * i];
-      v1 = V[3 * i + 1];
-      v2 = V[3 * i + 2];
-    }
-  }
-  const T keep = (T)1 - q.w;  // 1 - c_i
-  const T w0 = keep * v0 + dt * (G * ax);
-  const T w1 = keep * v1 + dt * (G * ay);
-  const T w2 = keep * v2 + dt * (G * az);
-  if (c.velocity == FGA_VEL_PARTICLE && owner) {  // only with a single reference range
-    T* V = (T*)pd.V;
-    V[3 * i] = w0;
-    V[3 * i + 1] = w1;
-    V[3 * i + 2] = w2;
-  }
-  // a6: moments of the displacement d = dt v'
+  const Coef<T> cf = load_coef<T>(pd.st);
+  const vec4_t<T>* Q = (const vec4_t<T>*)pd.Q;
+  vec4_t<T> q[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) q[k] = Q[owner[k] ? idx[k] : 0];
   double mom[kMom];
-  if (PREC == FGA_PREC_FP32_ALL) {
-    const float d[3] = {(float)(dt * w0), (float)(dt * w1), (float)(dt * w2)};
-    const float qq[3] = {(float)q.x, (float)q.y, (float)q.z};
-    for (int a = 0; a < 3; ++a) mom[a] = owner ? (double)d[a] : 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = owner ? (double)(d[a] * qq[b]) : 0.0;
-  } else {
-    const double d[3] = {(double)(dt * w0), (double)(dt * w1), (double)(dt * w2)};
-    const double qq[3] = {(double)q.x, (double)q.y, (double)q.z};
-    for (int a = 0; a < 3; ++a) mom[a] = owner ? d[a] : 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] = owner ? d[a] * qq[b] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kMom; ++k) mom[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    // a5: damped velocity and displacement
+    T v0 = 0, v1 = 0, v2 = 0;
+    if (jr == 0 && owner[k]) {
+      if (c.velocity == FGA_VEL_RIGID) {
+        v0 = cf.A[0] * q[k].x + cf.A[1] * q[k].y + cf.A[2] * q[k].z + cf.b[0];
+        v1 = cf.A[3] * q[k].x + cf.A[4] * q[k].y + cf.A[5] * q[k].z + cf.b[1];
+        v2 = cf.A[6] * q[k].x + cf.A[7] * q[k].y + cf.A[8] * q[k].z + cf.b[2];
+      } else {
+        const T* V = (const T*)pd.V;
+        v0 = V[3 * idx[k]];
+        v1 = V[3 * idx[k] + 1];
+        v2 = V[3 * idx[k] + 2];
+      }
+    }
+    const T keep = (T)1 - q[k].w;  // 1 - c_i
+    const T w0 = keep * v0 + dt * (G * acc[k][0]);
+    const T w1 = keep * v1 + dt * (G * acc[k][1]);
+    const T w2 = keep * v2 + dt * (G * acc[k][2]);
+    if (c.velocity == FGA_VEL_PARTICLE && owner[k]) {  // only with a single reference range
+      T* V = (T*)pd.V;
+      V[3 * idx[k]] = w0;
+      V[3 * idx[k] + 1] = w1;
+      V[3 * idx[k] + 2] = w2;
+    }
+    // a6: moments of the displacement d = dt v'
+    if (!owner[k]) continue;
+    if (PREC == FGA_PREC_FP32_ALL) {
+      const float d[3] = {(float)(dt * w0), (float)(dt * w1), (float)(dt * w2)};
+      const float qq[3] = {(float)q[k].x, (float)q[k].y, (float)q[k].z};
+      for (int a = 0; a < 3; ++a) mom[a] = (double)((float)mom[a] + d[a]);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          mom[3 + 3 * a + b] = (double)((float)mom[3 + 3 * a + b] + d[a] * qq[b]);
+    } else {
+      const double d[3] = {(double)(dt * w0), (double)(dt * w1), (double)(dt * w2)};
+      const double qq[3] = {(double)q[k].x, (double)q[k].y, (double)q[k].z};
+      for (int a = 0; a < 3; ++a) mom[a] += d[a];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] += d[a] * qq[b];
+    }
   }
   block_sum<kMom>(mom, lds);
   if (BH) {  // interaction count of the block
@@ -181,12 +171,95 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   }
 }
 
+// One item of the fused iteration with one particle per S lanes (the direct
+// sum with S = 1, or the per-particle Barnes-Hut traversal).
+template <typename T, bool BH, int PREC, int S>
+__device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
+                               double* lds, StackEntry* stk) {
+  const RigidState* st = pd.st;
+  const int it = item / pd.jr, jr = item - (item / pd.jr) * pd.jr;
+  const int i = it * (kBlock / S) + (int)threadIdx.x / S;
+  const bool valid = i < pd.m;
+  const Coef<T> cf = load_coef<T>(st);
+  const vec4_t<T>* Q = (const vec4_t<T>*)pd.Q;
+  const vec4_t<T> q = Q[valid ? i : pd.m - 1];
+  const T y0 = cf.R[0] * q.x + cf.R[1] * q.y + cf.R[2] * q.z + cf.mu[0];
+  const T y1 = cf.R[3] * q.x + cf.R[4] * q.y + cf.R[5] * q.z + cf.mu[1];
+  const T y2 = cf.R[6] * q.x + cf.R[7] * q.y + cf.R[8] * q.z + cf.mu[2];
+  int j0, j1;
+  jrange(pd.n, pd.jr, jr, j0, j1);
+  T ax = 0, ay = 0, az = 0;
+  unsigned cnt = 0;
+  if (BH) {
+    bh_accum<T, S>(pd.nodes, (const vec4_t<T>*)pd.X, j0, j1, c.ftheta2, cEps2<T>(c), valid, y0,
+                   y1, y2, ax, ay, az, cnt, stk + (threadIdx.x / kWave) * kStack);
+  } else if constexpr (sizeof(T) == 8) {
+    direct_f64((const double4*)pd.X, j0, j1, y0, y1, y2, c.eps2, ax, ay, az);
+  } else {
+    if (PREC == FGA_PREC_FP32_KAHAN)
+      direct_f32<true, 64>((const float4*)pd.X, j0, j1, y0, y1, y2, c.feps2, ax, ay, az);
+    else
+      direct_f32<false, 64>((const float4*)pd.X, j0, j1, y0, y1, y2, c.feps2, ax, ay, az);
+  }
+  const int idx[1] = {i};
+  const bool owner[1] = {valid && (threadIdx.x & (S - 1)) == 0};
+  const T acc[1][3] = {{ax, ay, az}};
+  finish_item<T, BH, PREC, 1>(pd, c, item, jr, idx, owner, acc, cnt, lds);
+}
+
+// One item with the group traversal: every wave holds one group of at most
+// 64 K consecutive template particles (lane l, slot k: particle first + K l + k)
+// that share the walk of the tree. FP32 only.
+template <int PREC, int K>
+__device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int item,
+                                     double* lds, GroupLds* g) {
+  const int it = item / pd.jr, jr = item - (item / pd.jr) * pd.jr;
+  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
+  const float4* Q = (const float4*)pd.Q;
+  const int gi = it * (kBlock / kWave) + wave;  // this wave's group
+  int2 grp = make_int2(0, 0);
+  if (gi < pd.n_groups) grp = pd.groups[gi];
+  int idx[K];
+  bool valid[K];
+  float y[K][3], acc[K][3];
+  {
+    const RigidState* st = pd.st;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      valid[k] = K * lane + k < grp.y;
+      idx[k] = grp.x + K * lane + k;
+      const float4 q = Q[valid[k] ? idx[k] : pd.m - 1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        y[k][a] = st->fR[3 * a] * q.x + st->fR[3 * a + 1] * q.y + st->fR[3 * a + 2] * q.z + st->fmu[a];
+      acc[k][0] = acc[k][1] = acc[k][2] = 0.f;
+    }
+  }
+  int j0, j1;
+  jrange(pd.n, pd.jr, jr, j0, j1);
+  unsigned cnt = 0, entries = 0;
+  const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
+      pd.nodes, (const float4*)pd.X, j0, j1, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
+      g[wave]);
+  if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
+  if (pd.gcost && lane == 0 && gi < pd.n_groups) atomicAdd(&pd.gcost[gi], entries);
+  finish_item<float, true, PREC, K>(pd, c, item, jr, idx, valid, acc, cnt, lds);
+}
+
 template <typename T, bool BH, int PREC, int S>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_iteration(PairDev pd, IterConsts c) {
   __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
   __shared__ StackEntry stk[BH ? (kBlock / kWave) * kStack : 1];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
   iteration_item<T, BH, PREC, S>(pd, c, (int)blockIdx.x, lds, stk);
+}
+
+template <int PREC, int K>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_iteration_group(PairDev pd, IterConsts c) {
+  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ GroupLds g[kBlock / kWave];
+  if (pd.st->converged) return;  // uniform: the state was written by the previous launch
+  iteration_item_group<PREC, K>(pd, c, (int)blockIdx.x, lds, g);
 }
 
 // Persistent batched iteration: blocks pull (pair, item) entries from a work
@@ -228,7 +301,16 @@ template <typename T>
 fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s) {
   const bool bh = pd.nodes != nullptr;
   const dim3 grid((unsigned)pd.n_items);
-  if (sizeof(T) == 8) {
+  if (sizeof(T) == 4 && bh && pd.group > 0) {  // group traversal, K particles per lane
+    switch (c.prec * 4 + pd.group) {
+      case FGA_PREC_FP32 * 4 + 1: k_iteration_group<FGA_PREC_FP32, 1><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32 * 4 + 2: k_iteration_group<FGA_PREC_FP32, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_ALL * 4 + 1: k_iteration_group<FGA_PREC_FP32_ALL, 1><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_ALL * 4 + 2: k_iteration_group<FGA_PREC_FP32_ALL, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_KAHAN * 4 + 2: k_iteration_group<FGA_PREC_FP32_KAHAN, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
+      default: k_iteration_group<FGA_PREC_FP32_KAHAN, 1><<<grid, kBlock, 0, s>>>(pd, c);
+    }
+  } else if (sizeof(T) == 8) {
     if (bh) k_iteration<T, true, FGA_PREC_FP64, 1><<<grid, kBlock, 0, s>>>(pd, c);
     else k_iteration<T, false, FGA_PREC_FP64, 1><<<grid, kBlock, 0, s>>>(pd, c);
   } else {
@@ -360,6 +442,45 @@ __global__ __launch_bounds__(kBlock) void k_forces_bh(const T* Y, const int* yor
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(count, c);
 }
 
+// Group traversal for fga_forces: every wave takes 64 K consecutive template
+// particles of the Morton order yorder and writes F_i = G m_Y,i acc_i.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const int* yorder, int m,
+                                                         const BHWide* nodes, const float4* Xs,
+                                                         float theta2, float eps2, const float* mY,
+                                                         double G, float* F,
+                                                         unsigned long long* count) {
+  __shared__ GroupLds g[kBlock / kWave];
+  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
+  int idx[K];
+  bool valid[K];
+  float y[K][3], acc[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int pos = blockIdx.x * (kBlock * K) + wave * (kWave * K) + K * lane + k;
+    valid[k] = pos < m;
+    idx[k] = valid[k] ? yorder[pos] : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      y[k][a] = Y[3 * idx[k] + a];
+      acc[k][a] = 0.f;
+    }
+  }
+  unsigned cnt = 0, entries = 0;
+  const bool ok = bh_group<K, true>(nodes, Xs, 0, 0x7fffffff, theta2, eps2, valid, y, acc, cnt,
+                                    entries, g[wave]);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (valid[k]) {
+      const double w = G * (mY ? (double)mY[idx[k]] : 1.0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) F[3 * idx[k] + a] = ok ? (float)(w * (double)acc[k][a]) : __builtin_nanf("");
+    }
+  unsigned long long c = cnt;
+  for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if (lane == 0) atomicAdd(count, c);
+}
+
 }  // namespace
 
 // Number of reference ranges so that the launch has about 8 waves per SIMD.
@@ -420,10 +541,26 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
   unsigned long long* cnt = nullptr;
   FGA_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
   (void)hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
-  constexpr int tp = kBlock;
-  k_forces_bh<T><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
-      (const T*)Y, yorder, (int)m, nodes, n_nodes, (const vec4_t<T>*)Xs, (float)(theta * theta),
-      (T)(p.eps * p.eps), (const T*)mY, p.G, (T*)F, cnt);
+  const int K = sizeof(T) == 4 ? p.group_width / kWave : 0;  // 64 -> 1, 128 -> 2
+  if constexpr (sizeof(T) == 4) {
+    if (K == 1 || K == 2) {
+      const int tp = kBlock * K;
+      if (K == 1)
+        k_forces_group<1><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
+            (const float*)Y, yorder, (int)m, nodes, (const float4*)Xs, (float)(theta * theta),
+            (float)(p.eps * p.eps), (const float*)mY, p.G, (float*)F, cnt);
+      else
+        k_forces_group<2><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
+            (const float*)Y, yorder, (int)m, nodes, (const float4*)Xs, (float)(theta * theta),
+            (float)(p.eps * p.eps), (const float*)mY, p.G, (float*)F, cnt);
+    }
+  }
+  if (K != 1 && K != 2) {
+    constexpr int tp = kBlock;
+    k_forces_bh<T><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
+        (const T*)Y, yorder, (int)m, nodes, n_nodes, (const vec4_t<T>*)Xs, (float)(theta * theta),
+        (T)(p.eps * p.eps), (const T*)mY, p.G, (T*)F, cnt);
+  }
   unsigned long long h = 0;
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);

@@ -33,6 +33,7 @@ def test_default_params_are_the_papers():
     p = fga.default_params()
     assert (p.G, p.eps, p.eta, p.dt, p.theta) == (66.7, 0.2, 0.2, 0.1, 0.6)
     assert (p.a, p.b, p.rho, p.max_depth) == (-5.0, 5.0, 16, 20)
+    assert (p.group_width, p.leaf_size, p.tile) == (0, 1, 0)
     assert fga.version().startswith("fga-mi355x")
 
 
@@ -57,6 +58,7 @@ def call_forces(**over):
     (dict(p=fga.default_params(rho=0)), 1), (dict(p=fga.default_params(a=5.0, b=-5.0)), 1),
     (dict(p=fga.default_params(max_depth=12)), 6), (dict(p=fga.default_params(precision=9)), 1),
     (dict(p=fga.default_params(leaf_size=65)), 1), (dict(p=fga.default_params(leaf_size=-1)), 1),
+    (dict(p=fga.default_params(group_width=32)), 1), (dict(p=fga.default_params(group_width=-1)), 1),
     (dict(dt=0, p=fga.default_params(precision=2)), 1),
 ])
 def test_forces_argument_validation(over, code):
