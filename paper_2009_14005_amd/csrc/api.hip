@@ -829,12 +829,14 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
     if (gs != FGA_OK) return fail(gs);
     max_items = std::max(max_items, (size_t)tmp.n_items);
   }
-  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * max_items) != hipSuccess ||
-      hipMalloc((void**)&S->done, sizeof(unsigned)) != hipSuccess) {
+  const size_t max_chunks = (size_t)completion_chunks((int)max_items);
+  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * (max_items + max_chunks)) != hipSuccess ||
+      hipMalloc((void**)&S->done, sizeof(unsigned) * (1 + max_chunks)) != hipSuccess) {
     set_error("hipMalloc of the iteration buffers failed");
     return fail(FGA_E_NOMEM);
   }
-  if (hipMemsetAsync(S->done, 0, sizeof(unsigned), s) != hipSuccess) return fail(FGA_E_DEVICE);
+  if (hipMemsetAsync(S->done, 0, sizeof(unsigned) * (1 + max_chunks), s) != hipSuccess)
+    return fail(FGA_E_DEVICE);
   if (p->velocity == FGA_VEL_PARTICLE) {
     const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
     if (hipMalloc(&S->V, vb) != hipSuccess) {
@@ -1115,12 +1117,19 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pds[k].group = 0;
   }
   const int n_items = item_off[npairs];
+  // per pair: items + chunks partial rows, 1 + chunks completion counters
+  std::vector<size_t> poff(npairs + 1, 0), doff(npairs + 1, 0);
+  for (int k = 0; k < npairs; ++k) {
+    const int ch = completion_chunks(pds[k].n_items);
+    poff[k + 1] = poff[k] + (size_t)12 * (pds[k].n_items + ch);
+    doff[k + 1] = doff[k] + 1 + ch;
+  }
   double* partial;
   unsigned *done, *queue;
   PairDev* dpairs;
   int2* ditems;
-  FGA_TRY(B.get(&partial, sizeof(double) * 12 * n_items));
-  FGA_TRY(B.get(&done, sizeof(unsigned) * npairs));
+  FGA_TRY(B.get(&partial, sizeof(double) * poff[npairs]));
+  FGA_TRY(B.get(&done, sizeof(unsigned) * doff[npairs]));
   FGA_TRY(B.get(&queue, sizeof(unsigned) * 2));
   FGA_TRY(B.get(&dpairs, sizeof(PairDev) * npairs));
   FGA_TRY(B.get(&ditems, sizeof(int2) * n_items));
@@ -1131,8 +1140,8 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pd.nodes = nodes ? nodes + noff[k] : nullptr;
     pd.V = nullptr;
     pd.st = st + k;
-    pd.partial = partial + (size_t)12 * item_off[k];
-    pd.done = done + k;
+    pd.partial = partial + poff[k];
+    pd.done = done + doff[k];
     pd.n = (int)n[k];
     pd.m = (int)m[k];
     pd.n_nodes = nodes ? noff[k + 1] - noff[k] : 0;
@@ -1146,7 +1155,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     for (int e = 0; e < pds[k].n_items; ++e) items.push_back(make_int2(k, e));
   FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
-  FGA_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * npairs, s));
+  FGA_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * doff[npairs], s));
   FGA_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned) * 2, s));
   int dev = 0, cus = 256;
   FGA_HIP(hipGetDevice(&dev));

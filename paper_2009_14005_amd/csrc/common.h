@@ -108,6 +108,12 @@ struct alignas(16) BHWide {
 };
 constexpr int kChildShift = 29;
 
+// Completion of an iteration: items report to chunks of kChunk items, chunks
+// to the pair. A pair with n items needs (n + chunks) x 12 partial moments and
+// 1 + chunks counters (zero at rest).
+constexpr int kChunk = 64;
+inline int completion_chunks(int n_items) { return (n_items + kChunk - 1) / kChunk; }
+
 // Geometry of one registration pair on the device, for the iteration kernels.
 struct PairDev {
   const void* X;        // reference (x, y, z, mass) as vec4, normalised; Morton-sorted for BH
@@ -115,8 +121,8 @@ struct PairDev {
   const BHWide* nodes;  // BH nodes in child-block layout, or nullptr for the direct sum
   void* V;              // per-particle velocities (particle mode), m x 3 of T, else nullptr
   RigidState* st;
-  double* partial;      // n_items x 12 partial moments
-  unsigned* done;       // completion counter of the current iteration
+  double* partial;      // (n_items + chunks) x 12 partial moments
+  unsigned* done;       // completion counters: pair, then one per chunk of kChunk items
   int n, m;
   int n_nodes;
   int jr;               // reference ranges per template tile

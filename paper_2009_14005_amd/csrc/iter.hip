@@ -141,28 +141,49 @@ __device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, in
     block_sum<1>(cc, lds + kMom * (kBlock / kWave));
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&pd.st->interactions, (unsigned long long)cc[0]);
   }
+  // completion in two levels, each in a fixed order (deterministic): the
+  // last block of every chunk of kChunk items sums the chunk's partials, and
+  // the last chunk to finish sums the chunk partials and applies the rigid step
+  const int n_chunks = (pd.n_items + kChunk - 1) / kChunk;
+  const int chunk = item / kChunk;
   if (threadIdx.x == 0) {
     for (int k = 0; k < kMom; ++k)
       pd.partial[(size_t)item * kMom + k] =
           PREC == FGA_PREC_FP32_ALL ? (double)(float)mom[k] : mom[k];
     __threadfence();
-    const unsigned prev = atomicAdd(pd.done, 1u);
-    s_last = prev == (unsigned)(pd.n_items - 1);
+    const unsigned in_chunk = (unsigned)min(kChunk, pd.n_items - chunk * kChunk);
+    const unsigned prev = atomicAdd(pd.done + 1 + chunk, 1u);
+    s_last = prev == in_chunk - 1;
   }
   __syncthreads();
   if (!s_last) return;
-  // a7: this block finished the iteration; sum the items in fixed order
   __threadfence();
   double tot[kMom];
-  for (int k = 0; k < kMom; ++k) tot[k] = 0.0;
-  for (int e = (int)threadIdx.x; e < pd.n_items; e += kBlock) {
-    const volatile double* pp = pd.partial + (size_t)e * kMom;
-    for (int k = 0; k < kMom; ++k) {
-      if (PREC == FGA_PREC_FP32_ALL) tot[k] = (double)((float)tot[k] + (float)pp[k]);
-      else tot[k] += pp[k];
+  auto sum_rows = [&](const double* base, int r0, int r1) {
+    for (int k = 0; k < kMom; ++k) tot[k] = 0.0;
+    for (int e = r0 + (int)threadIdx.x; e < r1; e += kBlock) {
+      const volatile double* pp = base + (size_t)e * kMom;
+      for (int k = 0; k < kMom; ++k) {
+        if (PREC == FGA_PREC_FP32_ALL) tot[k] = (double)((float)tot[k] + (float)pp[k]);
+        else tot[k] += pp[k];
+      }
     }
+    block_sum<kMom>(tot, lds);
+  };
+  double* cpart = pd.partial + (size_t)pd.n_items * kMom;  // chunk partials
+  sum_rows(pd.partial, chunk * kChunk, min(pd.n_items, (chunk + 1) * kChunk));
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < kMom; ++k) cpart[(size_t)chunk * kMom + k] = tot[k];
+    pd.done[1 + chunk] = 0u;
+    __threadfence();
+    const unsigned prev = atomicAdd(pd.done, 1u);
+    s_last = prev == (unsigned)(n_chunks - 1);
   }
-  block_sum<kMom>(tot, lds);
+  __syncthreads();
+  if (!s_last) return;
+  // a7: this block finished the iteration
+  __threadfence();
+  sum_rows(cpart, 0, n_chunks);
   if (threadIdx.x == 0) {
     if (!BH) pd.st->interactions += (long long)pd.n * (long long)pd.m;
     rigid_update(*pd.st, tot, c.dt);
