@@ -283,9 +283,10 @@ struct fga_state {
   int tree_stats[3] = {0, 0, 0};
   std::vector<float> qhost;             // Morton-sorted template (x, y, z, c), group walk only
   struct Groups {
-    int2* dev = nullptr;
+    int2* dev = nullptr;                // (first, count) of every group, Morton order
     int n = 0;
-    bool ordered = false;               // sorted by measured cost, heaviest first
+    std::vector<unsigned> cost;         // measured list entries per group (empty: not yet)
+    std::map<int, std::pair<int2*, int>> items;  // range cap -> wave items, count
   };
   std::map<int, Groups> groups;         // key K * 4 + tau option
 };
@@ -309,7 +310,10 @@ static void state_free(fga_state* s) {
   if (s->partial) (void)hipFree(s->partial);
   if (s->done) (void)hipFree(s->done);
   if (s->V) (void)hipFree(s->V);
-  for (auto& kv : s->groups) (void)hipFree(kv.second.dev);
+  for (auto& kv : s->groups) {
+    (void)hipFree(kv.second.dev);
+    for (auto& it : kv.second.items) (void)hipFree(it.second.first);
+  }
   delete s;
 }
 
@@ -367,62 +371,61 @@ static void make_groups(const float* q4, int64_t m, int G, double f, std::vector
   }
 }
 
-// Orders a group table by cost, heaviest first: one iteration with the
-// table (one reference range) counts the list entries of every group, and the
-// state is restored afterwards. Blocks are dispatched in index order, so the
-// expensive groups start first and the cheap ones fill in behind them.
-static fga_status order_groups(fga_state* S, int K, fga_state::Groups& gt) {
+static fga_status upload_items(fga_state* S, const std::vector<int2>& v, int2** out) {
+  FGA_HIP(hipMalloc((void**)out, sizeof(int2) * std::max<size_t>(1, v.size())));
+  FGA_HIP(hipMemcpyAsync(*out, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  return FGA_OK;
+}
+
+// Measures the cost of every group: one iteration with one wave per group
+// over the whole reference counts the list entries of each group; the state
+// is restored afterwards.
+static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
   RigidState saved;
   FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
+  std::vector<int2> ident(gt.n);
+  for (int k = 0; k < gt.n; ++k) ident[k] = make_int2(k, 1 << 8);
+  int2* wi = nullptr;
+  FGA_TRY(upload_items(S, ident, &wi));
   unsigned* cost = nullptr;
-  FGA_HIP(hipMalloc((void**)&cost, sizeof(unsigned) * gt.n));
-  std::vector<unsigned> hc(gt.n);
-  std::vector<int2> g(gt.n);
+  if (hipMalloc((void**)&cost, sizeof(unsigned) * gt.n) != hipSuccess) {
+    (void)hipFree(wi);
+    set_error("hipMalloc failed");
+    return FGA_E_NOMEM;
+  }
   PairDev pd = S->pd;
   pd.group = K;
   pd.slots = 1;
   pd.tile = kBlock * K;
   pd.groups = gt.dev;
+  pd.witems = wi;
   pd.n_groups = gt.n;
+  pd.n_witems = gt.n;
   pd.gcost = cost;
   pd.jr = 1;
   pd.n_items = (gt.n + kBlock / kWave - 1) / (kBlock / kWave);
+  gt.cost.assign(gt.n, 0u);
   fga_status st = FGA_OK;
   if (hipMemsetAsync(cost, 0, sizeof(unsigned) * gt.n, S->s) != hipSuccess) st = FGA_E_DEVICE;
   if (st == FGA_OK) st = launch_iteration<float>(pd, S->c, S->s);
   if (st == FGA_OK &&
-      (hipMemcpyAsync(hc.data(), cost, sizeof(unsigned) * gt.n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
-       hipMemcpyAsync(g.data(), gt.dev, sizeof(int2) * gt.n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
+      (hipMemcpyAsync(gt.cost.data(), cost, sizeof(unsigned) * gt.n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
        hipMemcpyAsync(S->st, &saved, sizeof saved, hipMemcpyHostToDevice, S->s) != hipSuccess ||
        hipStreamSynchronize(S->s) != hipSuccess))
     st = FGA_E_DEVICE;
   (void)hipFree(cost);
+  (void)hipFree(wi);
   if (st != FGA_OK) {
+    gt.cost.clear();
     if (st == FGA_E_DEVICE) set_error("group cost measurement failed");
-    return st;
   }
-  // heaviest first (cutting heavy groups into smaller runs was measured to
-  // lose more to the per-wave overhead of the extra waves than it gained)
-  std::vector<std::pair<double, int2>> parts;
-  for (int k = 0; k < gt.n; ++k) parts.push_back({(double)hc[k], g[k]});
-  std::stable_sort(parts.begin(), parts.end(),
-                   [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
-                     return x.first > y.first;
-                   });
-  std::vector<int2> sorted(parts.size());
-  for (size_t k = 0; k < parts.size(); ++k) sorted[k] = parts[k].second;
-  gt.n = (int)sorted.size();
-  FGA_HIP(hipMemcpyAsync(gt.dev, sorted.data(), sizeof(int2) * gt.n, hipMemcpyHostToDevice, S->s));
-  FGA_HIP(hipStreamSynchronize(S->s));
-  gt.ordered = true;
-  return FGA_OK;
+  return st;
 }
 
-// Device groups of a state for (K, tau option), built on first use and, once
-// the state can iterate (`order`), sorted by cost.
-static fga_status ensure_groups(fga_state* S, int K, int fi, bool order, const int2** dev,
-                                int* count) {
+// Device groups of a state for (K, tau option), built on first use.
+static fga_status ensure_groups(fga_state* S, int K, int fi, fga_state::Groups** out) {
   const int key = K * 4 + fi;
   auto it = S->groups.find(key);
   if (it == S->groups.end()) {
@@ -434,34 +437,79 @@ static fga_status ensure_groups(fga_state* S, int K, int fi, bool order, const i
     std::vector<int2> g;
     make_groups(S->qhost.data(), S->m, kWave * K, kGroupTau[fi], g);
     fga_state::Groups gt;
-    FGA_HIP(hipMalloc((void**)&gt.dev, sizeof(int2) * g.size()));
+    FGA_TRY(upload_items(S, g, &gt.dev));
     gt.n = (int)g.size();
-    it = S->groups.emplace(key, gt).first;
-    FGA_HIP(hipMemcpyAsync(gt.dev, g.data(), sizeof(int2) * g.size(), hipMemcpyHostToDevice, S->s));
-    FGA_HIP(hipStreamSynchronize(S->s));
+    it = S->groups.emplace(key, std::move(gt)).first;
   }
-  if (order && !it->second.ordered) FGA_TRY(order_groups(S, K, it->second));
-  *dev = it->second.dev;
-  *count = it->second.n;
+  *out = &it->second;
   return FGA_OK;
 }
 
-// Applies a work split (mode << 8 | reference ranges) to a pair's launch
-// geometry. mode: lanes per particle of the per-particle walk (1, 2, 4, 8), or
-// 16 + K + 4 fi for the group walk with K particles per lane and groups bounded
-// by kGroupTau[fi].
-static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool order = true) {
+// Wave items of a group table for a cap on the ranges per group: a group
+// whose measured cost is above the target (the larger of twice the median
+// and the total over 4096 waves) is split over nr = 2, 4, ... <= cap
+// reference ranges; items are ordered by estimated cost, heaviest first, so
+// that the expensive waves start first and the cheap ones fill in behind them.
+static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap,
+                             const int2** dev, int* count) {
+  auto it = gt.items.find(cap);
+  if (it == gt.items.end()) {
+    if (gt.cost.empty()) FGA_TRY(measure_groups(S, K, gt));
+    std::vector<double> cs(gt.cost.begin(), gt.cost.end());
+    double total = 0.0;
+    for (double c : cs) total += c;
+    std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
+    const double target = std::max(2.0 * cs[cs.size() / 2], total / 4096.0);
+    std::vector<std::pair<double, int2>> items;
+    for (int g = 0; g < gt.n; ++g) {
+      int nr = 1;
+      while (nr < cap && gt.cost[g] > target * nr) nr *= 2;
+      for (int r = 0; r < nr; ++r)
+        items.push_back({(double)gt.cost[g] / nr, make_int2(g, r | nr << 8)});
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
+                       return x.first > y.first;
+                     });
+    std::vector<int2> v(items.size());
+    for (size_t k = 0; k < items.size(); ++k) v[k] = items[k].second;
+    int2* d = nullptr;
+    FGA_TRY(upload_items(S, v, &d));
+    it = gt.items.emplace(cap, std::make_pair(d, (int)v.size())).first;
+  }
+  *dev = it->second.first;
+  *count = it->second.second;
+  return FGA_OK;
+}
+
+// Applies a work split (mode << 8 | ranges) to a pair's launch geometry.
+// mode: lanes per particle of the per-particle walk (1, 2, 4, 8), with
+// `ranges` reference ranges per tile; or 16 + K + 4 fi for the group walk with
+// K particles per lane, groups bounded by kGroupTau[fi] and at most `ranges`
+// reference ranges per group. With `build` false only the launch size (an
+// upper bound for the group walk) is set.
+static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = true) {
   const int mode = code >> 8;
   pd.jr = code & 255;
   pd.groups = nullptr;
+  pd.witems = nullptr;
   pd.gcost = nullptr;
   pd.n_groups = 0;
+  pd.n_witems = 0;
   if (mode >= 16) {
     pd.group = (mode - 16) & 3;
     pd.slots = 1;
     pd.tile = kBlock * pd.group;
-    FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, order, &pd.groups, &pd.n_groups));
-    pd.n_items = ((pd.n_groups + kBlock / kWave - 1) / (kBlock / kWave)) * pd.jr;
+    fga_state::Groups* gt = nullptr;
+    FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, &gt));
+    pd.groups = gt->dev;
+    pd.n_groups = gt->n;
+    if (build) {
+      FGA_TRY(wave_items(S, pd.group, *gt, pd.jr, &pd.witems, &pd.n_witems));
+    } else {
+      pd.n_witems = gt->n * pd.jr;
+    }
+    pd.n_items = (pd.n_witems + kBlock / kWave - 1) / (kBlock / kWave);
   } else {
     pd.group = 0;
     pd.slots = mode;

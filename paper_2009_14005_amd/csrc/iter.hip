@@ -228,18 +228,25 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   finish_item<T, BH, PREC, 1>(pd, c, item, jr, idx, owner, acc, cnt, lds);
 }
 
-// One item with the group traversal: every wave holds one group of at most
-// 64 K consecutive template particles (lane l, slot k: particle first + K l + k)
-// that share the walk of the tree. FP32 only.
+// One block of the group traversal: every wave takes one wave item, a group of
+// at most 64 K consecutive template particles (lane l, slot k: particle
+// first + K l + k) sharing one walk of the tree, restricted to reference range
+// r of nr (heavy groups are split over several ranges, hence several waves).
+// FP32 only.
 template <int PREC, int K>
 __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int item,
                                      double* lds, GroupLds* g) {
-  const int it = item / pd.jr, jr = item - (item / pd.jr) * pd.jr;
   const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
   const float4* Q = (const float4*)pd.Q;
-  const int gi = it * (kBlock / kWave) + wave;  // this wave's group
-  int2 grp = make_int2(0, 0);
-  if (gi < pd.n_groups) grp = pd.groups[gi];
+  const int wi = item * (kBlock / kWave) + wave;
+  int gi = -1, r = 0, nr = 1;
+  if (wi < pd.n_witems) {
+    const int2 w = pd.witems[wi];
+    gi = w.x;
+    r = w.y & 255;
+    nr = w.y >> 8;
+  }
+  const int2 grp = gi >= 0 ? pd.groups[gi] : make_int2(0, 0);
   int idx[K];
   bool valid[K];
   float y[K][3], acc[K][3];
@@ -257,14 +264,14 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
     }
   }
   int j0, j1;
-  jrange(pd.n, pd.jr, jr, j0, j1);
+  jrange(pd.n, nr, r, j0, j1);
   unsigned cnt = 0, entries = 0;
   const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
       pd.nodes, (const float4*)pd.X, j0, j1, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
       g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
-  if (pd.gcost && lane == 0 && gi < pd.n_groups) atomicAdd(&pd.gcost[gi], entries);
-  finish_item<float, true, PREC, K>(pd, c, item, jr, idx, valid, acc, cnt, lds);
+  if (pd.gcost && lane == 0 && gi >= 0) atomicAdd(&pd.gcost[gi], entries);
+  finish_item<float, true, PREC, K>(pd, c, item, r, idx, valid, acc, cnt, lds);
 }
 
 template <typename T, bool BH, int PREC, int S>
