@@ -283,10 +283,10 @@ struct fga_state {
   int tree_stats[3] = {0, 0, 0};
   std::vector<float> qhost;             // Morton-sorted template (x, y, z, c), group walk only
   struct Groups {
-    int2* dev = nullptr;                // (first, count) of every group, Morton order
+    std::vector<int2> host;             // (first, count) of every group, Morton order
     int n = 0;
     std::vector<unsigned> cost;         // measured list entries per group (empty: not yet)
-    std::map<int, std::pair<int2*, int>> items;  // range cap -> wave items, count
+    std::map<int, std::pair<int4*, int>> items;  // range cap -> wave items, count
   };
   std::map<int, Groups> groups;         // key K * 4 + tau option
 };
@@ -310,10 +310,8 @@ static void state_free(fga_state* s) {
   if (s->partial) (void)hipFree(s->partial);
   if (s->done) (void)hipFree(s->done);
   if (s->V) (void)hipFree(s->V);
-  for (auto& kv : s->groups) {
-    (void)hipFree(kv.second.dev);
+  for (auto& kv : s->groups)
     for (auto& it : kv.second.items) (void)hipFree(it.second.first);
-  }
   delete s;
 }
 
@@ -371,9 +369,9 @@ static void make_groups(const float* q4, int64_t m, int G, double f, std::vector
   }
 }
 
-static fga_status upload_items(fga_state* S, const std::vector<int2>& v, int2** out) {
-  FGA_HIP(hipMalloc((void**)out, sizeof(int2) * std::max<size_t>(1, v.size())));
-  FGA_HIP(hipMemcpyAsync(*out, v.data(), sizeof(int2) * v.size(), hipMemcpyHostToDevice, S->s));
+static fga_status upload_items(fga_state* S, const std::vector<int4>& v, int4** out) {
+  FGA_HIP(hipMalloc((void**)out, sizeof(int4) * std::max<size_t>(1, v.size())));
+  FGA_HIP(hipMemcpyAsync(*out, v.data(), sizeof(int4) * v.size(), hipMemcpyHostToDevice, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
   return FGA_OK;
 }
@@ -385,9 +383,9 @@ static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
   RigidState saved;
   FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
-  std::vector<int2> ident(gt.n);
-  for (int k = 0; k < gt.n; ++k) ident[k] = make_int2(k, 1 << 8);
-  int2* wi = nullptr;
+  std::vector<int4> ident(gt.n);
+  for (int k = 0; k < gt.n; ++k) ident[k] = make_int4(gt.host[k].x, gt.host[k].y, 1 << 8, k);
+  int4* wi = nullptr;
   FGA_TRY(upload_items(S, ident, &wi));
   unsigned* cost = nullptr;
   if (hipMalloc((void**)&cost, sizeof(unsigned) * gt.n) != hipSuccess) {
@@ -399,7 +397,6 @@ static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
   pd.group = K;
   pd.slots = 1;
   pd.tile = kBlock * K;
-  pd.groups = gt.dev;
   pd.witems = wi;
   pd.n_groups = gt.n;
   pd.n_witems = gt.n;
@@ -434,24 +431,22 @@ static fga_status ensure_groups(fga_state* S, int K, int fi, fga_state::Groups**
       FGA_HIP(hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * S->m, hipMemcpyDeviceToHost, S->s));
       FGA_HIP(hipStreamSynchronize(S->s));
     }
-    std::vector<int2> g;
-    make_groups(S->qhost.data(), S->m, kWave * K, kGroupTau[fi], g);
     fga_state::Groups gt;
-    FGA_TRY(upload_items(S, g, &gt.dev));
-    gt.n = (int)g.size();
+    make_groups(S->qhost.data(), S->m, kWave * K, kGroupTau[fi], gt.host);
+    gt.n = (int)gt.host.size();
     it = S->groups.emplace(key, std::move(gt)).first;
   }
   *out = &it->second;
   return FGA_OK;
 }
 
-// Wave items of a group table for a cap on the ranges per group: a group
-// whose measured cost is above the target (the larger of twice the median
-// and the total over 4096 waves) is split over nr = 2, 4, ... <= cap
-// reference ranges; items are ordered by estimated cost, heaviest first, so
-// that the expensive waves start first and the cheap ones fill in behind them.
+// Wave items of a group table for a cap on the parts per group: a group
+// whose measured cost is above the target (the larger of twice the median and
+// the total over 8192 waves) is split over nr = 2, 4, ... <= cap waves by
+// subtrees. Items are ordered by estimated cost, heaviest first, so that the
+// expensive waves start first and the cheap ones fill in behind them.
 static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap,
-                             const int2** dev, int* count) {
+                             const int4** dev, int* count) {
   auto it = gt.items.find(cap);
   if (it == gt.items.end()) {
     if (gt.cost.empty()) FGA_TRY(measure_groups(S, K, gt));
@@ -459,21 +454,22 @@ static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap
     double total = 0.0;
     for (double c : cs) total += c;
     std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
-    const double target = std::max(2.0 * cs[cs.size() / 2], total / 4096.0);
-    std::vector<std::pair<double, int2>> items;
+    const double target = std::max(2.0 * cs[cs.size() / 2], total / 8192.0);
+    std::vector<std::pair<double, int4>> items;
     for (int g = 0; g < gt.n; ++g) {
+      const int2 grp = gt.host[g];
       int nr = 1;
       while (nr < cap && gt.cost[g] > target * nr) nr *= 2;
       for (int r = 0; r < nr; ++r)
-        items.push_back({(double)gt.cost[g] / nr, make_int2(g, r | nr << 8)});
+        items.push_back({(double)gt.cost[g] / nr, make_int4(grp.x, grp.y, r | nr << 8, g)});
     }
     std::stable_sort(items.begin(), items.end(),
-                     [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
+                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
                        return x.first > y.first;
                      });
-    std::vector<int2> v(items.size());
+    std::vector<int4> v(items.size());
     for (size_t k = 0; k < items.size(); ++k) v[k] = items[k].second;
-    int2* d = nullptr;
+    int4* d = nullptr;
     FGA_TRY(upload_items(S, v, &d));
     it = gt.items.emplace(cap, std::make_pair(d, (int)v.size())).first;
   }
@@ -491,7 +487,6 @@ static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap
 static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = true) {
   const int mode = code >> 8;
   pd.jr = code & 255;
-  pd.groups = nullptr;
   pd.witems = nullptr;
   pd.gcost = nullptr;
   pd.n_groups = 0;
@@ -502,12 +497,11 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
     pd.tile = kBlock * pd.group;
     fga_state::Groups* gt = nullptr;
     FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, &gt));
-    pd.groups = gt->dev;
     pd.n_groups = gt->n;
     if (build) {
       FGA_TRY(wave_items(S, pd.group, *gt, pd.jr, &pd.witems, &pd.n_witems));
     } else {
-      pd.n_witems = gt->n * pd.jr;
+      pd.n_witems = gt->n * pd.jr;  // at most `jr` parts per group
     }
     pd.n_items = (pd.n_witems + kBlock / kWave - 1) / (kBlock / kWave);
   } else {

@@ -246,7 +246,7 @@ __device__ inline void bh_accum(const BHWide* __restrict__ nodes,
 //   - sum: whenever the list is nearly full, every lane evaluates its K
 //     particles against the whole list (one broadcast LDS read per entry and
 //     K Eq. (GAForce) terms), as in the direct sum.
-// Reference ranges [j0, j1) split the walk as in the per-particle traversal.
+// A heavy group's walk can be split over several waves by subtrees.
 constexpr int kGList = 128;   // interaction-list entries per wave
 constexpr int kGStack = 512;  // child-block entries per wave
 // Stack entries kept free for a depth-first descent: every level of the tree
@@ -350,10 +350,20 @@ __device__ inline float group_box(const bool (&valid)[K], const float (&y)[K][3]
   return d2;
 }
 
-// The walk for a group: the particles of the lanes with `sel`.
+// Work split of one group's walk over nr waves (part r): nodes of more than
+// kSplitPts points are walked by every part, and their accepted terms and leaf
+// points belong to part 0; a node of at most kSplitPts points whose parent is
+// larger (a frontier node) belongs, with its whole subtree, to part
+// (index mod nr). The parts' sums add up to the group's sum, and the many
+// small subtrees around a dense region spread evenly over the parts.
+constexpr int kSplitPts = 32;
+constexpr int kLargeParent = 1 << 28;  // stack entry flag: the block's parent is shared
+constexpr int kIndexMask = kLargeParent - 1;
+
+// The walk for a group: the particles of the lanes with `sel`, part r of nr.
 template <int K, bool KAHAN>
 __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
-                                  int j0, int j1, float theta2, float eps2, bool sel,
+                                  int r, int nr, float theta2, float eps2, bool sel,
                                   int nvalid, const float (&lo)[3], const float (&hi)[3],
                                   const float (&y)[K][3], float (&acc)[K][3],
                                   float (&cmp)[K][3], unsigned& count, unsigned& entries,
@@ -362,7 +372,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
   bool ok = true;
   int cnt = 0;  // list entries
   int sp = 1;   // stack entries; the root is a block of one node at index 0
-  if (lane == 0) g.stk[0] = 0;
+  if (lane == 0) g.stk[0] = kLargeParent;
   auto flush = [&]() {
     group_sum<K, KAHAN>(g.list, cnt, y, eps2, sel, acc, cmp);
     count += sel ? (unsigned)(cnt * nvalid) : 0u;
@@ -388,10 +398,13 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
     const int e = wave_owner(lane < E ? incl : 0x7fffffff, lane);
     const int che = __shfl(ch, e, kWave), ince = __shfl(incl, e, kWave);
     const bool act = lane < T;
-    const int node = (che & ((1 << kChildShift) - 1)) + lane -
+    const int node = (che & kIndexMask) + lane -
                      (ince - ((int)((unsigned)che >> kChildShift) + 1));
     const BHWide nd = nodes[act ? node : 0];
-    const bool on = act && nd.first < j1 && nd.last >= j0;
+    const bool shared = nd.last - nd.first + 1 > kSplitPts;
+    const bool frontier = !shared && (che & kLargeParent);
+    const bool on = act && (!frontier || node % nr == r);
+    const bool mine = !shared || r == 0;  // owns the node's own term or points
     const bool leaf = nd.child == -1;
     const bool twig = __float_as_uint(nd.l2) >> 31;
     float d2 = 0.f;
@@ -404,15 +417,15 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
       }
     }
     const bool accept = on && ((leaf && nd.first == nd.last) || fabsf(nd.l2) < theta2 * d2);
-    const bool own = accept && nd.first >= j0;
-    const bool pts = on && !accept && (leaf || twig);
+    const bool own = accept && mine;
+    const bool pts = on && !accept && (leaf || twig) && mine;
     const bool inner = on && !accept && !leaf && !twig;
     // push the child blocks of the opened internal nodes
     const unsigned long long im = __ballot(inner);
     if (inner) {
       const int pos = sp + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(im >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((unsigned)im, 0u));
-      if (pos < kGStack) g.stk[pos] = nd.child;
+      if (pos < kGStack) g.stk[pos] = nd.child | (shared ? kLargeParent : 0);
     }
     sp += __popcll(im);
     if (sp > kGStack) {
@@ -428,8 +441,8 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
     }
     cnt += __popcll(om);
     // append the points of opened leaves and twigs, 64 at a time
-    const int p0 = max(nd.first, j0);
-    const int np = pts ? min(nd.last, j1 - 1) - p0 + 1 : 0;
+    const int p0 = nd.first;
+    const int np = pts ? nd.last - p0 + 1 : 0;
     if (__ballot(np > 0) != 0ull) {
       const int pincl = wave_incl_scan(np);
       const int P = __shfl(pincl, kWave - 1, kWave);
@@ -449,13 +462,14 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
   return ok;
 }
 
-// Lane l holds particles K l .. K l + K - 1 of the wave's group; `entries`
+// Lane l holds particles K l .. K l + K - 1 of the wave's group, walked as
+// part r of nr (see kSplitPts); `entries`
 // (uniform) receives the number of list entries evaluated. Returns false if
 // the stack overflowed (never for trees of depth at most kQBits + 1;
 // the sum is then incomplete).
 template <int K, bool KAHAN>
 __device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
-                                int j0, int j1, float theta2, float eps2, const bool (&valid)[K],
+                                int r, int nr, float theta2, float eps2, const bool (&valid)[K],
                                 const float (&y)[K][3], float (&acc)[K][3], unsigned& count,
                                 unsigned& entries, GroupLds& g) {
   int nvalid = 0;
@@ -469,7 +483,7 @@ __device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* 
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int a = 0; a < 3; ++a) cmp[k][a] = 0.f;
-  return group_walk<K, KAHAN>(nodes, X, j0, j1, theta2, eps2, true, nvalid, lo, hi, y, acc, cmp,
+  return group_walk<K, KAHAN>(nodes, X, r, nr, theta2, eps2, true, nvalid, lo, hi, y, acc, cmp,
                               count, entries, g);
 }
 

@@ -228,10 +228,11 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
   finish_item<T, BH, PREC, 1>(pd, c, item, jr, idx, owner, acc, cnt, lds);
 }
 
-// One block of the group traversal: every wave takes one wave item, a group of
+// One block of the group traversal: every wave takes one wave item, a run of
 // at most 64 K consecutive template particles (lane l, slot k: particle
-// first + K l + k) sharing one walk of the tree, restricted to reference range
-// r of nr (heavy groups are split over several ranges, hence several waves).
+// first + K l + k) sharing one walk of the tree, restricted to
+// part r of nr of the walk (heavy groups are split over several waves by
+// subtrees).
 // FP32 only.
 template <int PREC, int K>
 __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int item,
@@ -240,13 +241,14 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
   const float4* Q = (const float4*)pd.Q;
   const int wi = item * (kBlock / kWave) + wave;
   int gi = -1, r = 0, nr = 1;
+  int2 grp = make_int2(0, 0);
   if (wi < pd.n_witems) {
-    const int2 w = pd.witems[wi];
-    gi = w.x;
-    r = w.y & 255;
-    nr = w.y >> 8;
+    const int4 w = pd.witems[wi];
+    grp = make_int2(w.x, w.y);
+    r = w.z & 255;
+    nr = w.z >> 8;
+    gi = w.w;
   }
-  const int2 grp = gi >= 0 ? pd.groups[gi] : make_int2(0, 0);
   int idx[K];
   bool valid[K];
   float y[K][3], acc[K][3];
@@ -263,11 +265,9 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
       acc[k][0] = acc[k][1] = acc[k][2] = 0.f;
     }
   }
-  int j0, j1;
-  jrange(pd.n, nr, r, j0, j1);
   unsigned cnt = 0, entries = 0;
   const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
-      pd.nodes, (const float4*)pd.X, j0, j1, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
+      pd.nodes, (const float4*)pd.X, r, nr, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
       g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
   if (pd.gcost && lane == 0 && gi >= 0) atomicAdd(&pd.gcost[gi], entries);
@@ -495,8 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, true>(nodes, Xs, 0, 0x7fffffff, theta2, eps2, valid, y, acc, cnt,
-                                    entries, g[wave]);
+  const bool ok = bh_group<K, true>(nodes, Xs, 0, 1, theta2, eps2, valid, y, acc, cnt, entries,
+                                    g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (valid[k]) {
