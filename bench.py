@@ -158,7 +158,7 @@ def measured_traffic():
     FETCH_SIZE / WRITE_SIZE summary, scaled by the calibration kernel; None
     when the kernel sources have changed since those counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "bh_iteration_lidar65536_traffic.json")
+    path = os.path.join(ROOT, "profiles", "bh_group_iteration_lidar65536_traffic.json")
     try:
         rec = json.load(open(path))
         h = hashlib.sha256()
