@@ -183,9 +183,14 @@ fga_status fga_register(const void* X, int64_t n, const void* Y, int64_t m, fga_
 
 /* npairs independent registrations run together: one set of launches builds
  * every pair's tree, and every iteration is one persistent launch over a work
- * queue of (pair, template tile, reference range) items, replayed from a HIP
- * graph. X[k], Y[k] are device arrays of n[k] x 3 and m[k] x 3 points.
- * R: npairs x 9, t: npairs x 3, reps: npairs (may be NULL), host memory. */
+ * queue replayed from a HIP graph. With FP32 Barnes-Hut (and group_width != 1)
+ * the queue holds blocks of the group walk (one particle per lane, groups
+ * bounded by twice the median box, heavy groups split over several waves by
+ * the cost one measuring iteration finds, heaviest first); otherwise (pair,
+ * template tile, reference range) items of the per-particle walk or the direct
+ * sum. Each pair stops by the Alg. 2 rule on its own. X[k], Y[k] are device
+ * arrays of n[k] x 3 and m[k] x 3 points. R: npairs x 9, t: npairs x 3, reps:
+ * npairs (may be NULL), host memory. */
 fga_status fga_register_batch(int npairs, const void* const* X, const int64_t* n,
                               const void* const* Y, const int64_t* m, fga_dtype dt,
                               const fga_params* p, double* R, double* t, fga_report* reps,

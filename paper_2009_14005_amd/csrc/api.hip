@@ -1143,38 +1143,72 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     FGA_TRY(relayout_wide(pre, noff[npairs], npairs, noff.data(), &nodes, s));
     B.ptrs.push_back(nodes);
   }
-  // work items: template tiles of every pair, largest reference first
-  const bool big = NY >= 262144;
+  int dev = 0, cus = 256;
+  FGA_HIP(hipGetDevice(&dev));
+  FGA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const IterConsts c = make_iter_consts(p);
+  // the group walk (FP32 Barnes-Hut unless group_width = 1) with one particle
+  // per lane: groups bounded by twice the median box of fixed 64-runs, split
+  // by measured cost
+  const bool grouped = sizeof(T) == 4 && p.theta > 0 && p.group_width != 1;
   std::vector<PairDev> pds(npairs);
+  std::vector<std::vector<int2>> groups(npairs);
+  std::vector<int> goff(npairs + 1, 0);
+  if (grouped) {
+    std::vector<float> qh((size_t)NY * 4);
+    FGA_HIP(hipMemcpyAsync(qh.data(), Qp, sizeof(float) * 4 * NY, hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < npairs; ++k) {
+      make_groups(qh.data() + 4 * yoff[k], m[k], kWave, kGroupTau[2], groups[k]);
+      goff[k + 1] = goff[k] + (int)groups[k].size();
+    }
+  }
+  const int kCap = 16;  // parts per group in the group walk
   std::vector<int> item_off(npairs + 1, 0);
   for (int k = 0; k < npairs; ++k) {
-    int jr = big ? 1 : (p.theta > 0 ? bh_ranges(m[k], n[k]) : direct_ranges(m[k], n[k]));
-    const int tp = kBlock;
-    const int tiles = (int)((m[k] + tp - 1) / tp);
-    item_off[k + 1] = item_off[k] + tiles * jr;
-    pds[k].jr = jr;
-    pds[k].n_items = tiles * jr;
-    pds[k].tile = tp;
-    pds[k].slots = 1;
-    pds[k].group = 0;
+    if (grouped) {
+      // capacity for up to kCap wave items per group
+      const int nwi = (int)groups[k].size() * kCap;
+      pds[k].n_items = (nwi + kBlock / kWave - 1) / (kBlock / kWave);
+      pds[k].jr = 1;
+      pds[k].tile = kBlock;
+      pds[k].slots = 1;
+      pds[k].group = 1;
+    } else {
+      const bool big = NY >= 262144;
+      int jr = big ? 1 : (p.theta > 0 ? bh_ranges(m[k], n[k]) : direct_ranges(m[k], n[k]));
+      const int tiles = (int)((m[k] + kBlock - 1) / kBlock);
+      pds[k].jr = jr;
+      pds[k].n_items = tiles * jr;
+      pds[k].tile = kBlock;
+      pds[k].slots = 1;
+      pds[k].group = 0;
+    }
+    item_off[k + 1] = item_off[k] + pds[k].n_items;
   }
-  const int n_items = item_off[npairs];
   // per pair: items + chunks partial rows, 1 + chunks completion counters
+  // (sized for the largest item count the pair can have)
   std::vector<size_t> poff(npairs + 1, 0), doff(npairs + 1, 0);
   for (int k = 0; k < npairs; ++k) {
     const int ch = completion_chunks(pds[k].n_items);
     poff[k + 1] = poff[k] + (size_t)12 * (pds[k].n_items + ch);
     doff[k + 1] = doff[k] + 1 + ch;
   }
+  const int max_queue = item_off[npairs];
   double* partial;
-  unsigned *done, *queue;
+  unsigned *done, *queue, *gcost = nullptr;
   PairDev* dpairs;
   int2* ditems;
+  int4* dwitems = nullptr;
   FGA_TRY(B.get(&partial, sizeof(double) * poff[npairs]));
   FGA_TRY(B.get(&done, sizeof(unsigned) * doff[npairs]));
   FGA_TRY(B.get(&queue, sizeof(unsigned) * 2));
   FGA_TRY(B.get(&dpairs, sizeof(PairDev) * npairs));
-  FGA_TRY(B.get(&ditems, sizeof(int2) * n_items));
+  FGA_TRY(B.get(&ditems, sizeof(int2) * max_queue));
+  if (grouped) {
+    FGA_TRY(B.get(&dwitems, sizeof(int4) * (size_t)goff[npairs] * kCap));
+    FGA_TRY(B.get(&gcost, sizeof(unsigned) * goff[npairs]));
+  }
   for (int k = 0; k < npairs; ++k) {
     PairDev& pd = pds[k];
     pd.X = Xp + xoff[k];
@@ -1187,30 +1221,95 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pd.n = (int)n[k];
     pd.m = (int)m[k];
     pd.n_nodes = nodes ? noff[k + 1] - noff[k] : 0;
+    pd.witems = dwitems ? dwitems + (size_t)goff[k] * kCap : nullptr;
+    pd.gcost = nullptr;
+    pd.n_groups = goff[k + 1] - goff[k];
+    pd.n_witems = 0;
   }
-  std::vector<int> order(npairs);
-  for (int k = 0; k < npairs; ++k) order[k] = k;
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
-  std::vector<int2> items;
-  items.reserve(n_items);
-  for (int k : order)
-    for (int e = 0; e < pds[k].n_items; ++e) items.push_back(make_int2(k, e));
-  FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
-  FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * doff[npairs], s));
   FGA_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned) * 2, s));
-  int dev = 0, cus = 256;
-  FGA_HIP(hipGetDevice(&dev));
-  FGA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  std::vector<int2> items;
+  if (grouped) {
+    // one iteration with one wave per group measures every group's cost; the
+    // rigid states are restored afterwards
+    std::vector<RigidState> saved(npairs);
+    FGA_HIP(hipMemcpyAsync(saved.data(), st, sizeof(RigidState) * npairs, hipMemcpyDeviceToHost, s));
+    std::vector<int4> wi((size_t)goff[npairs] * kCap);
+    std::vector<std::pair<double, int2>> blocks;
+    for (int k = 0; k < npairs; ++k) {
+      for (int g = 0; g < (int)groups[k].size(); ++g)
+        wi[(size_t)goff[k] * kCap + g] = make_int4(groups[k][g].x, groups[k][g].y, 1 << 8, goff[k] + g);
+      pds[k].n_witems = (int)groups[k].size();
+      pds[k].gcost = gcost;
+      const int nb = (pds[k].n_witems + kBlock / kWave - 1) / (kBlock / kWave);
+      pds[k].n_items = nb;
+      for (int b = 0; b < nb; ++b) items.push_back(make_int2(k, b));
+    }
+    FGA_HIP(hipMemcpyAsync(dwitems, wi.data(), sizeof(int4) * wi.size(), hipMemcpyHostToDevice, s));
+    FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
+    FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+    FGA_HIP(hipMemsetAsync(gcost, 0, sizeof(unsigned) * goff[npairs], s));
+    FGA_TRY(launch_batch_iteration<T>(dpairs, ditems, (int)items.size(), queue,
+                                      std::min((int)items.size(), cus * 8), c, s, true, true));
+    std::vector<unsigned> cost(goff[npairs]);
+    FGA_HIP(hipMemcpyAsync(cost.data(), gcost, sizeof(unsigned) * cost.size(), hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipMemcpyAsync(st, saved.data(), sizeof(RigidState) * npairs, hipMemcpyHostToDevice, s));
+    FGA_HIP(hipStreamSynchronize(s));
+    // wave items: heavy groups split over parts; blocks of four items of one
+    // pair, queued heaviest first
+    std::vector<double> cs(cost.begin(), cost.end());
+    double total = 0.0;
+    for (double v : cs) total += v;
+    std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
+    const double target = std::max(2.0 * cs[cs.size() / 2], total / 8192.0);
+    items.clear();
+    for (int k = 0; k < npairs; ++k) {
+      std::vector<std::pair<double, int4>> w;
+      for (int g = 0; g < (int)groups[k].size(); ++g) {
+        const unsigned cg = cost[goff[k] + g];
+        int nr = 1;
+        while (nr < kCap && cg > target * nr) nr *= 2;
+        for (int r = 0; r < nr; ++r)
+          w.push_back({(double)cg / nr, make_int4(groups[k][g].x, groups[k][g].y, r | nr << 8, goff[k] + g)});
+      }
+      std::stable_sort(w.begin(), w.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+        return x.first > y.first;
+      });
+      for (size_t e = 0; e < w.size(); ++e) wi[(size_t)goff[k] * kCap + e] = w[e].second;
+      pds[k].n_witems = (int)w.size();
+      pds[k].gcost = nullptr;
+      const int nb = (pds[k].n_witems + kBlock / kWave - 1) / (kBlock / kWave);
+      pds[k].n_items = nb;
+      for (int b = 0; b < nb; ++b) {
+        double bc = 0.0;
+        for (int e = 4 * b; e < std::min((int)w.size(), 4 * b + 4); ++e) bc += w[e].first;
+        blocks.push_back({bc, make_int2(k, b)});
+      }
+    }
+    std::stable_sort(blocks.begin(), blocks.end(), [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
+      return x.first > y.first;
+    });
+    for (auto& b : blocks) items.push_back(b.second);
+    FGA_HIP(hipMemcpyAsync(dwitems, wi.data(), sizeof(int4) * wi.size(), hipMemcpyHostToDevice, s));
+  } else {
+    std::vector<int> order(npairs);
+    for (int k = 0; k < npairs; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return n[x] > n[y]; });
+    for (int k : order)
+      for (int e = 0; e < pds[k].n_items; ++e) items.push_back(make_int2(k, e));
+  }
+  const int n_items = (int)items.size();
+  FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
+  FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
   const int n_blocks = std::min(n_items, cus * 8);
-  const IterConsts c = make_iter_consts(p);
   // one graph holds `every` iterations; replay until all pairs stopped
   const int every = std::max(1, std::min(p.check_every > 0 ? p.check_every : 16, std::max(1, p.max_iter)));
   FGA_HIP(hipStreamSynchronize(s));
   FGA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   fga_status cst = FGA_OK;
   for (int k = 0; k < every && cst == FGA_OK; ++k)
-    cst = launch_batch_iteration<T>(dpairs, ditems, n_items, queue, n_blocks, c, s, nodes != nullptr);
+    cst = launch_batch_iteration<T>(dpairs, ditems, n_items, queue, n_blocks, c, s, nodes != nullptr,
+                                    grouped);
   hipError_t ce = hipStreamEndCapture(s, &B.graph);
   if (cst != FGA_OK) return cst;
   FGA_HIP(ce);

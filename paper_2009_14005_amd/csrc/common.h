@@ -197,7 +197,7 @@ fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t 
 template <typename T>
 fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, int n_items,
                                   unsigned* queue, int n_blocks, const IterConsts& c,
-                                  hipStream_t s, bool bh);
+                                  hipStream_t s, bool bh, bool group);
 
 
 }  // namespace fga

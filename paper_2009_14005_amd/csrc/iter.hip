@@ -323,6 +323,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   }
 }
 
+// Persistent batched iteration with the group walk (K = 1): queue entries are
+// (pair, block of four wave items of that pair), ordered heaviest first.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_iteration_group(
+    const PairDev* pairs, const int2* items, int n_items, unsigned* queue, IterConsts c) {
+  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ GroupLds g[kBlock / kWave];
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
+    __syncthreads();
+    const int e = s_item;
+    __syncthreads();
+    if (e >= n_items) break;
+    const int2 w = items[e];
+    const PairDev pd = pairs[w.x];
+    if (pd.st->converged) continue;
+    iteration_item_group<PREC, 1>(pd, c, w.y, lds, g);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {  // the last block out resets the queue
+    __threadfence();
+    const unsigned prev = atomicAdd(&queue[1], 1u);
+    if (prev == gridDim.x - 1) {
+      queue[0] = 0u;
+      queue[1] = 0u;
+      __threadfence();
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -371,13 +402,25 @@ fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t 
 template <typename T>
 fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, int n_items,
                                   unsigned* queue, int n_blocks, const IterConsts& c,
-                                  hipStream_t s, bool bh) {
-  if (sizeof(T) == 8) {
+                                  hipStream_t s, bool bh, bool group) {
+  if (sizeof(T) == 4 && bh && group) {
+    switch (c.prec) {
+      case FGA_PREC_FP32: k_batch_iteration_group<FGA_PREC_FP32><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      case FGA_PREC_FP32_ALL: k_batch_iteration_group<FGA_PREC_FP32_ALL><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      default: k_batch_iteration_group<FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+    }
+  } else if (sizeof(T) == 8) {
     if (bh) k_batch_iteration<T, true, FGA_PREC_FP64><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
     else k_batch_iteration<T, false, FGA_PREC_FP64><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
   } else {
-    if (bh) k_batch_iteration<T, true, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
-    else k_batch_iteration<T, false, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+    switch (c.prec * 2 + (bh ? 1 : 0)) {
+      case FGA_PREC_FP32 * 2 + 1: k_batch_iteration<T, true, FGA_PREC_FP32><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      case FGA_PREC_FP32 * 2: k_batch_iteration<T, false, FGA_PREC_FP32><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      case FGA_PREC_FP32_ALL * 2 + 1: k_batch_iteration<T, true, FGA_PREC_FP32_ALL><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      case FGA_PREC_FP32_ALL * 2: k_batch_iteration<T, false, FGA_PREC_FP32_ALL><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      case FGA_PREC_FP32_KAHAN * 2 + 1: k_batch_iteration<T, true, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
+      default: k_batch_iteration<T, false, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
+    }
   }
   FGA_HIP(hipGetLastError());
   return FGA_OK;
@@ -386,9 +429,9 @@ fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, i
 template fga_status launch_iteration<float>(const PairDev&, const IterConsts&, hipStream_t);
 template fga_status launch_iteration<double>(const PairDev&, const IterConsts&, hipStream_t);
 template fga_status launch_batch_iteration<float>(const PairDev*, const int2*, int, unsigned*, int,
-                                                  const IterConsts&, hipStream_t, bool);
+                                                  const IterConsts&, hipStream_t, bool, bool);
 template fga_status launch_batch_iteration<double>(const PairDev*, const int2*, int, unsigned*,
-                                                   int, const IterConsts&, hipStream_t, bool);
+                                                   int, const IterConsts&, hipStream_t, bool, bool);
 
 // ------------------------------------------------------------------ forces
 namespace {
