@@ -324,45 +324,42 @@ static void state_free(fga_state* s) {
 static const double kGroupTau[4] = {0.0, 1.0, 2.0, 4.0};
 
 static void make_groups(const float* q4, int64_t m, int G, double f, std::vector<int2>& out) {
-  auto diag2 = [&](int64_t i0, int64_t i1) {
-    float lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q4[4 * i0 + a];
-    for (int64_t i = i0 + 1; i < i1; ++i)
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], q4[4 * i + a]);
-        hi[a] = std::max(hi[a], q4[4 * i + a]);
-      }
-    double d = 0.0;
-    for (int a = 0; a < 3; ++a) d += (double)(hi[a] - lo[a]) * (hi[a] - lo[a]);
-    return d;
-  };
   out.clear();
-  double tau2 = std::numeric_limits<double>::infinity();
+  out.reserve((size_t)(m / G + 1));
+  float tau2 = std::numeric_limits<float>::infinity();
   if (f > 0) {
-    std::vector<double> d;
-    for (int64_t i = 0; i < m; i += G) d.push_back(diag2(i, std::min<int64_t>(m, i + G)));
+    std::vector<float> d;
+    d.reserve((size_t)(m / G + 1));
+    for (int64_t i = 0; i < m; i += G) {
+      const int64_t e = std::min<int64_t>(m, i + G);
+      float lx = q4[4 * i], ly = q4[4 * i + 1], lz = q4[4 * i + 2];
+      float hx = lx, hy = ly, hz = lz;
+      for (int64_t k = i + 1; k < e; ++k) {
+        const float* v = q4 + 4 * k;
+        lx = std::min(lx, v[0]); hx = std::max(hx, v[0]);
+        ly = std::min(ly, v[1]); hy = std::max(hy, v[1]);
+        lz = std::min(lz, v[2]); hz = std::max(hz, v[2]);
+      }
+      d.push_back((hx - lx) * (hx - lx) + (hy - ly) * (hy - ly) + (hz - lz) * (hz - lz));
+    }
     std::nth_element(d.begin(), d.begin() + d.size() / 2, d.end());
-    const double med = d[d.size() / 2];
-    if (med > 0) tau2 = f * f * med;
+    const float med = d[d.size() / 2];
+    if (med > 0) tau2 = (float)(f * f) * med;
   }
   int64_t i = 0;
   while (i < m) {
-    float lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = q4[4 * i + a];
+    float lx = q4[4 * i], ly = q4[4 * i + 1], lz = q4[4 * i + 2];
+    float hx = lx, hy = ly, hz = lz;
     int64_t j = i + 1;
-    for (; j < m && j - i < G; ++j) {
-      float nl[3], nh[3];
-      double dd = 0.0;
-      for (int a = 0; a < 3; ++a) {
-        nl[a] = std::min(lo[a], q4[4 * j + a]);
-        nh[a] = std::max(hi[a], q4[4 * j + a]);
-        dd += (double)(nh[a] - nl[a]) * (nh[a] - nl[a]);
-      }
+    const int64_t e = std::min<int64_t>(m, i + G);
+    for (; j < e; ++j) {
+      const float* v = q4 + 4 * j;
+      const float nlx = std::min(lx, v[0]), nhx = std::max(hx, v[0]);
+      const float nly = std::min(ly, v[1]), nhy = std::max(hy, v[1]);
+      const float nlz = std::min(lz, v[2]), nhz = std::max(hz, v[2]);
+      const float dd = (nhx - nlx) * (nhx - nlx) + (nhy - nly) * (nhy - nly) + (nhz - nlz) * (nhz - nlz);
       if (dd > tau2) break;
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = nl[a];
-        hi[a] = nh[a];
-      }
+      lx = nlx; hx = nhx; ly = nly; hy = nhy; lz = nlz; hz = nhz;
     }
     out.push_back(make_int2((int)i, (int)(j - i)));
     i = j;
