@@ -253,8 +253,9 @@ constexpr int kGStack = 512;  // child-block entries per wave
 // (at most kQBits + 1 below the root) adds at most 7 entries to the stack.
 constexpr int kGReserve = 8 * (kQBits + 2);
 
+constexpr int kGRepMax = 8;   // replicas of a small group's particles over the lanes
 struct GroupLds {
-  float4 list[kGList];
+  float4 list[kGList + kGRepMax];  // slack for zero-mass padding to a multiple of the replicas
   int stk[kGStack];
 };
 
@@ -295,6 +296,48 @@ __device__ inline void group_sum(const float4* list, int cnt, const float (&y)[K
 #pragma unroll 4
   for (int e = 0; e < cnt; ++e) {
     const float4 x = list[e];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = x.z - y[k][2];
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+      const float r = __builtin_amdgcn_rsqf(r2);
+      const float s = x.w * r * (r * r);
+      t[k][0] = fmaf(dx, s, t[k][0]);
+      t[k][1] = fmaf(dy, s, t[k][1]);
+      t[k][2] = fmaf(dz, s, t[k][2]);
+    }
+  }
+  if (!sel) return;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (KAHAN) {
+        const float u = t[k][a] - cmp[k][a], v = acc[k][a] + u;
+        cmp[k][a] = (v - acc[k][a]) - u;
+        acc[k][a] = v;
+      } else {
+        acc[k][a] = t[k][a];
+      }
+    }
+}
+
+// The same sum for a group held R > 1 times over the lanes: replica `rep`
+// takes entries rep, rep + R, ... of the list (padded with zero-mass entries
+// to a multiple of R, cnt).
+template <int K, bool KAHAN>
+__device__ inline void group_sum_rep(const float4* list, int cnt, int rep, int R,
+                                     const float (&y)[K][3], float eps2, bool sel,
+                                     float (&acc)[K][3], float (&cmp)[K][3]) {
+  float t[K][3];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t[k][a] = KAHAN ? 0.f : acc[k][a];
+  const int n = cnt / R;  // entries per replica, uniform
+#pragma unroll 4
+  for (int i = 0; i < n; ++i) {
+    const float4 x = list[i * R + rep];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = x.z - y[k][2];
@@ -364,7 +407,8 @@ constexpr int kIndexMask = kLargeParent - 1;
 template <int K, bool KAHAN>
 __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
                                   int r, int nr, float theta2, float eps2, bool sel,
-                                  int nvalid, const float (&lo)[3], const float (&hi)[3],
+                                  int nvalid, int rep, int R, const float (&lo)[3],
+                                  const float (&hi)[3],
                                   const float (&y)[K][3], float (&acc)[K][3],
                                   float (&cmp)[K][3], unsigned& count, unsigned& entries,
                                   GroupLds& g) {
@@ -374,8 +418,14 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
   int sp = 1;   // stack entries; the root is a block of one node at index 0
   if (lane == 0) g.stk[0] = kLargeParent;
   auto flush = [&]() {
-    group_sum<K, KAHAN>(g.list, cnt, y, eps2, sel, acc, cmp);
-    count += sel ? (unsigned)(cnt * nvalid) : 0u;
+    if (R == 1) {
+      group_sum<K, KAHAN>(g.list, cnt, y, eps2, sel, acc, cmp);
+    } else {
+      const int padded = (cnt + R - 1) / R * R;  // zero-mass entries up to a multiple of R
+      if (lane < padded - cnt) g.list[cnt + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+      group_sum_rep<K, KAHAN>(g.list, padded, rep, R, y, eps2, sel, acc, cmp);
+    }
+    count += (sel && rep == 0) ? (unsigned)(cnt * nvalid) : 0u;
     entries += (unsigned)cnt;
     cnt = 0;
   };
@@ -462,16 +512,19 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
   return ok;
 }
 
-// Lane l holds particles K l .. K l + K - 1 of the wave's group, walked as
+// Lane l holds particles K p .. K p + K - 1 of the wave's group, p = l mod
+// (64 / R): with R > 1 (K = 1, groups of at most 64 / R particles) every
+// particle is held by R lanes that split the list between them. The walk is
 // part r of nr (see kSplitPts); `entries`
 // (uniform) receives the number of list entries evaluated. Returns false if
 // the stack overflowed (never for trees of depth at most kQBits + 1;
 // the sum is then incomplete).
 template <int K, bool KAHAN>
 __device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
-                                int r, int nr, float theta2, float eps2, const bool (&valid)[K],
-                                const float (&y)[K][3], float (&acc)[K][3], unsigned& count,
-                                unsigned& entries, GroupLds& g) {
+                                int r, int nr, int R, float theta2, float eps2,
+                                const bool (&valid)[K], const float (&y)[K][3],
+                                float (&acc)[K][3], unsigned& count, unsigned& entries,
+                                GroupLds& g) {
   int nvalid = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) nvalid += valid[k] ? 1 : 0;
@@ -483,8 +536,20 @@ __device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* 
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int a = 0; a < 3; ++a) cmp[k][a] = 0.f;
-  return group_walk<K, KAHAN>(nodes, X, r, nr, theta2, eps2, true, nvalid, lo, hi, y, acc, cmp,
-                              count, entries, g);
+  const int rep = (int)(threadIdx.x & (kWave - 1)) / (kWave / R);
+  const bool ok = group_walk<K, KAHAN>(nodes, X, r, nr, theta2, eps2, true, nvalid, rep, R, lo,
+                                       hi, y, acc, cmp, count, entries, g);
+  if (R > 1) {  // add the replicas' partial sums
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float v = KAHAN ? acc[k][a] - cmp[k][a] : acc[k][a];
+        for (int o = kWave / R; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+        acc[k][a] = v;
+      }
+  }
+  return ok;
 }
 
 }  // namespace fga

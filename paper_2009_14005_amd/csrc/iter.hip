@@ -249,6 +249,12 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
     nr = w.z >> 8;
     gi = w.w;
   }
+  // a small group is held R times over the lanes (K = 1): R copies of at
+  // most 64 / R particles, each copy summing every R-th list entry
+  int R = 1;
+  if (K == 1)
+    while (R < kGRepMax && grp.y <= kWave / (2 * R)) R *= 2;
+  const int pl = lane & (kWave / R - 1);
   int idx[K];
   bool valid[K];
   float y[K][3], acc[K][3];
@@ -256,8 +262,8 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
     const RigidState* st = pd.st;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      valid[k] = K * lane + k < grp.y;
-      idx[k] = grp.x + K * lane + k;
+      valid[k] = K * pl + k < grp.y;
+      idx[k] = grp.x + K * pl + k;
       const float4 q = Q[valid[k] ? idx[k] : pd.m - 1];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -267,11 +273,14 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
   }
   unsigned cnt = 0, entries = 0;
   const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
-      pd.nodes, (const float4*)pd.X, r, nr, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
+      pd.nodes, (const float4*)pd.X, r, nr, R, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
       g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
   if (pd.gcost && lane == 0 && gi >= 0) atomicAdd(&pd.gcost[gi], entries);
-  finish_item<float, true, PREC, K>(pd, c, item, r, idx, valid, acc, cnt, lds);
+  bool owner[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) owner[k] = valid[k] && lane < kWave / R;
+  finish_item<float, true, PREC, K>(pd, c, item, r, idx, owner, acc, cnt, lds);
 }
 
 template <typename T, bool BH, int PREC, int S>
@@ -538,8 +547,8 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, true>(nodes, Xs, 0, 1, theta2, eps2, valid, y, acc, cnt, entries,
-                                    g[wave]);
+  const bool ok = bh_group<K, true>(nodes, Xs, 0, 1, 1, theta2, eps2, valid, y, acc, cnt,
+                                    entries, g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (valid[k]) {
