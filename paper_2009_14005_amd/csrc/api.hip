@@ -759,8 +759,8 @@ fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const 
                        : sort_points_morton<float>(1, &seg, Y4, m, yorder, s);
   if (st == FGA_OK)
     st = dt == FGA_F64
-             ? forces_bh_tree<double>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s)
-             : forces_bh_tree<float>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, theta, *p, mY, F_out, interactions, s);
+             ? forces_bh_tree<double>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, n, theta, *p, mY, F_out, interactions, s)
+             : forces_bh_tree<float>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, n, theta, *p, mY, F_out, interactions, s);
   if (Y4) (void)hipFree(Y4);
   if (yorder) (void)hipFree(yorder);
   fga_tree_destroy(tr);

@@ -186,8 +186,9 @@ fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, con
                          const void* mY, const fga_params& p, void* F, hipStream_t s);
 template <typename T>
 fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
-                          int n_nodes, const void* Xs, double theta, const fga_params& p,
-                          const void* mY, void* F, long long* interactions, hipStream_t s);
+                          int n_nodes, const void* Xs, int64_t n, double theta,
+                          const fga_params& p, const void* mY, void* F, long long* interactions,
+                          hipStream_t s);
 template <typename T>
 fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipStream_t s);
 

@@ -257,6 +257,7 @@ constexpr int kGRepMax = 8;   // replicas of a small group's particles over the 
 struct GroupLds {
   float4 list[kGList + kGRepMax];  // slack for zero-mass padding to a multiple of the replicas
   int stk[kGStack];
+  int mark[kWave];                 // lane -> first lane of its stack entry, per step
 };
 
 __device__ inline float wave_min_f(float v) {
@@ -268,18 +269,6 @@ __device__ inline float wave_max_f(float v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
   return v;
-}
-
-// Lane of the first entry whose inclusive prefix count exceeds k (the counts
-// in `incl` are non-decreasing over the lanes and incl[63] > k).
-__device__ inline int wave_owner(int incl, int k) {
-  int o = 0;
-#pragma unroll
-  for (int step = 32; step > 0; step >>= 1) {
-    const int v = __shfl(incl, o + step - 1, kWave);
-    if (v <= k) o += step;
-  }
-  return o;
 }
 
 // Adds the list entries [0, cnt) to the K particles of this lane if `sel`.
@@ -405,8 +394,9 @@ constexpr int kIndexMask = kLargeParent - 1;
 
 // The walk for a group: the particles of the lanes with `sel`, part r of nr.
 template <int K, bool KAHAN>
-__device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
-                                  int r, int nr, float theta2, float eps2, bool sel,
+__device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
+                                  const float4* __restrict__ X, int n_points, int r, int nr,
+                                  float theta2, float eps2, bool sel,
                                   int nvalid, int rep, int R, const float (&lo)[3],
                                   const float (&hi)[3],
                                   const float (&y)[K][3], float (&acc)[K][3],
@@ -429,30 +419,45 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
     entries += (unsigned)cnt;
     cnt = 0;
   };
-  while (sp > 0) {
-    // pop whole child blocks from the top, at most 64 nodes, and while the
-    // stack stays below kGStack - kGReserve even if every node is opened
+  // pops whole child blocks from the top (at most 64 nodes, and only while the
+  // stack stays below kGStack - kGReserve even if every node is opened), one
+  // node per lane, and starts the loads of those nodes
+  int T = 0, node = 0, pke = 0;
+  BHWide nd;
+  auto pop = [&]() {
     const int avail = min(sp, kWave);
     int ch = 0, c = 0;
     if (lane < avail) {
       ch = g.stk[sp - 1 - lane];
       c = (int)((unsigned)ch >> kChildShift) + 1;
     }
-    const int incl = wave_incl_scan(c);
+    const int incl = wave_incl_sum_dpp(c);
     const bool take = lane < avail && incl <= kWave &&
                       (lane == 0 || sp - (lane + 1) + incl <= kGStack - kGReserve);
     const int E = __popcll(__ballot(take));
-    const int T = __shfl(incl, E - 1, kWave);
+    T = E > 0 ? __builtin_amdgcn_readlane(incl, E - 1) : 0;
     sp -= E;
-    // this lane's node: entry e = the first whose prefix count exceeds the lane
-    const int e = wave_owner(lane < E ? incl : 0x7fffffff, lane);
-    const int che = __shfl(ch, e, kWave), ince = __shfl(incl, e, kWave);
+    // this lane's node: entry e is the last whose first lane (incl - c) is at
+    // or below the lane; the entries' first lanes are distinct (relaxed
+    // atomics: the marks pass between lanes, so a lane's own -1 must not be
+    // forwarded to its read)
+    __hip_atomic_store(&g.mark[lane], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (lane < E)
+      __hip_atomic_store(&g.mark[incl - c], lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const int e = wave_incl_max(
+        __hip_atomic_load(&g.mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+    // entry lane: its first node minus its first lane (+ 64, >= 1) and the
+    // shared-parent flag in bit 30, fetched by the node lanes in one move
+    const int pk = ((ch & kIndexMask) - (incl - c) + kWave) | ((ch & kLargeParent) ? 1 << 30 : 0);
+    pke = __shfl(pk, e < 0 ? 0 : e, kWave);
+    node = min((pke & ((1 << 30) - 1)) - kWave + lane, n_nodes - 1);
+    nd = nodes[lane < T ? node : 0];
+  };
+  pop();
+  while (T > 0) {
     const bool act = lane < T;
-    const int node = (che & kIndexMask) + lane -
-                     (ince - ((int)((unsigned)che >> kChildShift) + 1));
-    const BHWide nd = nodes[act ? node : 0];
     const bool shared = nd.last - nd.first + 1 > kSplitPts;
-    const bool frontier = !shared && (che & kLargeParent);
+    const bool frontier = !shared && (pke & (1 << 30));
     const bool on = act && (!frontier || node % nr == r);
     const bool mine = !shared || r == 0;  // owns the node's own term or points
     const bool leaf = nd.child == -1;
@@ -494,17 +499,36 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
     const int p0 = nd.first;
     const int np = pts ? nd.last - p0 + 1 : 0;
     if (__ballot(np > 0) != 0ull) {
-      const int pincl = wave_incl_scan(np);
-      const int P = __shfl(pincl, kWave - 1, kWave);
+      const int pincl = wave_incl_sum_dpp(np);
+      const int P = __builtin_amdgcn_readlane(pincl, kWave - 1);
+      const int pex = pincl - np;          // first list slot of this lane's points
+      const int off = p0 - pex;            // point index = slot + off for this lane's slots
+      const unsigned long long has = __ballot(np > 0);
       for (int base = 0; base < P; base += kWave) {
         if (cnt > kGList - kWave) flush();
         const int k = base + lane;
-        const int o = wave_owner(pincl, k);
-        const int oincl = __shfl(pincl, o, kWave), onp = __shfl(np, o, kWave),
-                  op0 = __shfl(p0, o, kWave);
-        if (k < P) g.list[cnt + lane] = X[op0 + k - (oincl - onp)];
+        // owner of slot k: the last lane with points whose first slot is at or
+        // below k; slot `base` may continue a lane that started earlier
+        const unsigned long long before = __ballot(np > 0 && pex <= base) & has;
+        const int carry = 63 - __builtin_clzll(before);
+        __hip_atomic_store(&g.mark[lane], lane == 0 ? carry : -1, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (np > 0 && pex > base && pex < base + kWave)
+          __hip_atomic_store(&g.mark[pex - base], lane, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int o = wave_incl_max(
+            __hip_atomic_load(&g.mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+        const int ooff = __shfl(off, o, kWave);
+        if (k < P) g.list[cnt + lane] = X[min(max(k + ooff, 0), n_points - 1)];
         cnt += min(kWave, P - base);
       }
+    }
+    // the next step's nodes are requested before the list is summed, so
+    // their load latency overlaps the arithmetic
+    if (sp > 0) {
+      pop();
+    } else {
+      T = 0;
     }
     if (cnt > kGList - kWave) flush();
   }
@@ -520,8 +544,9 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, const float4
 // the stack overflowed (never for trees of depth at most kQBits + 1;
 // the sum is then incomplete).
 template <int K, bool KAHAN>
-__device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* __restrict__ X,
-                                int r, int nr, int R, float theta2, float eps2,
+__device__ inline bool bh_group(const BHWide* __restrict__ nodes, int n_nodes,
+                                const float4* __restrict__ X, int n_points, int r, int nr, int R,
+                                float theta2, float eps2,
                                 const bool (&valid)[K], const float (&y)[K][3],
                                 float (&acc)[K][3], unsigned& count, unsigned& entries,
                                 GroupLds& g) {
@@ -537,8 +562,8 @@ __device__ inline bool bh_group(const BHWide* __restrict__ nodes, const float4* 
 #pragma unroll
     for (int a = 0; a < 3; ++a) cmp[k][a] = 0.f;
   const int rep = (int)(threadIdx.x & (kWave - 1)) / (kWave / R);
-  const bool ok = group_walk<K, KAHAN>(nodes, X, r, nr, theta2, eps2, true, nvalid, rep, R, lo,
-                                       hi, y, acc, cmp, count, entries, g);
+  const bool ok = group_walk<K, KAHAN>(nodes, n_nodes, X, n_points, r, nr, theta2, eps2, true,
+                                       nvalid, rep, R, lo, hi, y, acc, cmp, count, entries, g);
   if (R > 1) {  // add the replicas' partial sums
 #pragma unroll
     for (int k = 0; k < K; ++k)

@@ -273,8 +273,8 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
   }
   unsigned cnt = 0, entries = 0;
   const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
-      pd.nodes, (const float4*)pd.X, r, nr, R, c.ftheta2, c.feps2, valid, y, acc, cnt, entries,
-      g[wave]);
+      pd.nodes, pd.n_nodes, (const float4*)pd.X, pd.n, r, nr, R, c.ftheta2, c.feps2, valid, y,
+      acc, cnt, entries, g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
   if (pd.gcost && lane == 0 && gi >= 0) atomicAdd(&pd.gcost[gi], entries);
   bool owner[K];
@@ -526,7 +526,8 @@ __global__ __launch_bounds__(kBlock) void k_forces_bh(const T* Y, const int* yor
 // particles of the Morton order yorder and writes F_i = G m_Y,i acc_i.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const int* yorder, int m,
-                                                         const BHWide* nodes, const float4* Xs,
+                                                         const BHWide* nodes, int n_nodes,
+                                                         const float4* Xs, int n_points,
                                                          float theta2, float eps2, const float* mY,
                                                          double G, float* F,
                                                          unsigned long long* count) {
@@ -547,8 +548,8 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, true>(nodes, Xs, 0, 1, 1, theta2, eps2, valid, y, acc, cnt,
-                                    entries, g[wave]);
+  const bool ok = bh_group<K, true>(nodes, n_nodes, Xs, n_points, 0, 1, 1, theta2, eps2, valid,
+                                    y, acc, cnt, entries, g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (valid[k]) {
@@ -616,8 +617,9 @@ template fga_status pack_points<double>(const void*, const void*, int64_t, void*
 
 template <typename T>
 fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
-                          int n_nodes, const void* Xs, double theta, const fga_params& p,
-                          const void* mY, void* F, long long* interactions, hipStream_t s) {
+                          int n_nodes, const void* Xs, int64_t n, double theta,
+                          const fga_params& p, const void* mY, void* F, long long* interactions,
+                          hipStream_t s) {
   unsigned long long* cnt = nullptr;
   FGA_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
   (void)hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
@@ -627,11 +629,13 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
       const int tp = kBlock * K;
       if (K == 1)
         k_forces_group<1><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
-            (const float*)Y, yorder, (int)m, nodes, (const float4*)Xs, (float)(theta * theta),
+            (const float*)Y, yorder, (int)m, nodes, n_nodes, (const float4*)Xs, (int)n,
+            (float)(theta * theta),
             (float)(p.eps * p.eps), (const float*)mY, p.G, (float*)F, cnt);
       else
         k_forces_group<2><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
-            (const float*)Y, yorder, (int)m, nodes, (const float4*)Xs, (float)(theta * theta),
+            (const float*)Y, yorder, (int)m, nodes, n_nodes, (const float4*)Xs, (int)n,
+            (float)(theta * theta),
             (float)(p.eps * p.eps), (const float*)mY, p.G, (float*)F, cnt);
     }
   }
@@ -659,10 +663,10 @@ template fga_status forces_direct<float>(const void*, int64_t, const void*, int6
 template fga_status forces_direct<double>(const void*, int64_t, const void*, int64_t, const void*,
                                           const void*, const fga_params&, void*, hipStream_t);
 template fga_status forces_bh_tree<float>(const void*, int64_t, const int*, const BHWide*, int,
-                                          const void*, double, const fga_params&, const void*,
-                                          void*, long long*, hipStream_t);
+                                          const void*, int64_t, double, const fga_params&,
+                                          const void*, void*, long long*, hipStream_t);
 template fga_status forces_bh_tree<double>(const void*, int64_t, const int*, const BHWide*, int,
-                                           const void*, double, const fga_params&, const void*,
-                                           void*, long long*, hipStream_t);
+                                           const void*, int64_t, double, const fga_params&,
+                                           const void*, void*, long long*, hipStream_t);
 
 }  // namespace fga
