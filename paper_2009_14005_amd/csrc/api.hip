@@ -289,6 +289,10 @@ struct fga_state {
     std::map<int, std::pair<int4*, int>> items;  // range cap -> wave items, count
   };
   std::map<int, Groups> groups;         // key K * 4 + tau option
+  // group walk whose costs are measured by the first iteration of fga_step
+  // (registrations): the K, tau option and part cap of the pending split
+  int pend_K = 0, pend_fi = 0, pend_cap = 0;
+  int4* ident_items = nullptr;          // one wave item per group, Morton order
 };
 
 struct fga_tree {
@@ -312,6 +316,7 @@ static void state_free(fga_state* s) {
   if (s->V) (void)hipFree(s->V);
   for (auto& kv : s->groups)
     for (auto& it : kv.second.items) (void)hipFree(it.second.first);
+  if (s->ident_items) (void)hipFree(s->ident_items);
   delete s;
 }
 
@@ -481,7 +486,8 @@ static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap
 // K particles per lane, groups bounded by kGroupTau[fi] and at most `ranges`
 // reference ranges per group. With `build` false only the launch size (an
 // upper bound for the group walk) is set.
-static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = true) {
+static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = true,
+                              bool defer = false) {
   const int mode = code >> 8;
   pd.jr = code & 255;
   pd.witems = nullptr;
@@ -495,7 +501,19 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
     fga_state::Groups* gt = nullptr;
     FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, &gt));
     pd.n_groups = gt->n;
-    if (build) {
+    if (build && defer && gt->cost.empty()) {
+      // one wave per group for now; the first iteration measures the costs
+      std::vector<int4> ident(gt->n);
+      for (int k = 0; k < gt->n; ++k) ident[k] = make_int4(gt->host[k].x, gt->host[k].y, 1 << 8, k);
+      if (S->ident_items) (void)hipFree(S->ident_items);
+      S->ident_items = nullptr;
+      FGA_TRY(upload_items(S, ident, &S->ident_items));
+      pd.witems = S->ident_items;
+      pd.n_witems = gt->n;
+      S->pend_K = pd.group;
+      S->pend_fi = (mode - 16) >> 2;
+      S->pend_cap = pd.jr;
+    } else if (build) {
       FGA_TRY(wave_items(S, pd.group, *gt, pd.jr, &pd.witems, &pd.n_witems));
     } else {
       pd.n_witems = gt->n * pd.jr;  // at most `jr` parts per group
@@ -778,8 +796,8 @@ static fga_status validate_pair(const void* X, int64_t n, const void* Y, int64_t
   return FGA_OK;
 }
 
-fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
-                            const fga_params* p, void* stream, fga_state** out) {
+static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                               const fga_params* p, void* stream, bool defer, fga_state** out) {
   FGA_TRY(validate_pair(X, n, Y, m, dt, p));
   FGA_TRY(check_ptr(out, "out"));
   FGA_TRY(check_device_ptr(X, "X"));
@@ -903,7 +921,8 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
     set_error("state initialisation failed");
     return fail(FGA_E_DEVICE);
   }
-  if (fga_status gs = apply_split(S, pd, cands[0]); gs != FGA_OK) return fail(gs);
+  if (fga_status gs = apply_split(S, pd, cands[0], true, defer && cands.size() == 1); gs != FGA_OK)
+    return fail(gs);
   if (cands.size() > 1) {
     const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width);
     int found = 0;
@@ -922,7 +941,7 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
       g_tune[key] = best;
       tune_save_locked();
     }
-    if (fga_status gs = apply_split(S, pd, best); gs != FGA_OK) return fail(gs);
+    if (fga_status gs = apply_split(S, pd, best, true, defer); gs != FGA_OK) return fail(gs);
   }
   if (S->V) {  // trial iterations wrote per-particle velocities; the state starts at rest
     const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
@@ -930,6 +949,41 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
       return fail(FGA_E_DEVICE);
   }
   *out = S;
+  return FGA_OK;
+}
+
+fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                            const fga_params* p, void* stream, fga_state** out) {
+  return state_create(X, n, Y, m, dt, p, stream, false, out);
+}
+
+// The first iteration of a deferred group split: one wave per group counts
+// every group's list entries while it iterates; the balanced wave items are
+// then built from those costs.
+static fga_status first_step_measured(fga_state* S) {
+  fga_state::Groups* gt = nullptr;
+  FGA_TRY(ensure_groups(S, S->pend_K, S->pend_fi, &gt));
+  unsigned* cost = nullptr;
+  FGA_HIP(hipMalloc((void**)&cost, sizeof(unsigned) * gt->n));
+  PairDev pd = S->pd;
+  pd.gcost = cost;
+  gt->cost.assign(gt->n, 0u);
+  fga_status st = FGA_OK;
+  if (hipMemsetAsync(cost, 0, sizeof(unsigned) * gt->n, S->s) != hipSuccess) st = FGA_E_DEVICE;
+  if (st == FGA_OK) st = launch_iteration<float>(pd, S->c, S->s);
+  if (st == FGA_OK &&
+      (hipMemcpyAsync(gt->cost.data(), cost, sizeof(unsigned) * gt->n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
+       hipStreamSynchronize(S->s) != hipSuccess))
+    st = FGA_E_DEVICE;
+  (void)hipFree(cost);
+  if (st != FGA_OK) {
+    gt->cost.clear();
+    if (st == FGA_E_DEVICE) set_error("first iteration with cost measurement failed");
+    return st;
+  }
+  FGA_TRY(wave_items(S, S->pend_K, *gt, S->pend_cap, &S->pd.witems, &S->pd.n_witems));
+  S->pd.n_items = (S->pd.n_witems + kBlock / kWave - 1) / (kBlock / kWave);
+  S->pend_K = 0;
   return FGA_OK;
 }
 
@@ -946,7 +1000,12 @@ fga_status fga_step(fga_state* S, int n_iters) {
     return FGA_E_INVALID_ARG;
   }
   const int every = S->p.check_every > 0 ? S->p.check_every : 16;
-  for (int k = 0; k < n_iters; ++k) {
+  int k0 = 0;
+  if (S->pend_K && n_iters > 0) {
+    FGA_TRY(first_step_measured(S));
+    k0 = 1;
+  }
+  for (int k = k0; k < n_iters; ++k) {
     fga_status st = S->f64 ? launch_iteration<double>(S->pd, S->c, S->s)
                            : launch_iteration<float>(S->pd, S->c, S->s);
     if (st != FGA_OK) return st;
@@ -1048,7 +1107,7 @@ fga_status fga_register(const void* X, int64_t n, const void* Y, int64_t m, fga_
   FGA_TRY(check_ptr(t, "t"));
   const double t0 = now_ms();
   fga_state* S = nullptr;
-  FGA_TRY(fga_state_create(X, n, Y, m, dt, p, stream, &S));
+  FGA_TRY(state_create(X, n, Y, m, dt, p, stream, true, &S));
   fga_status st = fga_step(S, p->max_iter);
   if (st == FGA_OK) st = fga_state_get(S, R, t, rep);
   fga_state_destroy(S);
