@@ -879,8 +879,23 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     const int jd = direct_ranges(m, n);
     if (std::find(cands.begin(), cands.end(), 1 << 8 | jd) == cands.end()) cands.push_back(1 << 8 | jd);
   }
+  // a cached tuning result needs only its own split; otherwise every
+  // candidate is timed
+  const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width);
+  int best = cands[0];
+  bool tuned = cands.size() == 1;
+  if (!tuned) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end()) {
+      best = it->second;
+      tuned = true;
+    }
+  }
+  const std::vector<int> used = tuned ? std::vector<int>{best} : cands;
   size_t max_items = 0;
-  for (int c : cands) {
+  for (int c : used) {
     PairDev tmp{};
     const fga_status gs = apply_split(S, tmp, c, false);
     if (gs != FGA_OK) return fail(gs);
@@ -921,28 +936,15 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     set_error("state initialisation failed");
     return fail(FGA_E_DEVICE);
   }
-  if (fga_status gs = apply_split(S, pd, cands[0], true, defer && cands.size() == 1); gs != FGA_OK)
-    return fail(gs);
-  if (cands.size() > 1) {
-    const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width);
-    int found = 0;
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      tune_load_locked();
-      auto it = g_tune.find(key);
-      if (it != g_tune.end()) found = it->second;
-    }
-    int best = found;
-    if (!(found > 0 && std::find(cands.begin(), cands.end(), found) != cands.end())) {
-      best = cands[0];
-      fga_status tst = tune_ranges(S, cands, &best);
-      if (tst != FGA_OK) return fail(tst);
-      std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune[key] = best;
-      tune_save_locked();
-    }
-    if (fga_status gs = apply_split(S, pd, best, true, defer); gs != FGA_OK) return fail(gs);
+  if (!tuned) {
+    if (fga_status gs = apply_split(S, pd, cands[0]); gs != FGA_OK) return fail(gs);
+    fga_status tst = tune_ranges(S, cands, &best);
+    if (tst != FGA_OK) return fail(tst);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    tune_save_locked();
   }
+  if (fga_status gs = apply_split(S, pd, best, true, defer); gs != FGA_OK) return fail(gs);
   if (S->V) {  // trial iterations wrote per-particle velocities; the state starts at rest
     const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
     if (hipMemsetAsync(S->V, 0, vb, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
