@@ -196,6 +196,13 @@ fga_status fga_register_batch(int npairs, const void* const* X, const int64_t* n
                               const fga_params* p, double* R, double* t, fga_report* reps,
                               void* stream);
 
+/* The library keeps the device buffers of finished calls in a cache and reuses
+ * them (a registration needs a few dozen buffers; allocating and freeing them
+ * each time costs more than a small registration). Returns every idle cached
+ * buffer to the device; buffers still in use by queued work stay cached.
+ * Thread-safe. */
+fga_status fga_trim_cache(void);
+
 /* ---- inspection entry points (used by tests and tools) ---- */
 
 /* Builds the compressed octree of Alg. 1 on X (n x 3) with masses mX (n),

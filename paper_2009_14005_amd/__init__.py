@@ -105,6 +105,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         sig = {
             "fga_default_params": (st, [P]),
+            "fga_trim_cache": (st, []),
             "fga_last_error": (ctypes.c_char_p, []),
             "fga_version": (ctypes.c_char_p, []),
             "fga_masses": (st, [vp, dt, i64, P, ctypes.c_int, vp, vp]),
@@ -195,6 +196,11 @@ def masses(pts, params: Params = None, norm: int = 0):
     _check(lib().fga_masses(_ptr(pts), _dtype_code(pts), pts.shape[0], ctypes.byref(p), norm,
                             _ptr(out), _stream()))
     return out
+
+
+def trim_cache():
+    """Returns the library's idle cached device buffers to the device."""
+    _check(lib().fga_trim_cache())
 
 
 def forces(Y, X, mX, mY=None, theta: float = 0.0, params: Params = None):

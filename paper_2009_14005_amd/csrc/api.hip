@@ -297,6 +297,7 @@ struct fga_state {
 
 struct fga_tree {
   int64_t n;
+  hipStream_t s = nullptr;
   BHNode* nodes = nullptr;  // preorder (exported)
   BHWide* wide = nullptr;   // child-block layout (traversed)
   int n_nodes = 0;
@@ -305,19 +306,20 @@ struct fga_tree {
   int stats[3] = {0, 0, 0};
 };
 
-static void state_free(fga_state* s) {
-  if (!s) return;
-  if (s->X) (void)hipFree(s->X);
-  if (s->Q) (void)hipFree(s->Q);
-  if (s->nodes) (void)hipFree(s->nodes);
-  if (s->st) (void)hipFree(s->st);
-  if (s->partial) (void)hipFree(s->partial);
-  if (s->done) (void)hipFree(s->done);
-  if (s->V) (void)hipFree(s->V);
-  for (auto& kv : s->groups)
-    for (auto& it : kv.second.items) (void)hipFree(it.second.first);
-  if (s->ident_items) (void)hipFree(s->ident_items);
-  delete s;
+static void state_free(fga_state* S) {
+  if (!S) return;
+  const hipStream_t s = S->s;
+  pool_free(S->X, s);
+  pool_free(S->Q, s);
+  pool_free(S->nodes, s);
+  pool_free(S->st, s);
+  pool_free(S->partial, s);
+  pool_free(S->done, s);
+  pool_free(S->V, s);
+  for (auto& kv : S->groups)
+    for (auto& it : kv.second.items) pool_free(it.second.first, s);
+  pool_free(S->ident_items, s);
+  delete S;
 }
 
 // Groups of the template for the group walk, over its Morton order: runs of
@@ -372,7 +374,7 @@ static void make_groups(const float* q4, int64_t m, int G, double f, std::vector
 }
 
 static fga_status upload_items(fga_state* S, const std::vector<int4>& v, int4** out) {
-  FGA_HIP(hipMalloc((void**)out, sizeof(int4) * std::max<size_t>(1, v.size())));
+  FGA_TRY(pool_get(out, sizeof(int4) * std::max<size_t>(1, v.size()), S->s));
   FGA_HIP(hipMemcpyAsync(*out, v.data(), sizeof(int4) * v.size(), hipMemcpyHostToDevice, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
   return FGA_OK;
@@ -390,9 +392,8 @@ static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
   int4* wi = nullptr;
   FGA_TRY(upload_items(S, ident, &wi));
   unsigned* cost = nullptr;
-  if (hipMalloc((void**)&cost, sizeof(unsigned) * gt.n) != hipSuccess) {
-    (void)hipFree(wi);
-    set_error("hipMalloc failed");
+  if (pool_get(&cost, sizeof(unsigned) * gt.n, S->s) != FGA_OK) {
+    pool_free(wi, S->s);
     return FGA_E_NOMEM;
   }
   PairDev pd = S->pd;
@@ -414,8 +415,8 @@ static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
        hipMemcpyAsync(S->st, &saved, sizeof saved, hipMemcpyHostToDevice, S->s) != hipSuccess ||
        hipStreamSynchronize(S->s) != hipSuccess))
     st = FGA_E_DEVICE;
-  (void)hipFree(cost);
-  (void)hipFree(wi);
+  pool_free(cost, S->s);
+  pool_free(wi, S->s);
   if (st != FGA_OK) {
     gt.cost.clear();
     if (st == FGA_E_DEVICE) set_error("group cost measurement failed");
@@ -505,7 +506,7 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
       // one wave per group for now; the first iteration measures the costs
       std::vector<int4> ident(gt->n);
       for (int k = 0; k < gt->n; ++k) ident[k] = make_int4(gt->host[k].x, gt->host[k].y, 1 << 8, k);
-      if (S->ident_items) (void)hipFree(S->ident_items);
+      pool_free(S->ident_items, S->s);
       S->ident_items = nullptr;
       FGA_TRY(upload_items(S, ident, &S->ident_items));
       pd.witems = S->ident_items;
@@ -651,11 +652,10 @@ fga_status fga_tree_create(const void* X, const void* mX, int64_t n, fga_dtype d
   hipStream_t s = (hipStream_t)stream;
   fga_tree* t = new fga_tree;
   t->n = n;
+  t->s = s;
   const size_t v4 = dt == FGA_F64 ? sizeof(double4) : sizeof(float4);
-  hipError_t e = hipMalloc(&t->Xs, v4 * n);
-  if (e != hipSuccess) {
+  if (pool_get(&t->Xs, v4 * n, s) != FGA_OK) {
     delete t;
-    set_error("hipMalloc failed: %s", hipGetErrorString(e));
     return FGA_E_NOMEM;
   }
   fga_status st = dt == FGA_F64 ? pack_points<double>(X, mX, n, t->Xs, s)
@@ -667,7 +667,7 @@ fga_status fga_tree_create(const void* X, const void* mX, int64_t n, fga_dtype d
              ? build_trees<double>(1, &seg, t->Xs, n, p->leaf_size, &t->nodes, off, &t->order, t->stats, s)
              : build_trees<float>(1, &seg, t->Xs, n, p->leaf_size, &t->nodes, off, &t->order, t->stats, s);
   if (st != FGA_OK) {
-    if (t->Xs) (void)hipFree(t->Xs);
+    pool_free(t->Xs, s);
     delete t;
     return st;
   }
@@ -720,10 +720,10 @@ fga_status fga_tree_export(const fga_tree* t, float* com_mass, int32_t* ints, in
 
 void fga_tree_destroy(fga_tree* t) {
   if (!t) return;
-  if (t->nodes) (void)hipFree(t->nodes);
-  if (t->wide) (void)hipFree(t->wide);
-  if (t->order) (void)hipFree(t->order);
-  if (t->Xs) (void)hipFree(t->Xs);
+  pool_free(t->nodes, t->s);
+  pool_free(t->wide, t->s);
+  pool_free(t->order, t->s);
+  pool_free(t->Xs, t->s);
   delete t;
 }
 
@@ -765,10 +765,8 @@ fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const 
   int* yorder = nullptr;
   const size_t v4 = dt == FGA_F64 ? sizeof(double4) : sizeof(float4);
   fga_status st = FGA_OK;
-  if (hipMalloc(&Y4, v4 * m) != hipSuccess || hipMalloc((void**)&yorder, sizeof(int) * m) != hipSuccess) {
-    set_error("hipMalloc failed");
+  if (pool_get(&Y4, v4 * m, s) != FGA_OK || pool_get(&yorder, sizeof(int) * m, s) != FGA_OK)
     st = FGA_E_NOMEM;
-  }
   if (st == FGA_OK)  // the masses slot is unused by the sort; any finite array of m values works
     st = dt == FGA_F64 ? pack_points<double>(Y, Y, m, Y4, s) : pack_points<float>(Y, Y, m, Y4, s);
   TreeSeg seg{0, m};
@@ -779,8 +777,8 @@ fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const 
     st = dt == FGA_F64
              ? forces_bh_tree<double>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, n, theta, *p, mY, F_out, interactions, s)
              : forces_bh_tree<float>(Y, m, yorder, tr->wide, tr->n_nodes, tr->Xs, n, theta, *p, mY, F_out, interactions, s);
-  if (Y4) (void)hipFree(Y4);
-  if (yorder) (void)hipFree(yorder);
+  pool_free(Y4, s);
+  pool_free(yorder, s);
   fga_tree_destroy(tr);
   return st;
 }
@@ -815,9 +813,8 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     state_free(S);
     return st;
   };
-  if (hipMalloc(&S->X, v4 * n) != hipSuccess || hipMalloc(&S->Q, v4 * m) != hipSuccess ||
-      hipMalloc((void**)&S->st, sizeof(RigidState)) != hipSuccess) {
-    set_error("hipMalloc of the state failed");
+  if (pool_get(&S->X, v4 * n, s) != FGA_OK || pool_get(&S->Q, v4 * m, s) != FGA_OK ||
+      pool_get(&S->st, sizeof(RigidState), s) != FGA_OK) {
     return fail(FGA_E_NOMEM);
   }
   CloudIn cx{X, n}, cy{Y, m};
@@ -838,7 +835,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     if (st != FGA_OK) return fail(st);
     S->n_nodes = off[1] - off[0];
     st = relayout_wide(pre, S->n_nodes, 1, off, &S->nodes, s);
-    (void)hipFree(pre);
+    pool_free(pre, s);
     if (st != FGA_OK) return fail(st);
   }
   const bool bh = p->theta > 0;
@@ -902,17 +899,15 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     max_items = std::max(max_items, (size_t)tmp.n_items);
   }
   const size_t max_chunks = (size_t)completion_chunks((int)max_items);
-  if (hipMalloc((void**)&S->partial, sizeof(double) * 12 * (max_items + max_chunks)) != hipSuccess ||
-      hipMalloc((void**)&S->done, sizeof(unsigned) * (1 + max_chunks)) != hipSuccess) {
-    set_error("hipMalloc of the iteration buffers failed");
+  if (pool_get(&S->partial, sizeof(double) * 12 * (max_items + max_chunks), s) != FGA_OK ||
+      pool_get(&S->done, sizeof(unsigned) * (1 + max_chunks), s) != FGA_OK) {
     return fail(FGA_E_NOMEM);
   }
   if (hipMemsetAsync(S->done, 0, sizeof(unsigned) * (1 + max_chunks), s) != hipSuccess)
     return fail(FGA_E_DEVICE);
   if (p->velocity == FGA_VEL_PARTICLE) {
     const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
-    if (hipMalloc(&S->V, vb) != hipSuccess) {
-      set_error("hipMalloc of the velocities failed");
+    if (pool_get(&S->V, vb, s) != FGA_OK) {
       return fail(FGA_E_NOMEM);
     }
     if (hipMemsetAsync(S->V, 0, vb, s) != hipSuccess) return fail(FGA_E_DEVICE);
@@ -966,7 +961,7 @@ static fga_status first_step_measured(fga_state* S) {
   fga_state::Groups* gt = nullptr;
   FGA_TRY(ensure_groups(S, S->pend_K, S->pend_fi, &gt));
   unsigned* cost = nullptr;
-  FGA_HIP(hipMalloc((void**)&cost, sizeof(unsigned) * gt->n));
+  FGA_TRY(pool_get(&cost, sizeof(unsigned) * gt->n, S->s));
   PairDev pd = S->pd;
   pd.gcost = cost;
   gt->cost.assign(gt->n, 0u);
@@ -977,7 +972,7 @@ static fga_status first_step_measured(fga_state* S) {
       (hipMemcpyAsync(gt->cost.data(), cost, sizeof(unsigned) * gt->n, hipMemcpyDeviceToHost, S->s) != hipSuccess ||
        hipStreamSynchronize(S->s) != hipSuccess))
     st = FGA_E_DEVICE;
-  (void)hipFree(cost);
+  pool_free(cost, S->s);
   if (st != FGA_OK) {
     gt->cost.clear();
     if (st == FGA_E_DEVICE) set_error("first iteration with cost measurement failed");
@@ -1130,20 +1125,15 @@ struct BatchBufs {
   ~BatchBufs() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (own) {
-      (void)hipStreamSynchronize(own);
-      (void)hipStreamDestroy(own);
-    }
+    if (own) (void)hipStreamSynchronize(own);
+    for (void* q : ptrs) pool_free(q, own);  // the stream has drained: reusable at once
+    if (own) (void)hipStreamDestroy(own);
     if (ev) (void)hipEventDestroy(ev);
-    for (void* q : ptrs) (void)hipFree(q);
   }
   template <typename P>
   fga_status get(P** out, size_t bytes) {
-    void* q = nullptr;
-    if (hipMalloc(&q, bytes < 16 ? 16 : bytes) != hipSuccess) {
-      set_error("hipMalloc(%zu) failed", bytes);
-      return FGA_E_NOMEM;
-    }
+    void* q = pool_alloc(bytes < 16 ? 16 : bytes, own);
+    if (!q) return FGA_E_NOMEM;
     ptrs.push_back(q);
     *out = (P*)q;
     return FGA_OK;

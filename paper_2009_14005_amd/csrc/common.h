@@ -30,6 +30,22 @@ void set_error(const char* fmt, ...);
     if (s_ != FGA_OK) return s_;     \
   } while (0)
 
+// ------------------------------------------------- caching device allocator
+// pool.hip: device blocks cached in size classes and reused once the work
+// queued on them before their release has finished. pool_alloc returns nullptr
+// (error message set) on failure; pool_free takes the last stream that used
+// the block.
+void* pool_alloc(size_t bytes, hipStream_t s);
+void pool_free(void* p, hipStream_t s);
+fga_status pool_trim();
+template <typename P>
+inline fga_status pool_get(P** out, size_t bytes, hipStream_t s) {
+  void* p = pool_alloc(bytes, s);
+  if (!p) return FGA_E_NOMEM;
+  *out = (P*)p;
+  return FGA_OK;
+}
+
 // --------------------------------------------------------- vector helpers
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };

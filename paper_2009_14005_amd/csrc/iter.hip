@@ -580,11 +580,9 @@ fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, con
                          const void* mY, const fga_params& p, void* F, hipStream_t s) {
   const int jrn = direct_ranges(m, n);
   void *X4 = nullptr, *part = nullptr;
-  FGA_HIP(hipMalloc(&X4, sizeof(vec4_t<T>) * n));
-  hipError_t e = hipMalloc(&part, sizeof(T) * 3 * (size_t)m * jrn);
-  if (e != hipSuccess) {
-    (void)hipFree(X4);
-    set_error("hipMalloc failed: %s", hipGetErrorString(e));
+  FGA_TRY(pool_get(&X4, sizeof(vec4_t<T>) * n, s));
+  if (pool_get(&part, sizeof(T) * 3 * (size_t)m * jrn, s) != FGA_OK) {
+    pool_free(X4, s);
     return FGA_E_NOMEM;
   }
   k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, (vec4_t<T>*)X4);
@@ -595,10 +593,10 @@ fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, con
   else
     k_forces_direct<T, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
   k_forces_combine<T><<<(int)((m + 255) / 256), 256, 0, s>>>((const T*)part, (int)m, jrn, (const T*)mY, p.G, (T*)F);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(X4);
-  (void)hipFree(part);
+  pool_free(X4, s);
+  pool_free(part, s);
   if (e != hipSuccess) {
     set_error("direct force kernels failed: %s", hipGetErrorString(e));
     return FGA_E_DEVICE;
@@ -621,7 +619,7 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
                           const fga_params& p, const void* mY, void* F, long long* interactions,
                           hipStream_t s) {
   unsigned long long* cnt = nullptr;
-  FGA_HIP(hipMalloc(&cnt, sizeof(unsigned long long)));
+  FGA_TRY(pool_get(&cnt, sizeof(unsigned long long), s));
   (void)hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
   const int K = sizeof(T) == 4 ? p.group_width / kWave : 0;  // 64 -> 1, 128 -> 2
   if constexpr (sizeof(T) == 4) {
@@ -649,7 +647,7 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(cnt);
+  pool_free(cnt, s);
   if (e != hipSuccess) {
     set_error("BH force kernel failed: %s", hipGetErrorString(e));
     return FGA_E_DEVICE;

@@ -384,8 +384,9 @@ void plan_add(Plan& pl, const void* p, int64_t n, int pair, int is_y, int64_t ou
 
 struct DevBufs {
   void* mem = nullptr;
+  hipStream_t s = nullptr;
   ~DevBufs() {
-    if (mem) (void)hipFree(mem);
+    if (mem) pool_free(mem, s);
   }
 };
 
@@ -424,7 +425,8 @@ fga_status prep_impl(int npairs, const CloudIn* X, const CloudIn* Y, const fga_p
   size_t o_hist = o_ps + sizeof(PairStats) * npairs;
   size_t total = o_hist + sizeof(unsigned) * pl.hist_cells;
   DevBufs buf;
-  FGA_HIP(hipMalloc(&buf.mem, total));
+  buf.s = s;
+  FGA_TRY(pool_get(&buf.mem, total, s));
   char* base = (char*)buf.mem;
   Seg* dseg = (Seg*)(base + o_seg);
   Chunk* dch = (Chunk*)(base + o_ch);
@@ -497,7 +499,8 @@ fga_status masses_impl(const void* pts, int64_t n, const fga_params& p, int norm
   size_t o_hist = o_ss + sizeof(SegStats);
   size_t total = o_hist + sizeof(unsigned) * pl.hist_cells;
   DevBufs buf;
-  FGA_HIP(hipMalloc(&buf.mem, total));
+  buf.s = s;
+  FGA_TRY(pool_get(&buf.mem, total, s));
   char* base = (char*)buf.mem;
   Seg* dseg = (Seg*)(base + o_seg);
   Chunk* dch = (Chunk*)(base + o_ch);

@@ -574,19 +574,18 @@ __global__ void k_remap_off(const unsigned* NI, int nseg, int* node_off) {
 }
 
 // ------------------------------------------------------------ host driver
+// Temporaries of one build, from the caching allocator, returned at scope end.
 struct Scratch {
+  hipStream_t s;
   std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
   ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) pool_free(p, s);
   }
   template <typename P>
   fga_status get(P** out, size_t bytes) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes < 16 ? 16 : bytes);
-    if (e != hipSuccess) {
-      set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-      return FGA_E_NOMEM;
-    }
+    void* p = pool_alloc(bytes < 16 ? 16 : bytes, s);
+    if (!p) return FGA_E_NOMEM;
     ptrs.push_back(p);
     *out = (P*)p;
     return FGA_OK;
@@ -666,7 +665,7 @@ template <typename T>
 fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t ntot,
                        int leaf_size, BHNode** nodes_out, int* node_off_host, int** order_out,
                        int* stats_host, hipStream_t s) {
-  Scratch sc;
+  Scratch sc(s);
   vec4_t<T>* X = (vec4_t<T>*)Xpacked;
   vec4_t<T>* Xs;
   u64* codes;
@@ -676,14 +675,12 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   FGA_TRY(sc.get(&codes, sizeof(u64) * ntot));
   FGA_TRY(sc.get(&box, sizeof(SegBox) * nseg));
   if (order_out) {
-    void* p = nullptr;
-    FGA_HIP(hipMalloc(&p, sizeof(unsigned) * ntot));
-    perm = (unsigned*)p;
-    *order_out = (int*)p;
+    FGA_TRY(pool_get(&perm, sizeof(unsigned) * ntot, s));
+    *order_out = (int*)perm;
   }
   fga_status st = morton_sort<T>(nseg, segs, X, ntot, Xs, perm, codes, box, sc, s);
   if (st != FGA_OK) {
-    if (perm) (void)hipFree(perm);
+    if (perm) pool_free(perm, s);
     return st;
   }
   FGA_HIP(hipMemcpyAsync(X, Xs, sizeof(vec4_t<T>) * ntot, hipMemcpyDeviceToDevice, s));
@@ -722,14 +719,10 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   FGA_HIP(hipStreamSynchronize(s));
   BHNode* nodes = nullptr;
   {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(BHNode) * (total ? total : 1));
-    if (e != hipSuccess) {
-      if (perm) (void)hipFree(perm);
-      set_error("hipMalloc of %u tree nodes failed", total);
+    if (pool_get(&nodes, sizeof(BHNode) * (total ? total : 1), s) != FGA_OK) {
+      if (perm) pool_free(perm, s);
       return FGA_E_NOMEM;
     }
-    nodes = (BHNode*)p;
   }
   const int L = leaf_size > 1 ? leaf_size : 1;
   unsigned* keep = nullptr;
@@ -750,10 +743,9 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
     FGA_HIP(hipMemcpyAsync(&kept, NI + total, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     FGA_HIP(hipStreamSynchronize(s));
     BHNode* packed = nullptr;
-    if (hipMalloc((void**)&packed, sizeof(BHNode) * (kept ? kept : 1)) != hipSuccess) {
-      (void)hipFree(nodes);
-      if (perm) (void)hipFree(perm);
-      set_error("hipMalloc of %u tree nodes failed", kept);
+    if (pool_get(&packed, sizeof(BHNode) * (kept ? kept : 1), s) != FGA_OK) {
+      pool_free(nodes, s);
+      if (perm) pool_free(perm, s);
       return FGA_E_NOMEM;
     }
     FGA_HIP(hipMemsetAsync(stats + 1, 0, sizeof(unsigned) * 2, s));
@@ -761,7 +753,7 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
                                                                       total, packed, stats);
     k_remap_off<<<(nseg + 64) / 64, 64, 0, s>>>(NI, nseg, node_off);
     FGA_HIP(hipStreamSynchronize(s));
-    (void)hipFree(nodes);
+    pool_free(nodes, s);
     nodes = packed;
   }
   unsigned hstats[4];
@@ -771,8 +763,8 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   if (e1 == hipSuccess) e1 = hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s);
   if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
   if (e1 != hipSuccess) {
-    (void)hipFree(nodes);
-    if (perm) (void)hipFree(perm);
+    pool_free(nodes, s);
+    if (perm) pool_free(perm, s);
     set_error("tree build failed: %s", hipGetErrorString(e1));
     return FGA_E_DEVICE;
   }
@@ -854,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_relayout(const BHNode* pre, int tota
 
 fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node_off_host,
                          BHWide** out, hipStream_t s) {
-  Scratch sc;
+  Scratch sc(s);
   int* doff;
   unsigned *nch, *G, *bsum;
   const int nb = (int)(((int64_t)total + kScanTile) / kScanTile);
@@ -866,12 +858,12 @@ fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node
   k_nchild<<<(total + kBlock) / kBlock, kBlock, 0, s>>>(pre, total, doff, nseg, nch);
   FGA_TRY((exclusive_scan<unsigned, LoadCnt>(LoadCnt{nch}, (int64_t)total, G, bsum, s)));
   BHWide* w = nullptr;
-  FGA_HIP(hipMalloc((void**)&w, sizeof(BHWide) * (total ? total : 1)));
+  FGA_TRY(pool_get(&w, sizeof(BHWide) * (total ? total : 1), s));
   k_relayout<<<(total + kBlock - 1) / kBlock, kBlock, 0, s>>>(pre, total, doff, nseg, nch, G, w);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    (void)hipFree(w);
+    pool_free(w, s);
     set_error("child-block relayout failed: %s", hipGetErrorString(e));
     return FGA_E_DEVICE;
   }
@@ -884,7 +876,7 @@ fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node
 template <typename T>
 fga_status sort_points_morton(int nseg, const TreeSeg* segs, void* Q, int64_t ntot, int* perm,
                               hipStream_t s) {
-  Scratch sc;
+  Scratch sc(s);
   vec4_t<T>* Qs;
   SegBox* box;
   FGA_TRY(sc.get(&Qs, sizeof(vec4_t<T>) * ntot));

@@ -353,6 +353,20 @@ def test_step_resume_is_bit_identical():
     assert np.array_equal(Ra, Rb) and np.array_equal(ta, tb)
 
 
+def test_buffer_cache_reuse_and_trim():
+    """Registrations reuse cached device buffers; results do not depend on
+    whether the buffers came from the cache or from a fresh allocation."""
+    X, Y, _, _ = synth.mixture_pair(16, per_comp=256, m=1500)
+    prm = fga.default_params(theta=0.5, max_iter=40, tol=0.0)
+    fga.trim_cache()
+    R0, t0, _ = fga.register(dev(X), dev(Y), prm)
+    outs = [fga.register(dev(X), dev(Y), prm)[:2] for _ in range(3)]
+    fga.trim_cache()
+    outs.append(fga.register(dev(X), dev(Y), prm)[:2])
+    for R, t in outs:
+        assert np.array_equal(R, R0) and np.array_equal(t, t0)
+
+
 def test_deterministic_repeat():
     X, Y, _, _ = synth.mixture_pair(13, per_comp=512, m=3000)
     out = [fga_run(X, Y, theta=0.5, max_iter=40)[:2] for _ in range(2)]
