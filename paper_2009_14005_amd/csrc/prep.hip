@@ -225,18 +225,37 @@ __device__ inline double niv_value(unsigned n_c, double v_cell, double v_ball) {
 }
 
 // ---------------------------------------------------------------- stage D
+// Counts per lattice cell. Up to 16^3 cells the block counts its chunk in
+// LDS and adds only its non-zero cells to the global histogram (the points of
+// a scan crowd into few cells, where global atomics would queue up).
+constexpr int kHistLds = 4096;
 template <typename Tin>
 __global__ __launch_bounds__(kBlock) void k_hist(const Seg* segs, const Chunk* chunks,
                                                  const SegStats* ss, const PairStats* ps,
                                                  PrepConsts c, unsigned* hist) {
+  __shared__ unsigned lh[kHistLds];
   const Chunk ch = chunks[blockIdx.x];
   const Seg sg = segs[ch.seg];
   const SegStats st = ss[ch.seg];
+  const int cells = c.rho * c.rho * c.rho;
+  if (cells > kHistLds) {
+    for (int64_t k = threadIdx.x; k < ch.count; k += kBlock) {
+      double x[3];
+      normalised<Tin>(sg, st, ps, c, ch.start + k, x);
+      atomicAdd(&hist[sg.hist_off + niv_cell(x, st, c.rho)], 1u);
+    }
+    return;
+  }
+  for (int k = (int)threadIdx.x; k < cells; k += kBlock) lh[k] = 0u;
+  __syncthreads();
   for (int64_t k = threadIdx.x; k < ch.count; k += kBlock) {
     double x[3];
     normalised<Tin>(sg, st, ps, c, ch.start + k, x);
-    atomicAdd(&hist[sg.hist_off + niv_cell(x, st, c.rho)], 1u);
+    atomicAdd(&lh[niv_cell(x, st, c.rho)], 1u);
   }
+  __syncthreads();
+  for (int k = (int)threadIdx.x; k < cells; k += kBlock)
+    if (lh[k]) atomicAdd(&hist[sg.hist_off + k], lh[k]);
 }
 
 // ---------------------------------------------------------------- stage E

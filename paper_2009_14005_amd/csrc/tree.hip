@@ -505,7 +505,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const u64*
                                                  const unsigned char* leaf0, const int* own_d,
                                                  const int* own_a, const int* own_b,
                                                  const unsigned* P, const D4* W, BHNode* nodes,
-                                                 unsigned* stats, int L, unsigned* keep) {
+                                                 unsigned cap, unsigned* stats, int L,
+                                                 unsigned* keep) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
   const int sg = find_seg(sr, nseg, k);
@@ -533,8 +534,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const u64*
       for (int q = a; q < b && twig; ++q) twig = lcp_digits(codes[q], codes[q + 1]) == d;
       if (twig) nd.l2 = -nd.l2;
     }
-    if (L > 1) prune_mark(codes, sr[sg], a, b, L, lroot, &nd, keep + idx);
-    nodes[idx] = nd;
+    if (idx >= cap) {  // more nodes than the array holds: reported, never written
+      atomicOr(&stats[3], 1u);
+    } else {
+      if (L > 1) prune_mark(codes, sr[sg], a, b, L, lroot, &nd, keep + idx);
+      nodes[idx] = nd;
+    }
     atomicMax(&stats[0], (unsigned)d);
     atomicAdd(&stats[2], 1u);
   }
@@ -556,8 +561,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const u64*
     nd.last = (int)e - s0;
     const double l = ldexp(lroot, -kQBits);  // a leaf of several points is a depth-20 cell
     nd.l2 = (float)(l * l);
-    if (L > 1) prune_mark(codes, sr[sg], k, e, L, lroot, &nd, keep + idx);
-    nodes[idx] = nd;
+    if (idx >= cap) {
+      atomicOr(&stats[3], 1u);
+    } else {
+      if (L > 1) prune_mark(codes, sr[sg], k, e, L, lroot, &nd, keep + idx);
+      nodes[idx] = nd;
+    }
     atomicAdd(&stats[1], 1u);
   }
 }
@@ -714,24 +723,26 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   k_count<<<nb, kBlock, 0, s>>>(mask, leaf0, ntot, cnt);
   FGA_TRY((exclusive_scan<unsigned, LoadCnt>(LoadCnt{cnt}, ntot, P, bsumU, s)));
   FGA_TRY((exclusive_scan<D4, LoadMass<T>>(LoadMass<T>{X}, ntot, W, bsumD, s)));
-  unsigned total = 0;
-  FGA_HIP(hipMemcpyAsync(&total, P + ntot, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-  FGA_HIP(hipStreamSynchronize(s));
-  BHNode* nodes = nullptr;
-  {
-    if (pool_get(&nodes, sizeof(BHNode) * (total ? total : 1), s) != FGA_OK) {
-      if (perm) pool_free(perm, s);
-      return FGA_E_NOMEM;
-    }
-  }
+  // a compressed octree of n points has at most 2 n - 1 nodes: the node array
+  // is sized for that, so the count is not needed on the host before k_emit
   const int L = leaf_size > 1 ? leaf_size : 1;
+  unsigned total = (unsigned)(2 * ntot);
+  if (L > 1) {  // the leaf-size pass sizes its arrays by the exact count
+    FGA_HIP(hipMemcpyAsync(&total, P + ntot, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipStreamSynchronize(s));
+  }
+  BHNode* nodes = nullptr;
+  if (pool_get(&nodes, sizeof(BHNode) * (total ? total : 1), s) != FGA_OK) {
+    if (perm) pool_free(perm, s);
+    return FGA_E_NOMEM;
+  }
   unsigned* keep = nullptr;
   if (L > 1) {
     FGA_TRY(sc.get(&keep, sizeof(unsigned) * (total + 1)));
     FGA_HIP(hipMemsetAsync(keep, 0, sizeof(unsigned) * (total + 1), s));
   }
   k_emit<T><<<nb, kBlock, 0, s>>>(X, codes, sr, box, nseg, ntot, mask, leaf0, own_d, own_a, own_b, P, W,
-                                  nodes, stats, L, keep);
+                                  nodes, total ? total : 1, stats, L, keep);
   k_seg_nodes<<<(nseg + 63) / 64, 64, 0, s>>>(sr, nseg, P, node_off);
   if (L > 1) {  // drop the cells below the leaf size and compact the preorder
     unsigned *NI, *bsumK;
@@ -766,6 +777,12 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
     pool_free(nodes, s);
     if (perm) pool_free(perm, s);
     set_error("tree build failed: %s", hipGetErrorString(e1));
+    return FGA_E_DEVICE;
+  }
+  if (hstats[3]) {
+    pool_free(nodes, s);
+    if (perm) pool_free(perm, s);
+    set_error("tree build: node count above the 2 n - 1 bound");
     return FGA_E_DEVICE;
   }
   stats_host[0] = (int)hstats[0];
@@ -860,8 +877,7 @@ fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node
   BHWide* w = nullptr;
   FGA_TRY(pool_get(&w, sizeof(BHWide) * (total ? total : 1), s));
   k_relayout<<<(total + kBlock - 1) / kBlock, kBlock, 0, s>>>(pre, total, doff, nseg, nch, G, w);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     pool_free(w, s);
     set_error("child-block relayout failed: %s", hipGetErrorString(e));
@@ -884,7 +900,6 @@ fga_status sort_points_morton(int nseg, const TreeSeg* segs, void* Q, int64_t nt
   FGA_TRY(morton_sort<T>(nseg, segs, (vec4_t<T>*)Q, ntot, Qs, (unsigned*)perm, nullptr, box, sc,
                          s));
   FGA_HIP(hipMemcpyAsync(Q, Qs, sizeof(vec4_t<T>) * ntot, hipMemcpyDeviceToDevice, s));
-  FGA_HIP(hipStreamSynchronize(s));
   return FGA_OK;
 }
 
