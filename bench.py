@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--plain-pairs", type=int, default=32,
                     help="pairs of the batch timed with sequential plain solves")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="also run the 131,072-point precision study (force errors and final pose per mode)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (a known-size kernel for HBM counters)")
     return ap.parse_args()
@@ -131,7 +133,7 @@ def main():
         "pct_fp32_vector_peak": 100.0 * value * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
         "accuracy_vs_ground_truth": {"phi_deg": phi, "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag)},
         "roofline": {
-            "kernel": "k_iteration<float, BH, FP32_KAHAN> (fused force + ODE + moments + Kabsch)",
+            "kernel": KERNEL_NAMES.get(r1.traversal, "?") + " (fused force + ODE + moments + Kabsch)",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VECTOR / 1e12,
@@ -148,9 +150,18 @@ def main():
     if not args.no_extras:
         out["direct"] = bench_direct(fga, torch, synth, dev, stream)
         out["batched"] = bench_batched(fga, torch, synth, dev, args)
+        out["mixture_fp64_direct"] = bench_mixture(fga, torch, synth, dev)
+    if args.precision_study:
+        out["precision_study"] = precision_study(fga, torch, synth, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y)
     print(json.dumps(out), flush=True)
+
+
+KERNEL_NAMES = {0: "k_iteration<float, direct, FP32_KAHAN>",
+                1: "k_iteration<float, BH per-particle walk, FP32_KAHAN>",
+                64: "k_iteration_group<FP32_KAHAN, 1> (group walk, 64 particles per wave)",
+                128: "k_iteration_group<FP32_KAHAN, 2> (group walk, 128 particles per wave)"}
 
 
 def measured_traffic():
@@ -194,6 +205,68 @@ def bench_direct(fga, torch, synth, dev, stream):
                      "tflops": ips * FLOP_PER_INTERACTION / 1e12,
                      "frac_fp32_vector_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR}
         log(f"  {name}: {ms:.2f} ms/iteration, {ips:.3e} interactions/s")
+    return res
+
+
+def bench_mixture(fga, torch, synth, dev):
+    """The 1,024 / 900-point Gaussian-mixture registration: direct sum in
+    FP64, 200 fixed iterations (launch-bound at this size)."""
+    X, Y, Rg, tg = synth.mixture_pair()
+    Xd = torch.as_tensor(X, dtype=torch.float64, device=dev)
+    Yd = torch.as_tensor(Y, dtype=torch.float64, device=dev)
+    p = fga.default_params(theta=0.0, tol=0.0, max_iter=200, precision=fga.PREC_FP64)
+    fga.register(Xd, Yd, p)
+    torch.cuda.synchronize()
+    n = 10
+    t0 = time.perf_counter()
+    for _ in range(n):
+        R, t, rep = fga.register(Xd, Yd, p)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / n * 1e3
+    phi = float(np.degrees(np.arccos(np.clip(0.5 * (np.trace(Rg.T @ R) - 1), -1, 1))))
+    log(f"mixture FP64 direct: {ms:.2f} ms per 200-iteration registration")
+    return {"ms_per_registration": ms, "iterations": rep.iters, "interactions_per_s": rep.interactions / (ms * 1e-3),
+            "phi_deg_vs_ground_truth": phi}
+
+
+def precision_study(fga, torch, synth, dev):
+    """131,072 x 131,072 direct sums: per precision mode, the relative force
+    error on 512 sampled template points against the FP64 oracle (max and
+    median), and the final pose after 100 iterations against the FP64 device
+    path on the same FP32-rounded coordinates (whose agreement with the
+    oracle's Alg. 2 is pinned on the 1,024-point mixture to 1e-11), as rotation
+    angle and translation / diagonal."""
+    import oracle
+    oracle.build(force=False)
+    X, Y, _, _ = synth.precision_pair()
+    X32 = np.ascontiguousarray(X, dtype=np.float32).astype(np.float64)
+    Y32 = np.ascontiguousarray(Y, dtype=np.float32).astype(np.float64)
+    n = len(X32)
+    mX = np.full(n, 1.0 / n)
+    idx = np.random.default_rng(1).choice(len(Y32), 512, replace=False)
+    ref = oracle.direct_forces(Y32[idx], X32, mX)
+    diag = float(np.linalg.norm(X.max(0) - X.min(0)))
+    log("precision study: FP64 reference registration")
+    p64 = fga.default_params(theta=0.0, tol=0.0, max_iter=100, precision=fga.PREC_FP64)
+    R64, t64, _ = fga.register(torch.as_tensor(X32, dtype=torch.float64, device=dev),
+                               torch.as_tensor(Y32, dtype=torch.float64, device=dev), p64)
+    res = {}
+    modes = (("fp32", fga.PREC_FP32), ("fp32_kahan", fga.PREC_FP32_KAHAN), ("fp32_all", fga.PREC_FP32_ALL))
+    Xd = torch.as_tensor(X32, dtype=torch.float32, device=dev)
+    Yd = torch.as_tensor(Y32, dtype=torch.float32, device=dev)
+    for name, prec in modes:
+        prm = fga.default_params(precision=prec)
+        F, _ = fga.forces(Yd, Xd, torch.as_tensor(mX, dtype=torch.float32, device=dev), None, 0.0, prm)
+        Fs = F.cpu().numpy().astype(np.float64)[idx]
+        e = np.linalg.norm(Fs - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        R, t, _ = fga.register(Xd, Yd,
+                               fga.default_params(theta=0.0, tol=0.0, max_iter=100, precision=prec))
+        A = R64.T @ R  # small-angle form: arccos of the trace saturates below ~1e-6 deg
+        phi = float(np.degrees(np.arcsin(min(1.0, 0.5 * np.linalg.norm(
+            [A[2, 1] - A[1, 2], A[0, 2] - A[2, 0], A[1, 0] - A[0, 1]])))))
+        res[name] = {"force_rel_err_max": float(e.max()), "force_rel_err_median": float(np.median(e)),
+                     "rotation_deg_vs_fp64": phi, "translation_vs_fp64_over_diag": float(np.linalg.norm(t - t64) / diag)}
+        log(f"  {name}: force err max {e.max():.2e} median {np.median(e):.2e}; pose {phi:.2e} deg")
     return res
 
 

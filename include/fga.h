@@ -111,6 +111,8 @@ typedef struct {
   double last_dT2;        /* ||T_k - T_{k-1}||_F^2 of the last iteration (normalised frame) */
   long long interactions; /* force interactions evaluated (accepted nodes + leaf points) */
   double ms_total;        /* wall time of the call in milliseconds */
+  int traversal;          /* force kernel in use: 0 = direct sum (theta = 0), 1 = per-particle
+                             Barnes-Hut walk, 64 or 128 = group walk of that many particles */
 } fga_report;
 
 typedef struct fga_state fga_state;

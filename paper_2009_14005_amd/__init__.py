@@ -67,7 +67,7 @@ class Params(ctypes.Structure):
 class _CReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int),
                 ("last_dT2", ctypes.c_double), ("interactions", ctypes.c_longlong),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("traversal", ctypes.c_int)]
 
 
 @dataclass
@@ -77,10 +77,11 @@ class Report:
     last_dT2: float
     interactions: int
     ms_total: float
+    traversal: int = 0
 
     @staticmethod
     def _from(c: _CReport) -> "Report":
-        return Report(c.iters, bool(c.converged), c.last_dT2, c.interactions, c.ms_total)
+        return Report(c.iters, bool(c.converged), c.last_dT2, c.interactions, c.ms_total, c.traversal)
 
 
 _lib = None

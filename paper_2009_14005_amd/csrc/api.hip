@@ -1042,6 +1042,7 @@ fga_status fga_state_get(const fga_state* S, double R[9], double t[3], fga_repor
     rep->last_dT2 = h.dT2;
     rep->interactions = h.interactions;
     rep->ms_total = 0.0;
+    rep->traversal = !S->nodes ? 0 : S->pd.group ? kWave * S->pd.group : 1;
   }
   if (h.flags & 2) {
     set_error("Barnes-Hut group walk: traversal stack overflow (forces incomplete)");
@@ -1387,6 +1388,11 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
       reps[k].last_dT2 = hs[k].dT2;
       reps[k].interactions = hs[k].interactions;
       reps[k].ms_total = ms;
+      reps[k].traversal = grouped ? kWave : nodes ? 1 : 0;
+    }
+    if ((hs[k].flags & 2) && result == FGA_OK) {
+      set_error("pair %d: Barnes-Hut group walk: traversal stack overflow (forces incomplete)", k);
+      result = FGA_E_DEVICE;
     }
     if ((hs[k].flags & 1) && result == FGA_OK) {
       set_error("pair %d: the template is collinear; the Kabsch rotation is undetermined", k);

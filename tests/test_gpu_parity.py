@@ -255,7 +255,7 @@ def test_register_config0_fp64_direct():
     X, Y, _, _ = synth.mixture_pair()
     ref = oracle_run(X, Y, 0.0, 200)
     R, t, rep = fga_run(X, Y, torch.float64, theta=0.0, max_iter=200, precision=fga.PREC_FP64)
-    assert rep.iters == 200
+    assert rep.iters == 200 and rep.traversal == 0
     phi, dtn = check_transform(R, t, ref, X)
     # arccos cannot resolve angles below ~1e-6 deg; compare the matrices directly
     assert np.abs(R - ref["R"]).max() < 1e-11 and dtn < 1e-10, (np.abs(R - ref["R"]).max(), dtn)
@@ -284,6 +284,7 @@ def test_register_config0_bh_traversals(gw):
     R, t, rep = fga_run(X, Y, theta=0.5, max_iter=200, group_width=gw)
     check_transform(R, t, ref, X)
     assert rep.interactions > 0
+    assert rep.traversal == gw
 
 
 @pytest.mark.parametrize("prec", [fga.PREC_FP32, fga.PREC_FP32_ALL])
@@ -401,6 +402,7 @@ def test_batch_matches_plain(gw):
     R, t, reps = fga.register_batch(Xs, Ys, prm)
     for k, (X, Y, _, _) in enumerate(pairs):
         R1, t1, rep1 = fga.register(dev(X), dev(Y), prm)
+        assert reps[k].traversal == (1 if gw == 1 else 64)
         if gw == 1:
             assert reps[k].iters == rep1.iters
         else:
