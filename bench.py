@@ -251,7 +251,10 @@ def precision_study(fga, torch, synth, dev):
     R64, t64, _ = fga.register(torch.as_tensor(X32, dtype=torch.float64, device=dev),
                                torch.as_tensor(Y32, dtype=torch.float64, device=dev), p64)
     res = {}
-    modes = (("fp32", fga.PREC_FP32), ("fp32_kahan", fga.PREC_FP32_KAHAN), ("fp32_all", fga.PREC_FP32_ALL))
+    # pure FP32 (force tiles and moment sums); FP32 tiles with FP64 moment
+    # and state reductions; the same with Kahan-compensated tiles
+    modes = (("pure_fp32", fga.PREC_FP32_ALL), ("fp32_tiles_fp64_reductions", fga.PREC_FP32),
+             ("fp32_kahan_tiles_fp64_reductions", fga.PREC_FP32_KAHAN))
     Xd = torch.as_tensor(X32, dtype=torch.float32, device=dev)
     Yd = torch.as_tensor(Y32, dtype=torch.float32, device=dev)
     for name, prec in modes:

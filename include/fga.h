@@ -66,7 +66,10 @@ typedef enum { FGA_MASS_NIV = 0, FGA_MASS_UNIFORM = 1 } fga_mass_mode;
 /* Arithmetic of the force sum. The displacement moments, the rigid state and
  * the Kabsch step are FP64 in every mode except FP32_ALL.
  * FP32:       FP32 positions and forces, plain per-lane accumulation.
- * FP32_KAHAN: FP32 positions and forces, tile sums added with Kahan compensation.
+ * FP32_KAHAN: FP32 positions and forces, tile sums added with Kahan compensation
+ *             (direct sum: tiles of 64 reference points; group walk: each
+ *             flushed interaction list). The per-particle Barnes-Hut walk
+ *             accumulates plainly in every FP32 mode.
  * FP64:       FP64 positions and forces (requires FGA_F64 data).
  * FP32_ALL:   like FP32, and the per-particle moments are also summed in FP32. */
 typedef enum {

@@ -866,7 +866,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     } else {
       for (int c = 1; c <= (bh ? 16 : 64); c *= 2) {
         const int64_t per = n / c;
-        if ((c == 1 || (per >= (bh ? 256 : 1024) && tl * c <= 65536)) && tl * c <= 262144)
+        if ((c == 1 || (per >= (bh ? 256 : 64) && tl * c <= 65536)) && tl * c <= 262144)
           cands.push_back(md << 8 | c);
       }
     }

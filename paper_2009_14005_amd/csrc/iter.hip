@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_bh(const T* Y, const int* yor
 
 // Group traversal for fga_forces: every wave takes 64 K consecutive template
 // particles of the Morton order yorder and writes F_i = G m_Y,i acc_i.
-template <int K>
+template <int K, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const int* yorder, int m,
                                                          const BHWide* nodes, int n_nodes,
                                                          const float4* Xs, int n_points,
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, true>(nodes, n_nodes, Xs, n_points, 0, 1, 1, theta2, eps2, valid,
+  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, 1, theta2, eps2, valid,
                                     y, acc, cnt, entries, g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -588,7 +588,7 @@ fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, con
   k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, (vec4_t<T>*)X4);
   const dim3 grid((unsigned)((m + kBlock - 1) / kBlock), (unsigned)jrn);
   const T eps2 = (T)(p.eps * p.eps);
-  if (sizeof(T) == 8 || p.precision != FGA_PREC_FP32)
+  if (sizeof(T) == 8 || p.precision == FGA_PREC_FP32_KAHAN)
     k_forces_direct<T, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
   else
     k_forces_direct<T, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
@@ -625,16 +625,19 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
   if constexpr (sizeof(T) == 4) {
     if (K == 1 || K == 2) {
       const int tp = kBlock * K;
-      if (K == 1)
-        k_forces_group<1><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
-            (const float*)Y, yorder, (int)m, nodes, n_nodes, (const float4*)Xs, (int)n,
-            (float)(theta * theta),
-            (float)(p.eps * p.eps), (const float*)mY, p.G, (float*)F, cnt);
+      const dim3 grid((unsigned)((m + tp - 1) / tp));
+      const float t2 = (float)(theta * theta), e2 = (float)(p.eps * p.eps);
+      const float* Yf = (const float*)Y;
+      const float4* X4 = (const float4*)Xs;
+      const bool kahan = p.precision == FGA_PREC_FP32_KAHAN;
+      if (K == 1 && kahan)
+        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
+      else if (K == 1)
+        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
+      else if (kahan)
+        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
       else
-        k_forces_group<2><<<(int)((m + tp - 1) / tp), kBlock, 0, s>>>(
-            (const float*)Y, yorder, (int)m, nodes, n_nodes, (const float4*)Xs, (int)n,
-            (float)(theta * theta),
-            (float)(p.eps * p.eps), (const float*)mY, p.G, (float*)F, cnt);
+        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
     }
   }
   if (K != 1 && K != 2) {

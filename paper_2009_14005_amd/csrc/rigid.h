@@ -27,64 +27,80 @@ FGA_HD double m3_det(const double* A) {
          A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 
+// One Jacobi rotation of columns P < Q of W (and of V alongside) that makes
+// them orthogonal; false if they already are, to 1e-15 relative. The column
+// dot product carries rounding of a few ulps (2.2e-16 each), so a tighter
+// threshold is usually never met and the sweeps run to their cap; at 1e-15
+// the solve ends after 3 to 5 sweeps. P and Q are compile-time so that W and
+// V stay in registers.
+template <int P, int Q>
+FGA_HD bool jacobi_rotate(double* W, double* V) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    al += W[3 * i + P] * W[3 * i + P];
+    be += W[3 * i + Q] * W[3 * i + Q];
+    ga += W[3 * i + P] * W[3 * i + Q];
+  }
+  if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) return false;
+  const double ze = (be - al) / (2.0 * ga);
+  const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+  const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+  for (int i = 0; i < 3; ++i) {
+    const double wp = W[3 * i + P], wq = W[3 * i + Q];
+    W[3 * i + P] = c * wp - sn * wq;
+    W[3 * i + Q] = sn * wp + c * wq;
+    const double vp = V[3 * i + P], vq = V[3 * i + Q];
+    V[3 * i + P] = c * vp - sn * vq;
+    V[3 * i + Q] = sn * vp + c * vq;
+  }
+  return true;
+}
+
+// Swaps columns P and Q of W and V and entries P and Q of nrm.
+template <int P, int Q>
+FGA_HD void swap_columns(double* W, double* V, double* nrm) {
+  for (int i = 0; i < 3; ++i) {
+    double t = W[3 * i + P];
+    W[3 * i + P] = W[3 * i + Q];
+    W[3 * i + Q] = t;
+    t = V[3 * i + P];
+    V[3 * i + P] = V[3 * i + Q];
+    V[3 * i + Q] = t;
+  }
+  const double t = nrm[P];
+  nrm[P] = nrm[Q];
+  nrm[Q] = t;
+}
+
 // One-sided (Hestenes) Jacobi SVD of a 3x3 matrix: A = U diag(s) V^T with
-// s sorted in descending order. Columns of W = A V are rotated pairwise until
-// they are mutually orthogonal; then s_k = |W_k| and U_k = W_k / s_k.
-// Columns belonging to zero singular values are left as zero in U.
+// s sorted in descending order. Columns of W = A V are rotated pairwise, in
+// the order (0,1), (0,2), (1,2), until they are mutually orthogonal; then
+// s_k = |W_k| and U_k = W_k / s_k. Columns belonging to zero singular values
+// are left as zero in U. Every array index is a compile-time constant, so the
+// device keeps the whole solve in registers.
 FGA_HD void svd3(const double* A, double* U, double* s, double* V) {
   double W[9];
   for (int k = 0; k < 9; ++k) W[k] = A[k];
   for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    bool rotated = false;
-    for (int pair = 0; pair < 3; ++pair) {
-      const int p = pair == 2 ? 1 : 0;
-      const int q = pair == 0 ? 1 : 2;
-      double al = 0.0, be = 0.0, ga = 0.0;
-      for (int i = 0; i < 3; ++i) {
-        al += W[3 * i + p] * W[3 * i + p];
-        be += W[3 * i + q] * W[3 * i + q];
-        ga += W[3 * i + p] * W[3 * i + q];
-      }
-      if (ga == 0.0 || fabs(ga) <= 1e-17 * sqrt(al * be)) continue;
-      rotated = true;
-      const double ze = (be - al) / (2.0 * ga);
-      const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
-      const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
-      for (int i = 0; i < 3; ++i) {
-        const double wp = W[3 * i + p], wq = W[3 * i + q];
-        W[3 * i + p] = c * wp - sn * wq;
-        W[3 * i + q] = sn * wp + c * wq;
-        const double vp = V[3 * i + p], vq = V[3 * i + q];
-        V[3 * i + p] = c * vp - sn * vq;
-        V[3 * i + q] = sn * vp + c * vq;
-      }
-    }
+    bool rotated = jacobi_rotate<0, 1>(W, V);
+    rotated = jacobi_rotate<0, 2>(W, V) || rotated;
+    rotated = jacobi_rotate<1, 2>(W, V) || rotated;
     if (!rotated) break;
   }
-  int idx[3] = {0, 1, 2};
   double nrm[3];
   for (int k = 0; k < 3; ++k)
     nrm[k] = sqrt(W[k] * W[k] + W[3 + k] * W[3 + k] + W[6 + k] * W[6 + k]);
-  // sort columns by singular value, descending (three compare-swaps)
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2 - a; ++b)
-      if (nrm[idx[b]] < nrm[idx[b + 1]]) {
-        int tmp = idx[b];
-        idx[b] = idx[b + 1];
-        idx[b + 1] = tmp;
-      }
-  double V2[9];
+  // sort columns by singular value, descending (three compare-swaps; equal
+  // values keep their order)
+  if (nrm[0] < nrm[1]) swap_columns<0, 1>(W, V, nrm);
+  if (nrm[1] < nrm[2]) swap_columns<1, 2>(W, V, nrm);
+  if (nrm[0] < nrm[1]) swap_columns<0, 1>(W, V, nrm);
   for (int k = 0; k < 3; ++k) {
-    const int c = idx[k];
-    s[k] = nrm[c];
-    const double inv = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
-    for (int i = 0; i < 3; ++i) {
-      U[3 * i + k] = W[3 * i + c] * inv;
-      V2[3 * i + k] = V[3 * i + c];
-    }
+    s[k] = nrm[k];
+    const double inv = nrm[k] > 0.0 ? 1.0 / nrm[k] : 0.0;
+    for (int i = 0; i < 3; ++i) U[3 * i + k] = W[3 * i + k] * inv;
   }
-  for (int k = 0; k < 9; ++k) V[k] = V2[k];
 }
 
 // Eq. (R_Kabsch): C = U S V^T, R = U diag(1, 1, sgn det(U V^T)) V^T, sgn(0) = +1.

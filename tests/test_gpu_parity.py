@@ -104,14 +104,14 @@ def test_direct_forces_fp64():
     assert np.allclose(F.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
-def test_direct_forces_plain_fp32_mode():
+@pytest.mark.parametrize("prec", [fga.PREC_FP32, fga.PREC_FP32_ALL])
+def test_direct_forces_plain_fp32_mode(prec):
     Xn, Yn, mX = normalised_mixture(4, per=512, m=2000)
     X32 = Xn.astype(np.float32).astype(np.float64)
     Y32 = Yn.astype(np.float32).astype(np.float64)
     m32 = mX.astype(np.float32).astype(np.float64)
     ref = oracle.direct_forces(Y32, X32, m32)
-    F, _ = fga.forces(dev(Y32), dev(X32), dev(m32), None, 0.0,
-                      fga.default_params(precision=fga.PREC_FP32))
+    F, _ = fga.forces(dev(Y32), dev(X32), dev(m32), None, 0.0, fga.default_params(precision=prec))
     emax, agg = force_gate(F.cpu().numpy().astype(np.float64), ref)
     assert emax <= 1e-5 and agg <= 1e-5, (emax, agg)
 
@@ -188,7 +188,10 @@ def test_group_forces_against_oracle_tree(theta, gw):
     ot = oracle.BHTree(X, m)
     ref, cref = ot.forces(Y, None, 66.7, 0.2, theta, count=True)
     dref = oracle.direct_forces(Y, X, m)
-    F, cnt = fga.forces(dev(Y), dev(X), dev(m), None, theta, fga.default_params(group_width=gw))
+    # plain tile sums at the largest opening angle, Kahan-compensated ones elsewhere
+    prec = fga.PREC_FP32 if theta == 0.8 else fga.PREC_FP32_KAHAN
+    F, cnt = fga.forces(dev(Y), dev(X), dev(m), None, theta,
+                        fga.default_params(group_width=gw, precision=prec))
     F = F.cpu().numpy().astype(np.float64)
     assert np.isfinite(F).all()
     e = rel_err(F, ref)
