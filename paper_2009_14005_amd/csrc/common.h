@@ -124,11 +124,14 @@ struct alignas(16) BHWide {
 };
 constexpr int kChildShift = 29;
 
-// Completion of an iteration: items report to chunks of kChunk items, chunks
-// to the pair. A pair with n items needs (n + chunks) x 12 partial moments and
-// 1 + chunks counters (zero at rest).
-constexpr int kChunk = 64;
-inline int completion_chunks(int n_items) { return (n_items + kChunk - 1) / kChunk; }
+// Completion of an iteration: every item writes one row of 12 partial
+// moments; the reduction launch sums kReduceRows rows per block, and its last
+// block the block results. A pair with n items needs (n + chunks) x 12
+// partial moments and one counter (zero at rest).
+constexpr int kReduceRows = 256;
+__host__ __device__ inline int completion_chunks(int n_items) {
+  return (n_items + kReduceRows - 1) / kReduceRows;
+}
 
 // Geometry of one registration pair on the device, for the iteration kernels.
 struct PairDev {
@@ -138,7 +141,7 @@ struct PairDev {
   void* V;              // per-particle velocities (particle mode), m x 3 of T, else nullptr
   RigidState* st;
   double* partial;      // (n_items + chunks) x 12 partial moments
-  unsigned* done;       // completion counters: pair, then one per chunk of kChunk items
+  unsigned* done;       // completion counter of the reduction launch
   int n, m;
   int n_nodes;
   int jr;               // reference ranges per template tile
@@ -212,9 +215,9 @@ fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipS
 template <typename T>
 fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s);
 template <typename T>
-fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, int n_items,
-                                  unsigned* queue, int n_blocks, const IterConsts& c,
-                                  hipStream_t s, bool bh, bool group);
+fga_status launch_batch_iteration(const PairDev* pairs_dev, int npairs, int reduce_blocks,
+                                  const int2* items, int n_items, unsigned* queue, int n_blocks,
+                                  const IterConsts& c, hipStream_t s, bool bh, bool group);
 
 
 }  // namespace fga

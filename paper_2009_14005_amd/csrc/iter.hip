@@ -3,9 +3,10 @@
 //   a3/a4 acceleration g_i by direct sum or Barnes-Hut  (Eq. GAForce; Alg. 2)
 //   a5  damped velocity and displacement               (Eqs. GAForceDissipative,
 //       v' = (1 - c_i) v_i + dt g_i,  d_i = dt v'       TotalGAForce, PreviousVelocity)
-//   a6  FP64 moments sum d_i and sum d_i q_i^T, reduced per block, then over blocks
-//   a7  Kabsch step and state update by the last block to finish (Eqs. R_Kabsch,
-//       transEst; template update and composition of Alg. 2)
+//   a6  FP64 moments sum d_i and sum d_i q_i^T, reduced per block into one row
+//       per item; a second, small launch sums the rows in a fixed order
+//   a7  Kabsch step and state update by the last block of that launch (Eqs.
+//       R_Kabsch, transEst; template update and composition of Alg. 2)
 //
 // Work is split into items (template tile of kBlock particles) x (reference
 // range). The moments are linear in g_i, so every item adds its own share and
@@ -72,17 +73,15 @@ __device__ inline void jrange(int n, int jrn, int jr, int& j0, int& j1) {
   j1 = min(n, j0 + per);
 }
 
-// Steps a5-a7 for the K template particles this thread holds (those with
-// owner[k] set): damped velocity and displacement, FP64 moments, the block's
-// partial sums, and, in the block that completes the pair's iteration, the
-// ordered sum over items and the rigid step.
+// Steps a5-a6 for the K template particles this thread holds (those with
+// owner[k] set): damped velocity and displacement, FP64 moments and the
+// block's row of partial sums.
 // The velocity coefficients and the template coordinates are read again here
 // rather than kept in registers through the force sum.
 template <typename T, bool BH, int PREC, int K>
 __device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, int jr,
                             const int (&idx)[K], const bool (&owner)[K], const T (&acc)[K][3],
                             unsigned cnt, double* lds) {
-  __shared__ int s_last;
   const T G = cG<T>(c), dt = cDt<T>(c);
   const Coef<T> cf = load_coef<T>(pd.st);
   const vec4_t<T>* Q = (const vec4_t<T>*)pd.Q;
@@ -141,54 +140,62 @@ __device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, in
     block_sum<1>(cc, lds + kMom * (kBlock / kWave));
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&pd.st->interactions, (unsigned long long)cc[0]);
   }
-  // completion in two levels, each in a fixed order (deterministic): the
-  // last block of every chunk of kChunk items sums the chunk's partials, and
-  // the last chunk to finish sums the chunk partials and applies the rigid step
-  const int n_chunks = (pd.n_items + kChunk - 1) / kChunk;
-  const int chunk = item / kChunk;
-  if (threadIdx.x == 0) {
+  // the block's row of partial moments; the reduction launch sums the rows
+  if (threadIdx.x == 0)
     for (int k = 0; k < kMom; ++k)
       pd.partial[(size_t)item * kMom + k] =
           PREC == FGA_PREC_FP32_ALL ? (double)(float)mom[k] : mom[k];
-    __threadfence();
-    const unsigned in_chunk = (unsigned)min(kChunk, pd.n_items - chunk * kChunk);
-    const unsigned prev = atomicAdd(pd.done + 1 + chunk, 1u);
-    s_last = prev == in_chunk - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double tot[kMom];
-  auto sum_rows = [&](const double* base, int r0, int r1) {
-    for (int k = 0; k < kMom; ++k) tot[k] = 0.0;
-    for (int e = r0 + (int)threadIdx.x; e < r1; e += kBlock) {
-      const volatile double* pp = base + (size_t)e * kMom;
-      for (int k = 0; k < kMom; ++k) {
-        if (PREC == FGA_PREC_FP32_ALL) tot[k] = (double)((float)tot[k] + (float)pp[k]);
-        else tot[k] += pp[k];
-      }
+}
+
+// Ordered sum of partial-moment rows [r0, r1) (one row per thread, then the
+// fixed-order block sum); the result is valid in thread 0.
+template <int PREC>
+__device__ inline void sum_rows(const double* base, int r0, int r1, double (&tot)[kMom],
+                                double* lds) {
+#pragma unroll
+  for (int k = 0; k < kMom; ++k) tot[k] = 0.0;
+  for (int e = r0 + (int)threadIdx.x; e < r1; e += kBlock) {
+    const double* pp = base + (size_t)e * kMom;
+#pragma unroll
+    for (int k = 0; k < kMom; ++k) {
+      if (PREC == FGA_PREC_FP32_ALL) tot[k] = (double)((float)tot[k] + (float)pp[k]);
+      else tot[k] += pp[k];
     }
-    block_sum<kMom>(tot, lds);
-  };
-  double* cpart = pd.partial + (size_t)pd.n_items * kMom;  // chunk partials
-  sum_rows(pd.partial, chunk * kChunk, min(pd.n_items, (chunk + 1) * kChunk));
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < kMom; ++k) cpart[(size_t)chunk * kMom + k] = tot[k];
-    pd.done[1 + chunk] = 0u;
-    __threadfence();
-    const unsigned prev = atomicAdd(pd.done, 1u);
-    s_last = prev == (unsigned)(n_chunks - 1);
   }
-  __syncthreads();
-  if (!s_last) return;
-  // a7: this block finished the iteration
-  __threadfence();
-  sum_rows(cpart, 0, n_chunks);
+  block_sum<kMom>(tot, lds);
+}
+
+// a6/a7 completion of one pair's iteration, block b of the reduction launch:
+// the block sums kReduceRows rows of the iteration kernel's partial moments;
+// with several blocks the last one to finish sums their results (both levels
+// in a fixed order, so the result is deterministic) and applies the rigid
+// step. Running this in a launch of its own keeps device-scope fences, which
+// write back and invalidate the L2 of the issuing XCD, out of the force
+// kernel, whose tree and points live in that L2.
+template <int PREC>
+__device__ void reduce_step(const PairDev& pd, const IterConsts& c, int b, double* lds) {
+  __shared__ int s_last;
+  const int nb = completion_chunks(pd.n_items);
+  double tot[kMom];
+  sum_rows<PREC>(pd.partial, b * kReduceRows, min(pd.n_items, (b + 1) * kReduceRows), tot, lds);
+  if (nb > 1) {
+    double* bpart = pd.partial + (size_t)pd.n_items * kMom;  // one row per reduction block
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < kMom; ++k) bpart[(size_t)b * kMom + k] = tot[k];
+      __threadfence();
+      const unsigned prev = atomicAdd(pd.done, 1u);
+      s_last = prev == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    sum_rows<PREC>(bpart, 0, nb, tot, lds);
+  }
   if (threadIdx.x == 0) {
-    if (!BH) pd.st->interactions += (long long)pd.n * (long long)pd.m;
+    if (!pd.nodes) pd.st->interactions += (long long)pd.n * (long long)pd.m;
     rigid_update(*pd.st, tot, c.dt);
     *pd.done = 0u;
-    __threadfence();
   }
 }
 
@@ -321,15 +328,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     iteration_item<T, BH, PREC, 1>(pd, c, w.y, lds, stk);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {  // the last block out resets the queue
-    __threadfence();
-    const unsigned prev = atomicAdd(&queue[1], 1u);
-    if (prev == gridDim.x - 1) {
-      queue[0] = 0u;
-      queue[1] = 0u;
-      __threadfence();
-    }
-  }
 }
 
 // Persistent batched iteration with the group walk (K = 1): queue entries are
@@ -352,15 +350,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     iteration_item_group<PREC, 1>(pd, c, w.y, lds, g);
     __syncthreads();
   }
-  if (threadIdx.x == 0) {  // the last block out resets the queue
-    __threadfence();
-    const unsigned prev = atomicAdd(&queue[1], 1u);
-    if (prev == gridDim.x - 1) {
-      queue[0] = 0u;
-      queue[1] = 0u;
-      __threadfence();
-    }
-  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_reduce_step(PairDev pd, IterConsts c) {
+  __shared__ double lds[kMom * (kBlock / kWave)];
+  if (pd.st->converged) return;  // uniform: the state was written by an earlier launch
+  reduce_step<PREC>(pd, c, (int)blockIdx.x, lds);
+}
+
+// Reduction launch of the batched iteration: blockIdx.y is the pair. Block
+// (0, 0) also rewinds the work queue for the next iteration.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_batch_reduce_step(const PairDev* pairs, unsigned* queue,
+                                                              IterConsts c) {
+  __shared__ double lds[kMom * (kBlock / kWave)];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) queue[0] = 0u;
+  const PairDev pd = pairs[blockIdx.y];
+  if ((int)blockIdx.x >= completion_chunks(pd.n_items) || pd.st->converged) return;
+  reduce_step<PREC>(pd, c, (int)blockIdx.x, lds);
+}
+
+template <int PREC>
+inline void reduce_launch(const PairDev& pd, const IterConsts& c, hipStream_t s) {
+  k_reduce_step<PREC><<<completion_chunks(pd.n_items), kBlock, 0, s>>>(pd, c);
 }
 
 }  // namespace
@@ -404,14 +417,17 @@ fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t 
         }
     }
   }
+  if (sizeof(T) == 8) reduce_launch<FGA_PREC_FP64>(pd, c, s);
+  else if (c.prec == FGA_PREC_FP32_ALL) reduce_launch<FGA_PREC_FP32_ALL>(pd, c, s);
+  else reduce_launch<FGA_PREC_FP32_KAHAN>(pd, c, s);
   FGA_HIP(hipGetLastError());
   return FGA_OK;
 }
 
 template <typename T>
-fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, int n_items,
-                                  unsigned* queue, int n_blocks, const IterConsts& c,
-                                  hipStream_t s, bool bh, bool group) {
+fga_status launch_batch_iteration(const PairDev* pairs_dev, int npairs, int reduce_blocks,
+                                  const int2* items, int n_items, unsigned* queue, int n_blocks,
+                                  const IterConsts& c, hipStream_t s, bool bh, bool group) {
   if (sizeof(T) == 4 && bh && group) {
     switch (c.prec) {
       case FGA_PREC_FP32: k_batch_iteration_group<FGA_PREC_FP32><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c); break;
@@ -431,16 +447,22 @@ fga_status launch_batch_iteration(const PairDev* pairs_dev, const int2* items, i
       default: k_batch_iteration<T, false, FGA_PREC_FP32_KAHAN><<<n_blocks, kBlock, 0, s>>>(pairs_dev, items, n_items, queue, c);
     }
   }
+  const dim3 rgrid((unsigned)std::max(1, reduce_blocks), (unsigned)npairs);
+  if (sizeof(T) == 8) k_batch_reduce_step<FGA_PREC_FP64><<<rgrid, kBlock, 0, s>>>(pairs_dev, queue, c);
+  else if (c.prec == FGA_PREC_FP32_ALL) k_batch_reduce_step<FGA_PREC_FP32_ALL><<<rgrid, kBlock, 0, s>>>(pairs_dev, queue, c);
+  else k_batch_reduce_step<FGA_PREC_FP32_KAHAN><<<rgrid, kBlock, 0, s>>>(pairs_dev, queue, c);
   FGA_HIP(hipGetLastError());
   return FGA_OK;
 }
 
 template fga_status launch_iteration<float>(const PairDev&, const IterConsts&, hipStream_t);
 template fga_status launch_iteration<double>(const PairDev&, const IterConsts&, hipStream_t);
-template fga_status launch_batch_iteration<float>(const PairDev*, const int2*, int, unsigned*, int,
-                                                  const IterConsts&, hipStream_t, bool, bool);
-template fga_status launch_batch_iteration<double>(const PairDev*, const int2*, int, unsigned*,
-                                                   int, const IterConsts&, hipStream_t, bool, bool);
+template fga_status launch_batch_iteration<float>(const PairDev*, int, int, const int2*, int,
+                                                  unsigned*, int, const IterConsts&, hipStream_t,
+                                                  bool, bool);
+template fga_status launch_batch_iteration<double>(const PairDev*, int, int, const int2*, int,
+                                                   unsigned*, int, const IterConsts&, hipStream_t,
+                                                   bool, bool);
 
 // ------------------------------------------------------------------ forces
 namespace {
