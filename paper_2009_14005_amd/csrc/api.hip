@@ -529,17 +529,19 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
   return FGA_OK;
 }
 
-// Times each candidate number of reference ranges on the state's own kernel,
-// restoring the FP64 state after every trial.
-static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands, int* best) {
+// Times each candidate work split on the state's own kernels, restoring the
+// FP64 state after every trial; `times` receives (ms, candidate), fastest
+// first.
+static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands,
+                              std::vector<std::pair<float, int>>* times) {
   RigidState saved;
   FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
   hipEvent_t e0, e1;
   FGA_HIP(hipEventCreate(&e0));
   FGA_HIP(hipEventCreate(&e1));
-  float best_ms = 1e30f;
   fga_status st = FGA_OK;
+  times->clear();
   for (int c : cands) {
     PairDev pd = S->pd;
     st = apply_split(S, pd, c);
@@ -549,19 +551,23 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands, int* 
     };
     st = launch();
     if (st != FGA_OK) break;
-    if (hipEventRecord(e0, S->s) != hipSuccess) { st = FGA_E_DEVICE; break; }
-    for (int r = 0; r < 2 && st == FGA_OK; ++r) st = launch();
+    // the fastest of three separately timed launches: robust to a launch
+    // slowed by something else on the device
+    float ms = 1e30f;
+    for (int r = 0; r < 3 && st == FGA_OK; ++r) {
+      float one = 0.f;
+      if (hipEventRecord(e0, S->s) != hipSuccess) { st = FGA_E_DEVICE; break; }
+      st = launch();
+      if (st != FGA_OK) break;
+      if (hipEventRecord(e1, S->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&one, e0, e1) != hipSuccess) {
+        st = FGA_E_DEVICE;
+        break;
+      }
+      ms = std::min(ms, one);
+    }
     if (st != FGA_OK) break;
-    float ms = 0.f;
-    if (hipEventRecord(e1, S->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      st = FGA_E_DEVICE;
-      break;
-    }
-    if (ms < best_ms) {
-      best_ms = ms;
-      *best = c;
-    }
+    times->push_back({ms, c});
     if (hipMemcpyAsync(S->st, &saved, sizeof saved, hipMemcpyHostToDevice, S->s) != hipSuccess ||
         hipStreamSynchronize(S->s) != hipSuccess) {
       st = FGA_E_DEVICE;
@@ -571,6 +577,47 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands, int* 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != FGA_OK) set_error("autotuning the reference ranges failed");
+  std::stable_sort(times->begin(), times->end(),
+                   [](const std::pair<float, int>& x, const std::pair<float, int>& y) {
+                     return x.first < y.first;
+                   });
+  return st;
+}
+
+// Autotuning of a state's work split. The cost of a split changes with the
+// template's pose as the registration proceeds (the first, misaligned pose
+// can rank the splits differently from the poses where most iterations are
+// spent), so every candidate is timed at the initial pose, the state is then
+// advanced by kTuneAdvance iterations with the fastest split, the leading
+// kTuneFinal candidates are timed again there, and the initial state is
+// restored. The stop rule is off while tuning.
+constexpr int kTuneAdvance = 16;
+constexpr int kTuneFinal = 8;
+static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* best) {
+  RigidState init;
+  FGA_HIP(hipMemcpyAsync(&init, S->st, sizeof init, hipMemcpyDeviceToHost, S->s));
+  FGA_HIP(hipStreamSynchronize(S->s));
+  RigidState open = init;
+  open.tol = 0.0;
+  FGA_HIP(hipMemcpyAsync(S->st, &open, sizeof open, hipMemcpyHostToDevice, S->s));
+  std::vector<std::pair<float, int>> times;
+  fga_status st = tune_ranges(S, cands, &times);
+  if (st == FGA_OK) {
+    *best = times[0].second;
+    if (times.size() > 1) {
+      PairDev adv = S->pd;
+      st = apply_split(S, adv, *best);
+      for (int k = 0; k < kTuneAdvance && st == FGA_OK; ++k)
+        st = S->f64 ? launch_iteration<double>(adv, S->c, S->s) : launch_iteration<float>(adv, S->c, S->s);
+      std::vector<int> lead;
+      for (size_t k = 0; k < times.size() && k < (size_t)kTuneFinal; ++k) lead.push_back(times[k].second);
+      if (st == FGA_OK) st = tune_ranges(S, lead, &times);
+      if (st == FGA_OK) *best = times[0].second;
+    }
+  }
+  if (hipMemcpyAsync(S->st, &init, sizeof init, hipMemcpyHostToDevice, S->s) != hipSuccess ||
+      hipStreamSynchronize(S->s) != hipSuccess)
+    st = FGA_E_DEVICE;
   return st;
 }
 
@@ -899,7 +946,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     max_items = std::max(max_items, (size_t)tmp.n_items);
   }
   const size_t max_chunks = (size_t)completion_chunks((int)max_items);
-  if (pool_get(&S->partial, sizeof(double) * 12 * (max_items + max_chunks), s) != FGA_OK ||
+  if (pool_get(&S->partial, sizeof(double) * kPartialRow * (max_items + max_chunks), s) != FGA_OK ||
       pool_get(&S->done, sizeof(unsigned) * (1 + max_chunks), s) != FGA_OK) {
     return fail(FGA_E_NOMEM);
   }
@@ -933,7 +980,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   }
   if (!tuned) {
     if (fga_status gs = apply_split(S, pd, cands[0]); gs != FGA_OK) return fail(gs);
-    fga_status tst = tune_ranges(S, cands, &best);
+    fga_status tst = autotune(S, cands, &best);
     if (tst != FGA_OK) return fail(tst);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = best;
@@ -1240,7 +1287,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
   std::vector<size_t> poff(npairs + 1, 0), doff(npairs + 1, 0);
   for (int k = 0; k < npairs; ++k) {
     const int ch = completion_chunks(pds[k].n_items);
-    poff[k + 1] = poff[k] + (size_t)12 * (pds[k].n_items + ch);
+    poff[k + 1] = poff[k] + (size_t)kPartialRow * (pds[k].n_items + ch);
     doff[k + 1] = doff[k] + 1 + ch;
   }
   const int max_queue = item_off[npairs];

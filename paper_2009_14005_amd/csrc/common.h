@@ -73,6 +73,7 @@ struct RigidState {
   double b[3];
   double S0[9];   // sum_i q_i q_i^T
   double mu0[3];  // mean of the normalised template
+  double Vw[9];   // right singular vectors of the last Kabsch matrix (start of the next SVD)
   double dT2;     // ||T_k - T_{k-1}||_F^2 of the last step
   double tol;     // convergence tolerance (<= 0: never converged)
   double rank_tol;  // singular-value ratio below which C counts as rank deficient
@@ -124,10 +125,12 @@ struct alignas(16) BHWide {
 };
 constexpr int kChildShift = 29;
 
-// Completion of an iteration: every item writes one row of 12 partial
-// moments; the reduction launch sums kReduceRows rows per block, and its last
-// block the block results. A pair with n items needs (n + chunks) x 12
-// partial moments and one counter (zero at rest).
+// Completion of an iteration: every item writes one row of kPartialRow
+// doubles (12 partial moments and its interaction count); the reduction
+// launch sums kReduceRows rows per block, and its last block the block
+// results. A pair with n items needs (n + chunks) rows and one counter (zero
+// at rest).
+constexpr int kPartialRow = 13;
 constexpr int kReduceRows = 256;
 __host__ __device__ inline int completion_chunks(int n_items) {
   return (n_items + kReduceRows - 1) / kReduceRows;
@@ -140,7 +143,7 @@ struct PairDev {
   const BHWide* nodes;  // BH nodes in child-block layout, or nullptr for the direct sum
   void* V;              // per-particle velocities (particle mode), m x 3 of T, else nullptr
   RigidState* st;
-  double* partial;      // (n_items + chunks) x 12 partial moments
+  double* partial;      // (n_items + chunks) x kPartialRow partial moments and counts
   unsigned* done;       // completion counter of the reduction launch
   int n, m;
   int n_nodes;

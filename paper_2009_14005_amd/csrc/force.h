@@ -512,47 +512,40 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
       g.list[pos] = nd.cm;
     }
     cnt += __popcll(om);
-    // points of opened leaves and twigs, appended 64 at a time: slot k of a
-    // round belongs to the last lane with points whose first slot is at or
-    // below k (slot `base` may continue a lane that started earlier)
+    // append the points of opened leaves and twigs, 64 at a time
     const int p0 = nd.first;
     const int np = pts ? nd.last - p0 + 1 : 0;
-    const unsigned long long has = __ballot(np > 0);
-    int P = 0, pex = 0, off = 0;
-    auto point_load = [&](int base) {
-      const unsigned long long before = __ballot(np > 0 && pex <= base) & has;
-      const int carry = 63 - __builtin_clzll(before);
-      __hip_atomic_store(&g.mark[lane], lane == 0 ? (unsigned)carry + 1u : 0u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_WAVEFRONT);
-      if (np > 0 && pex > base && pex < base + kWave)
-        __hip_atomic_store(&g.mark[pex - base], (unsigned)lane + 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WAVEFRONT);
-      const int o = (int)wave_incl_max_u32(__hip_atomic_load(&g.mark[lane], __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_WAVEFRONT)) - 1;
-      const int ooff = __shfl(off, o, kWave);
-      return X[min(max(base + lane + ooff, 0), n_points - 1)];
-    };
-    float4 xp = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (has != 0ull) {
+    if (__ballot(np > 0) != 0ull) {
       const int pincl = wave_incl_sum_dpp(np);
-      P = __builtin_amdgcn_readlane(pincl, kWave - 1);
-      pex = pincl - np;  // first list slot of this lane's points
-      off = p0 - pex;    // point index = slot + off for this lane's slots
-      xp = point_load(0);
+      const int P = __builtin_amdgcn_readlane(pincl, kWave - 1);
+      const int pex = pincl - np;          // first list slot of this lane's points
+      const int off = p0 - pex;            // point index = slot + off for this lane's slots
+      const unsigned long long has = __ballot(np > 0);
+      for (int base = 0; base < P; base += kWave) {
+        if (cnt > kGList - kWave) flush();
+        const int k = base + lane;
+        // owner of slot k: the last lane with points whose first slot is at or
+        // below k; slot `base` may continue a lane that started earlier
+        const unsigned long long before = __ballot(np > 0 && pex <= base) & has;
+        const int carry = 63 - __builtin_clzll(before);
+        __hip_atomic_store(&g.mark[lane], lane == 0 ? (unsigned)carry + 1u : 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (np > 0 && pex > base && pex < base + kWave)
+          __hip_atomic_store(&g.mark[pex - base], (unsigned)lane + 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int o = (int)wave_incl_max_u32(__hip_atomic_load(&g.mark[lane], __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_WAVEFRONT)) - 1;
+        const int ooff = __shfl(off, o, kWave);
+        if (k < P) g.list[cnt + lane] = X[min(max(k + ooff, 0), n_points - 1)];
+        cnt += min(kWave, P - base);
+      }
     }
-    // the next step's nodes are requested before the points are stored and
-    // the list is summed, so that both loads are in flight together and
-    // their latency overlaps the arithmetic
+    // the next step's nodes are requested before the list is summed, so
+    // their load latency overlaps the arithmetic
     if (sp > 0) {
       pop();
     } else {
       T = 0;
-    }
-    for (int base = 0; base < P; base += kWave) {
-      if (base > 0) xp = point_load(base);
-      if (cnt > kGList - kWave) flush();
-      if (base + lane < P) g.list[cnt + lane] = xp;
-      cnt += min(kWave, P - base);
     }
     if (cnt > kGList - kWave) flush();
   }

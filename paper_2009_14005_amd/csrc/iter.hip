@@ -20,7 +20,9 @@
 namespace fga {
 namespace {
 
-constexpr int kMom = 12;
+constexpr int kMom = 12;                // moments: sum d_i, sum d_i q_i^T
+constexpr int kRow = kPartialRow;       // + the interaction count (exact in FP64)
+static_assert(kRow == kMom + 1, "partial row layout");
 
 template <typename T>
 struct Coef {
@@ -88,9 +90,9 @@ __device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, in
   vec4_t<T> q[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) q[k] = Q[owner[k] ? idx[k] : 0];
-  double mom[kMom];
+  double mom[kRow];
 #pragma unroll
-  for (int k = 0; k < kMom; ++k) mom[k] = 0.0;
+  for (int k = 0; k < kRow; ++k) mom[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     // a5: damped velocity and displacement
@@ -134,35 +136,33 @@ __device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, in
         for (int b = 0; b < 3; ++b) mom[3 + 3 * a + b] += d[a] * qq[b];
     }
   }
-  block_sum<kMom>(mom, lds);
-  if (BH) {  // interaction count of the block
-    double cc[1] = {(double)cnt};
-    block_sum<1>(cc, lds + kMom * (kBlock / kWave));
-    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&pd.st->interactions, (unsigned long long)cc[0]);
-  }
+  // the block's interaction count travels in the row (no atomics here: the
+  // count is summed by the reduction launch)
+  mom[kMom] = BH ? (double)cnt : 0.0;
+  block_sum<kRow>(mom, lds);
   // the block's row of partial moments; the reduction launch sums the rows
   if (threadIdx.x == 0)
-    for (int k = 0; k < kMom; ++k)
-      pd.partial[(size_t)item * kMom + k] =
-          PREC == FGA_PREC_FP32_ALL ? (double)(float)mom[k] : mom[k];
+    for (int k = 0; k < kRow; ++k)
+      pd.partial[(size_t)item * kRow + k] =
+          PREC == FGA_PREC_FP32_ALL && k < kMom ? (double)(float)mom[k] : mom[k];
 }
 
 // Ordered sum of partial-moment rows [r0, r1) (one row per thread, then the
 // fixed-order block sum); the result is valid in thread 0.
 template <int PREC>
-__device__ inline void sum_rows(const double* base, int r0, int r1, double (&tot)[kMom],
+__device__ inline void sum_rows(const double* base, int r0, int r1, double (&tot)[kRow],
                                 double* lds) {
 #pragma unroll
-  for (int k = 0; k < kMom; ++k) tot[k] = 0.0;
+  for (int k = 0; k < kRow; ++k) tot[k] = 0.0;
   for (int e = r0 + (int)threadIdx.x; e < r1; e += kBlock) {
-    const double* pp = base + (size_t)e * kMom;
+    const double* pp = base + (size_t)e * kRow;
 #pragma unroll
-    for (int k = 0; k < kMom; ++k) {
-      if (PREC == FGA_PREC_FP32_ALL) tot[k] = (double)((float)tot[k] + (float)pp[k]);
+    for (int k = 0; k < kRow; ++k) {
+      if (PREC == FGA_PREC_FP32_ALL && k < kMom) tot[k] = (double)((float)tot[k] + (float)pp[k]);
       else tot[k] += pp[k];
     }
   }
-  block_sum<kMom>(tot, lds);
+  block_sum<kRow>(tot, lds);
 }
 
 // a6/a7 completion of one pair's iteration, block b of the reduction launch:
@@ -176,13 +176,13 @@ template <int PREC>
 __device__ void reduce_step(const PairDev& pd, const IterConsts& c, int b, double* lds) {
   __shared__ int s_last;
   const int nb = completion_chunks(pd.n_items);
-  double tot[kMom];
+  double tot[kRow];
   sum_rows<PREC>(pd.partial, b * kReduceRows, min(pd.n_items, (b + 1) * kReduceRows), tot, lds);
   if (nb > 1) {
-    double* bpart = pd.partial + (size_t)pd.n_items * kMom;  // one row per reduction block
+    double* bpart = pd.partial + (size_t)pd.n_items * kRow;  // one row per reduction block
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int k = 0; k < kMom; ++k) bpart[(size_t)b * kMom + k] = tot[k];
+      for (int k = 0; k < kRow; ++k) bpart[(size_t)b * kRow + k] = tot[k];
       __threadfence();
       const unsigned prev = atomicAdd(pd.done, 1u);
       s_last = prev == (unsigned)(nb - 1);
@@ -193,7 +193,7 @@ __device__ void reduce_step(const PairDev& pd, const IterConsts& c, int b, doubl
     sum_rows<PREC>(bpart, 0, nb, tot, lds);
   }
   if (threadIdx.x == 0) {
-    if (!pd.nodes) pd.st->interactions += (long long)pd.n * (long long)pd.m;
+    pd.st->interactions += pd.nodes ? (long long)tot[kMom] : (long long)pd.n * (long long)pd.m;
     rigid_update(*pd.st, tot, c.dt);
     *pd.done = 0u;
   }
@@ -292,7 +292,7 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
 
 template <typename T, bool BH, int PREC, int S>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_iteration(PairDev pd, IterConsts c) {
-  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ StackEntry stk[BH ? (kBlock / kWave) * kStack : 1];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
   iteration_item<T, BH, PREC, S>(pd, c, (int)blockIdx.x, lds, stk);
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 
 template <int PREC, int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_iteration_group(PairDev pd, IterConsts c) {
-  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ GroupLds g[kBlock / kWave];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
   iteration_item_group<PREC, K>(pd, c, (int)blockIdx.x, lds, g);
@@ -313,7 +313,7 @@ template <typename T, bool BH, int PREC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_iteration(const PairDev* pairs,
                                                             const int2* items, int n_items,
                                                             unsigned* queue, IterConsts c) {
-  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ StackEntry stk[BH ? (kBlock / kWave) * kStack : 1];
   __shared__ int s_item;
   while (true) {
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 template <int PREC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_iteration_group(
     const PairDev* pairs, const int2* items, int n_items, unsigned* queue, IterConsts c) {
-  __shared__ double lds[(kMom + 1) * (kBlock / kWave)];
+  __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ GroupLds g[kBlock / kWave];
   __shared__ int s_item;
   while (true) {
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_reduce_step(PairDev pd, IterConsts c) {
-  __shared__ double lds[kMom * (kBlock / kWave)];
+  __shared__ double lds[kRow * (kBlock / kWave)];
   if (pd.st->converged) return;  // uniform: the state was written by an earlier launch
   reduce_step<PREC>(pd, c, (int)blockIdx.x, lds);
 }
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_step(PairDev pd, IterConsts c
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_batch_reduce_step(const PairDev* pairs, unsigned* queue,
                                                               IterConsts c) {
-  __shared__ double lds[kMom * (kBlock / kWave)];
+  __shared__ double lds[kRow * (kBlock / kWave)];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) queue[0] = 0u;
   const PairDev pd = pairs[blockIdx.y];
   if ((int)blockIdx.x >= completion_chunks(pd.n_items) || pd.st->converged) return;

@@ -28,11 +28,11 @@ FGA_HD double m3_det(const double* A) {
 }
 
 // One Jacobi rotation of columns P < Q of W (and of V alongside) that makes
-// them orthogonal; false if they already are, to 1e-15 relative. The column
-// dot product carries rounding of a few ulps (2.2e-16 each), so a tighter
-// threshold is usually never met and the sweeps run to their cap; at 1e-15
-// the solve ends after 3 to 5 sweeps. P and Q are compile-time so that W and
-// V stay in registers.
+// them orthogonal; false if they already are, to 1e-15 relative (cosine of
+// their angle, compared squared). The column dot product carries rounding of
+// a few ulps (2.2e-16 each), so a tighter threshold is usually never met and
+// the sweeps run to their cap; at 1e-15 a cold solve ends after 3 to 5
+// sweeps. P and Q are compile-time so that W and V stay in registers.
 template <int P, int Q>
 FGA_HD bool jacobi_rotate(double* W, double* V) {
   double al = 0.0, be = 0.0, ga = 0.0;
@@ -41,7 +41,7 @@ FGA_HD bool jacobi_rotate(double* W, double* V) {
     be += W[3 * i + Q] * W[3 * i + Q];
     ga += W[3 * i + P] * W[3 * i + Q];
   }
-  if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) return false;
+  if (ga * ga <= 1e-30 * (al * be)) return false;
   const double ze = (be - al) / (2.0 * ga);
   const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
   const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
@@ -77,11 +77,19 @@ FGA_HD void swap_columns(double* W, double* V, double* nrm) {
 // the order (0,1), (0,2), (1,2), until they are mutually orthogonal; then
 // s_k = |W_k| and U_k = W_k / s_k. Columns belonging to zero singular values
 // are left as zero in U. Every array index is a compile-time constant, so the
-// device keeps the whole solve in registers.
-FGA_HD void svd3(const double* A, double* U, double* s, double* V) {
+// device keeps the whole solve in registers. V0 (orthogonal, or NULL for the
+// identity) is the starting V: W = A V0. The right singular vectors of a
+// matrix close to A make W nearly orthogonal from the start, so fewer sweeps
+// are needed; the factors are the same up to rounding and column signs.
+FGA_HD void svd3(const double* A, double* U, double* s, double* V, const double* V0 = nullptr) {
   double W[9];
-  for (int k = 0; k < 9; ++k) W[k] = A[k];
-  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  if (V0) {
+    for (int k = 0; k < 9; ++k) V[k] = V0[k];
+    m3_mul(A, V0, W);
+  } else {
+    for (int k = 0; k < 9; ++k) W[k] = A[k];
+    for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  }
   for (int sweep = 0; sweep < 40; ++sweep) {
     bool rotated = jacobi_rotate<0, 1>(W, V);
     rotated = jacobi_rotate<0, 2>(W, V) || rotated;
@@ -107,10 +115,13 @@ FGA_HD void svd3(const double* A, double* U, double* s, double* V) {
 // For rank(C) = 2 the third left singular vector is completed as U_0 x U_1.
 // Returns 0, or 1 when rank(C) < 2 (collinear template: R is then undefined
 // and set to the identity). A singular value below rank_tol * s_0 counts as
-// zero; rank_tol reflects the precision the template is stored in.
-FGA_HD int kabsch3(const double* C, double* R, double rank_tol = 1e-13) {
+// zero; rank_tol reflects the precision the template is stored in. Vw, if
+// given, starts the SVD (see svd3) and receives its V.
+FGA_HD int kabsch3(const double* C, double* R, double rank_tol = 1e-13, double* Vw = nullptr) {
   double U[9], s[3], V[9];
-  svd3(C, U, s, V);
+  svd3(C, U, s, V, Vw);
+  if (Vw)
+    for (int k = 0; k < 9; ++k) Vw[k] = V[k];
   const double tiny = rank_tol * s[0];
   if (!(s[0] > 0.0) || s[1] <= tiny) {
     for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
@@ -143,7 +154,7 @@ FGA_HD void rigid_update(RigidState& s, const double* mom, double dt) {
   m3_mul(s.R, s.S0, RS0);
   for (int k = 0; k < 9; ++k) RS0[k] += mom[3 + k];
   m3_mul_bt(RS0, s.R, C);
-  if (kabsch3(C, Rs, s.rank_tol)) s.flags |= 1;
+  if (kabsch3(C, Rs, s.rank_tol, s.Vw)) s.flags |= 1;
   double muD[3], ts[3], Rn[9], tn[3];
   for (int a = 0; a < 3; ++a) muD[a] = s.mu[a] + dbar[a];
   for (int a = 0; a < 3; ++a)
@@ -196,6 +207,7 @@ FGA_HD void rigid_init(RigidState& s, const double* S0, const double* mu0, int m
     s.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
     s.A[k] = 0.0;
     s.S0[k] = S0[k];
+    s.Vw[k] = (k % 4 == 0) ? 1.0 : 0.0;
     s.fR[k] = (float)s.R[k];
     s.fA[k] = 0.0f;
   }
