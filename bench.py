@@ -133,7 +133,8 @@ def main():
         "pct_fp32_vector_peak": 100.0 * value * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
         "accuracy_vs_ground_truth": {"phi_deg": phi, "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag)},
         "roofline": {
-            "kernel": KERNEL_NAMES.get(r1.traversal, "?") + " (fused force + ODE + moments + Kabsch)",
+            "kernel": KERNEL_NAMES.get(r1.traversal, "?") + " + k_reduce_step (one iteration: pose, forces, "
+                      "ODE, moments; then ordered moment sum and Kabsch step)",
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32_VECTOR / 1e12,
@@ -142,6 +143,7 @@ def main():
             "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
             "traffic": measured_traffic(),
             "avg_launch_us": it_ms * 1e3,
+            "launches_per_iteration": 2,
             "interactions_per_launch": it_inter,
             "flop_per_interaction": FLOP_PER_INTERACTION,
         },
