@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip direct/batched extras")
+    ap.add_argument("--no-extras", action="store_true", help="skip the extra workloads")
+    ap.add_argument("--extras", default="direct,batched,mixture",
+                    help="comma list of extra workloads to run: direct, batched, mixture")
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--plain-pairs", type=int, default=32,
                     help="pairs of the batch timed with sequential plain solves")
@@ -149,9 +151,12 @@ def main():
         },
     }
 
-    if not args.no_extras:
+    extras = set() if args.no_extras else set(args.extras.split(","))
+    if "direct" in extras:
         out["direct"] = bench_direct(fga, torch, synth, dev, stream)
+    if "batched" in extras:
         out["batched"] = bench_batched(fga, torch, synth, dev, args)
+    if "mixture" in extras:
         out["mixture_fp64_direct"] = bench_mixture(fga, torch, synth, dev)
     if args.precision_study:
         out["precision_study"] = precision_study(fga, torch, synth, dev)
