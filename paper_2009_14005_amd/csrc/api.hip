@@ -457,7 +457,17 @@ static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap
     double total = 0.0;
     for (double c : cs) total += c;
     std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
-    const double target = std::max(2.0 * cs[cs.size() / 2], total / 8192.0);
+    // heavy groups are split until their parts fall under `target`; with few
+    // groups for the chip (under two per resident wave slot) the parts are
+    // made finer, so that waves finishing early take over the remaining
+    // ones instead of idling while the heaviest finish
+    int dev = 0, cus = 256;
+    FGA_HIP(hipGetDevice(&dev));
+    FGA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const bool few = gt.n < 2 * cus * 4 * kGroupWavesPerSimd;
+    const double median = cs[cs.size() / 2];
+    const double target = few ? std::max(0.5 * median, total / 32768.0)
+                              : std::max(2.0 * median, total / 8192.0);
     std::vector<std::pair<double, int4>> items;
     for (int g = 0; g < gt.n; ++g) {
       const int2 grp = gt.host[g];
@@ -502,8 +512,10 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
     fga_state::Groups* gt = nullptr;
     FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, &gt));
     pd.n_groups = gt->n;
-    if (build && defer && gt->cost.empty()) {
+    if (build && defer) {
       // one wave per group for now; the first iteration measures the costs
+      // (also when tuning measured them already: every registration then
+      // runs the same first iteration and the same splits, bit for bit)
       std::vector<int4> ident(gt->n);
       for (int k = 0; k < gt->n; ++k) ident[k] = make_int4(gt->host[k].x, gt->host[k].y, 1 << 8, k);
       pool_free(S->ident_items, S->s);
@@ -1025,6 +1037,8 @@ static fga_status first_step_measured(fga_state* S) {
     if (st == FGA_E_DEVICE) set_error("first iteration with cost measurement failed");
     return st;
   }
+  for (auto& kv : gt->items) pool_free(kv.second.first, S->s);  // built from older costs
+  gt->items.clear();
   FGA_TRY(wave_items(S, S->pend_K, *gt, S->pend_cap, &S->pd.witems, &S->pd.n_witems));
   S->pd.n_items = (S->pd.n_witems + kBlock / kWave - 1) / (kBlock / kWave);
   S->pend_K = 0;

@@ -131,6 +131,10 @@ constexpr int kChildShift = 29;
 // results. A pair with n items needs (n + chunks) rows and one counter (zero
 // at rest).
 constexpr int kPartialRow = 13;
+
+// Waves per SIMD the group-walk kernels are compiled for (their register
+// budget); the host sizes the heavy-group split by it.
+constexpr int kGroupWavesPerSimd = 6;
 constexpr int kReduceRows = 256;
 __host__ __device__ inline int completion_chunks(int n_items) {
   return (n_items + kReduceRows - 1) / kReduceRows;

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 }
 
 template <int PREC, int K>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_iteration_group(PairDev pd, IterConsts c) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGroupWavesPerSimd))) void k_iteration_group(PairDev pd, IterConsts c) {
   __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ GroupLds g[kBlock / kWave];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // Persistent batched iteration with the group walk (K = 1): queue entries are
 // (pair, block of four wave items of that pair), ordered heaviest first.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_iteration_group(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGroupWavesPerSimd))) void k_batch_iteration_group(
     const PairDev* pairs, const int2* items, int n_items, unsigned* queue, IterConsts c) {
   __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ GroupLds g[kBlock / kWave];
