@@ -319,11 +319,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   while (true) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
     __syncthreads();
-    const int e = s_item;
+    // uniform across the block: in a scalar register, so the pair's fields
+    // below are scalar loads rather than per-lane copies
+    const int e = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (e >= n_items) break;
     const int2 w = items[e];
-    const PairDev pd = pairs[w.x];
+    const PairDev& pd = pairs[w.x];  // read in place (uniform address: scalar loads)
     if (pd.st->converged) continue;
     iteration_item<T, BH, PREC, 1>(pd, c, w.y, lds, stk);
     __syncthreads();
@@ -341,11 +343,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGroupWa
   while (true) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(&queue[0], 1u);
     __syncthreads();
-    const int e = s_item;
+    // uniform across the block: in a scalar register, so the pair's fields
+    // below are scalar loads rather than per-lane copies
+    const int e = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (e >= n_items) break;
     const int2 w = items[e];
-    const PairDev pd = pairs[w.x];
+    const PairDev& pd = pairs[w.x];  // read in place (uniform address: scalar loads)
     if (pd.st->converged) continue;
     iteration_item_group<PREC, 1>(pd, c, w.y, lds, g);
     __syncthreads();
