@@ -1360,7 +1360,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
     FGA_HIP(hipMemsetAsync(gcost, 0, sizeof(unsigned) * goff[npairs], s));
     int rb = 1;
-    for (int k = 0; k < npairs; ++k) rb = std::max(rb, completion_chunks(pds[k].n_items));
+    for (int k = 0; k < npairs; ++k) rb = std::max(rb, reduce_blocks(pds[k].n_items));
     FGA_TRY(launch_batch_iteration<T>(dpairs, npairs, rb, ditems, (int)items.size(), queue,
                                       std::min((int)items.size(), cus * 8), c, s, true, true));
     std::vector<unsigned> cost(goff[npairs]);
@@ -1414,15 +1414,15 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
   FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * n_items, hipMemcpyHostToDevice, s));
   const int n_blocks = std::min(n_items, cus * 8);
-  int reduce_blocks = 1;
-  for (int k = 0; k < npairs; ++k) reduce_blocks = std::max(reduce_blocks, completion_chunks(pds[k].n_items));
+  int n_reduce = 1;
+  for (int k = 0; k < npairs; ++k) n_reduce = std::max(n_reduce, reduce_blocks(pds[k].n_items));
   // one graph holds `every` iterations; replay until all pairs stopped
   const int every = std::max(1, std::min(p.check_every > 0 ? p.check_every : 16, std::max(1, p.max_iter)));
   FGA_HIP(hipStreamSynchronize(s));
   FGA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   fga_status cst = FGA_OK;
   for (int k = 0; k < every && cst == FGA_OK; ++k)
-    cst = launch_batch_iteration<T>(dpairs, npairs, reduce_blocks, ditems, n_items, queue, n_blocks,
+    cst = launch_batch_iteration<T>(dpairs, npairs, n_reduce, ditems, n_items, queue, n_blocks,
                                     c, s, nodes != nullptr, grouped);
   hipError_t ce = hipStreamEndCapture(s, &B.graph);
   if (cst != FGA_OK) return cst;

@@ -139,6 +139,13 @@ constexpr int kReduceRows = 256;
 __host__ __device__ inline int completion_chunks(int n_items) {
   return (n_items + kReduceRows - 1) / kReduceRows;
 }
+// Blocks of the reduction launch: one block sums up to kOneBlockRows rows by
+// itself (no second level, no cross-block completion); more rows take one
+// block per kReduceRows rows. Never more than completion_chunks(n_items).
+constexpr int kOneBlockRows = 4096;
+__host__ __device__ inline int reduce_blocks(int n_items) {
+  return n_items <= kOneBlockRows ? 1 : completion_chunks(n_items);
+}
 
 // Geometry of one registration pair on the device, for the iteration kernels.
 struct PairDev {

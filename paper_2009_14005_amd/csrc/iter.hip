@@ -175,9 +175,12 @@ __device__ inline void sum_rows(const double* base, int r0, int r1, double (&tot
 template <int PREC>
 __device__ void reduce_step(const PairDev& pd, const IterConsts& c, int b, double* lds) {
   __shared__ int s_last;
-  const int nb = completion_chunks(pd.n_items);
+  const int nb = reduce_blocks(pd.n_items);
   double tot[kRow];
-  sum_rows<PREC>(pd.partial, b * kReduceRows, min(pd.n_items, (b + 1) * kReduceRows), tot, lds);
+  if (nb == 1)
+    sum_rows<PREC>(pd.partial, 0, pd.n_items, tot, lds);
+  else
+    sum_rows<PREC>(pd.partial, b * kReduceRows, min(pd.n_items, (b + 1) * kReduceRows), tot, lds);
   if (nb > 1) {
     double* bpart = pd.partial + (size_t)pd.n_items * kRow;  // one row per reduction block
     if (threadIdx.x == 0) {
@@ -371,13 +374,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce_step(const PairDev* pai
   __shared__ double lds[kRow * (kBlock / kWave)];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) queue[0] = 0u;
   const PairDev pd = pairs[blockIdx.y];
-  if ((int)blockIdx.x >= completion_chunks(pd.n_items) || pd.st->converged) return;
+  if ((int)blockIdx.x >= reduce_blocks(pd.n_items) || pd.st->converged) return;
   reduce_step<PREC>(pd, c, (int)blockIdx.x, lds);
 }
 
 template <int PREC>
 inline void reduce_launch(const PairDev& pd, const IterConsts& c, hipStream_t s) {
-  k_reduce_step<PREC><<<completion_chunks(pd.n_items), kBlock, 0, s>>>(pd, c);
+  k_reduce_step<PREC><<<reduce_blocks(pd.n_items), kBlock, 0, s>>>(pd, c);
 }
 
 }  // namespace
