@@ -371,6 +371,20 @@ def test_buffer_cache_reuse_and_trim():
         assert np.array_equal(R, R0) and np.array_equal(t, t0)
 
 
+def test_multi_block_reduction_matches_single_block():
+    """The reduction launch sums up to 4096 partial rows in one block, more
+    in 256-row blocks whose results the last block adds: 79 template tiles x
+    64 reference ranges (5,056 rows) and x 1 range (79 rows) give the same
+    FP64 trajectory up to summation order."""
+    X, Y, _, _ = synth.mixture_pair(21, per_comp=2600, m=20000)
+    kw = dict(theta=0.0, max_iter=10, precision=fga.PREC_FP64)
+    R1, t1, r1 = fga_run(X, Y, torch.float64, tile=1, **kw)
+    R64, t64, r64 = fga_run(X, Y, torch.float64, tile=64, **kw)
+    assert r1.interactions == r64.interactions == 10 * len(X) * len(Y)
+    assert np.abs(R1 - R64).max() < 1e-12 and np.abs(t1 - t64).max() < 1e-10, (
+        np.abs(R1 - R64).max(), np.abs(t1 - t64).max())
+
+
 def test_deterministic_repeat():
     X, Y, _, _ = synth.mixture_pair(13, per_comp=512, m=3000)
     out = [fga_run(X, Y, theta=0.5, max_iter=40)[:2] for _ in range(2)]
