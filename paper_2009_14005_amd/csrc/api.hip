@@ -282,6 +282,7 @@ struct fga_state {
   NormInfo norm;
   int tree_stats[3] = {0, 0, 0};
   std::vector<float> qhost;             // Morton-sorted template (x, y, z, c), group walk only
+  hipEvent_t qready = nullptr;          // recorded after the copy into qhost
   struct Groups {
     std::vector<int2> host;             // (first, count) of every group, Morton order
     int n = 0;
@@ -319,6 +320,7 @@ static void state_free(fga_state* S) {
   for (auto& kv : S->groups)
     for (auto& it : kv.second.items) pool_free(it.second.first, s);
   pool_free(S->ident_items, s);
+  if (S->qready) (void)hipEventDestroy(S->qready);
   delete S;
 }
 
@@ -433,6 +435,8 @@ static fga_status ensure_groups(fga_state* S, int K, int fi, fga_state::Groups**
       S->qhost.resize((size_t)S->m * 4);
       FGA_HIP(hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * S->m, hipMemcpyDeviceToHost, S->s));
       FGA_HIP(hipStreamSynchronize(S->s));
+    } else if (S->qready) {
+      FGA_HIP(hipEventSynchronize(S->qready));
     }
     fga_state::Groups gt;
     make_groups(S->qhost.data(), S->m, kWave * K, kGroupTau[fi], gt.host);
@@ -885,6 +889,15 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   st = S->f64 ? sort_points_morton<double>(1, &sy, S->Q, m, nullptr, s)
               : sort_points_morton<float>(1, &sy, S->Q, m, nullptr, s);
   if (st != FGA_OK) return fail(st);
+  if (p->theta > 0 && !S->f64 && p->group_width != 1) {
+    // the host builds the group tables from the sorted template: copy it now,
+    // so that the copy and the table building overlap the tree build below
+    S->qhost.resize((size_t)m * 4);
+    if (hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventCreateWithFlags(&S->qready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(S->qready, s) != hipSuccess)
+      return fail(FGA_E_DEVICE);
+  }
   if (p->theta > 0) {
     TreeSeg sx{0, n};
     int off[2] = {0, 0};
