@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra workloads")
-    ap.add_argument("--extras", default="direct,batched,mixture",
-                    help="comma list of extra workloads to run: direct, batched, mixture")
+    ap.add_argument("--extras", default="direct,batched,mixture,mesh",
+                    help="comma list of extra workloads to run: direct, batched, mixture, mesh")
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--plain-pairs", type=int, default=32,
                     help="pairs of the batch timed with sequential plain solves")
@@ -158,6 +158,8 @@ def main():
         out["batched"] = bench_batched(fga, torch, synth, dev, args)
     if "mixture" in extras:
         out["mixture_fp64_direct"] = bench_mixture(fga, torch, synth, dev)
+    if "mesh" in extras:
+        out["mesh"] = bench_mesh(fga, torch, synth, dev, stream)
     if args.precision_study:
         out["precision_study"] = precision_study(fga, torch, synth, dev)
     if not args.no_cpu_baseline:
@@ -212,6 +214,57 @@ def bench_direct(fga, torch, synth, dev, stream):
                      "tflops": ips * FLOP_PER_INTERACTION / 1e12,
                      "frac_fp32_vector_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR}
         log(f"  {name}: {ms:.2f} ms/iteration, {ips:.3e} interactions/s")
+    return res
+
+
+def bench_mesh(fga, torch, synth, dev, stream):
+    """1,048,576 + 1,048,576 points on a weighted triangle mesh: one
+    iteration of the registration with Barnes-Hut at theta 0.3, 0.5, 0.8
+    (group walk, autotuned) and with the direct sum, and the Barnes-Hut force
+    error against the direct sum on 4,096 template points (uniform masses,
+    the mesh's own coordinates)."""
+    log("mesh workload: 1,048,576 + 1,048,576 points")
+    X, Y, _, _ = synth.mesh_pair()
+    Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)
+    Yd = torch.as_tensor(Y, dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+
+    def timed(theta, warm, n_it):
+        st = fga.State(Xd, Yd, fga.default_params(theta=theta, tol=0.0))
+        st.step(warm)
+        torch.cuda.synchronize()
+        _, _, r0 = st.get()
+        e0.record(stream)
+        st.step(n_it)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        _, _, r1 = st.get()
+        st.close()
+        ms = e0.elapsed_time(e1) / n_it
+        inter = (r1.interactions - r0.interactions) / n_it
+        return {"ms_per_iteration": ms, "interactions_per_particle": inter / len(Y),
+                "interactions_per_s": inter / (ms * 1e-3)}
+
+    res["direct"] = timed(0.0, 1, 2)
+    log(f"  direct: {res['direct']['ms_per_iteration']:.1f} ms/iteration")
+    idx = np.random.default_rng(2).choice(len(Y), 4096, replace=False)
+    Ys = Yd[torch.as_tensor(idx, device=dev)].contiguous()
+    mX = torch.full((len(X),), 1.0 / len(X), dtype=torch.float32, device=dev)
+    Fd, _ = fga.forces(Ys, Xd, mX, None, 0.0)
+    Fd = Fd.cpu().numpy().astype(np.float64)
+    nd = np.linalg.norm(Fd, axis=1)
+    for th in (0.3, 0.5, 0.8):
+        r = timed(th, 2, 10)
+        Fb, _ = fga.forces(Ys, Xd, mX, None, th, fga.default_params(group_width=64))
+        e = np.linalg.norm(Fb.cpu().numpy().astype(np.float64) - Fd, axis=1) / nd
+        r["force_rel_err_vs_direct_median"] = float(np.median(e))
+        r["force_rel_err_vs_direct_p99"] = float(np.percentile(e, 99))
+        r["speedup_vs_direct"] = res["direct"]["ms_per_iteration"] / r["ms_per_iteration"]
+        res[f"theta_{th}"] = r
+        log(f"  theta {th}: {r['ms_per_iteration'] * 1e3:.0f} us/iteration, "
+            f"{r['interactions_per_particle']:.0f} interactions/particle, "
+            f"error vs direct median {r['force_rel_err_vs_direct_median']:.1e}")
     return res
 
 
