@@ -96,8 +96,10 @@ typedef struct {
   int leaf_size;          /* BH leaf size L: cells with at most L points are not split.
                              0 or 1 = Alg. 1 exactly (singleton leaves); 2..64 trade
                              accuracy within the BH error for fewer node visits */
-  int tile;               /* reference ranges per template tile of 256 particles (work split of
-                             one iteration); 0 = autotuned per shape class and cached */
+  int tile;               /* work split of one iteration, 0..255: reference ranges per template
+                             tile of 256 particles, or for the group walk the most parts a
+                             heavy group is split into (the largest power of two <= tile);
+                             0 = autotuned per shape class and cached */
   int check_every;        /* host checks the convergence flag every k iterations (0 = 16) */
   int group_width;        /* BH traversal (FP32 only): 1 = per-particle, every particle makes
                              the Alg. 2 accept/open decisions itself; 64 or 128 = the

@@ -112,8 +112,8 @@ fga_status check_params(const fga_params* p) {
     set_error("group_width must be 0, 1, 64 or 128 (got %d)", p->group_width);
     return FGA_E_INVALID_ARG;
   }
-  if (p->tile < 0 || p->check_every < 0) {
-    set_error("tile and check_every must be >= 0");
+  if (p->tile < 0 || p->tile > 255 || p->check_every < 0) {
+    set_error("tile must be in [0, 255] and check_every >= 0");
     return FGA_E_INVALID_ARG;
   }
   return FGA_OK;
@@ -476,7 +476,7 @@ static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap
     for (int g = 0; g < gt.n; ++g) {
       const int2 grp = gt.host[g];
       int nr = 1;
-      while (nr < cap && gt.cost[g] > target * nr) nr *= 2;
+      while (2 * nr <= cap && gt.cost[g] > target * nr) nr *= 2;  // a power of two <= cap
       for (int r = 0; r < nr; ++r)
         items.push_back({(double)gt.cost[g] / nr, make_int4(grp.x, grp.y, r | nr << 8, g)});
     }
@@ -1393,7 +1393,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
       for (int g = 0; g < (int)groups[k].size(); ++g) {
         const unsigned cg = cost[goff[k] + g];
         int nr = 1;
-        while (nr < kCap && cg > target * nr) nr *= 2;
+        while (2 * nr <= kCap && cg > target * nr) nr *= 2;
         for (int r = 0; r < nr; ++r)
           w.push_back({(double)cg / nr, make_int4(groups[k][g].x, groups[k][g].y, r | nr << 8, goff[k] + g)});
       }

@@ -164,7 +164,7 @@ struct PairDev {
   int slots;            // lanes per template particle in the Barnes-Hut traversal (1, 2, 4, 8)
   int group;            // 0: per-particle traversal; K > 0: group traversal, K particles per lane
   const int4* witems;   // group walk, one per wave: (first particle, count <= 64 K,
-                        // range r | ranges << 8, group) of the wave's particles
+                        // part r | parts << 8 (a power of two), group) of the wave's particles
   unsigned* gcost;      // optional: list entries evaluated per group are added here
   int n_groups;
   int n_witems;

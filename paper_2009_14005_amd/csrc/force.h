@@ -475,7 +475,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
     const bool act = lane < T;
     const bool shared = nd.last - nd.first + 1 > kSplitPts;
     const bool frontier = !shared && (pke & (1 << 30));
-    const bool on = act && (!frontier || node % nr == r);
+    const bool on = act && (!frontier || (node & (nr - 1)) == r);  // nr: a power of two
     const bool mine = !shared || r == 0;  // owns the node's own term or points
     const bool leaf = nd.child == -1;
     const bool twig = __float_as_uint(nd.l2) >> 31;
