@@ -3,15 +3,19 @@
 One step = one whole registration of the LiDAR-shaped pair (two 64-beam x
 1024-azimuth ring scans, 65,536 points each; Barnes-Hut theta = 0.5, FP32
 forces with Kahan tiles, FP64 rigid state, NIV masses): normalisation and
-masses, tree build, 100 fused iterations of Alg. 2, de-normalisation. The
+masses, tree build, 100 iterations of Alg. 2 (two launches each: forces,
+ODE and per-block moments; then the moment sum and the Kabsch step),
+de-normalisation. The
 iteration count is fixed (tol = 0) so every step does the same work.
 
 Printed on stdout: one JSON line. `value` is force interactions per second
 over the whole step (inputs already resident in HBM). Extra fields report the
-fused BH iteration kernel against the FP32 vector peak (`roofline`), the
+Barnes-Hut iteration against the FP32 vector peak (`roofline`), the
 direct-sum kernel on the 131,072 x 131,072 precision-study shape, batched
-versus plain registrations/s on the 256-pair workload, and the FP64 oracle
-timed on the host cores on a bounded sample (`cpu_baseline`).
+versus plain registrations/s on the 256-pair workload, the 1,024-point FP64
+mixture, the 1,048,576-point mesh (Barnes-Hut theta sweep against the
+direct sum), and the FP64 oracle timed on the host cores on a bounded sample
+(`cpu_baseline`).
 """
 import argparse
 import json
@@ -97,7 +101,8 @@ def main():
     phi = float(np.degrees(np.arccos(np.clip(0.5 * (np.trace(R_gt.T @ R) - 1), -1, 1))))
     diag = float(np.linalg.norm(X.max(0) - X.min(0)))
 
-    # the dominant kernel: one fused BH iteration per launch, timed with events
+    # the dominant work: one BH iteration (force launch + reduction launch),
+    # timed with events on the library's stream
     st = fga.State(Xd, Yd, p)
     st.step(5)
     torch.cuda.synchronize()
@@ -113,7 +118,7 @@ def main():
     it_ms = e0.elapsed_time(e1) / n_it
     it_inter = (r1.interactions - r0.interactions) / n_it
     achieved = it_inter * FLOP_PER_INTERACTION / (it_ms * 1e-3)
-    log(f"fused BH iteration: {it_ms * 1e3:.1f} us, {it_inter:.3e} interactions/iteration, "
+    log(f"BH iteration: {it_ms * 1e3:.1f} us, {it_inter:.3e} interactions/iteration, "
         f"{achieved / 1e12:.2f} TFLOP/s")
     out = {
         "metric": "force interactions/s (% FP32 VALU peak) + registrations/s, batched vs plain",
@@ -191,7 +196,7 @@ def measured_traffic():
 
 def bench_direct(fga, torch, synth, dev, stream):
     """Direct all-pairs kernel on the 131,072 x 131,072 precision-study shape,
-    as the fused iteration of a registration (FP32 Kahan tiles)."""
+    as the iteration of a registration (FP32 Kahan tiles)."""
     log("direct kernel: 131,072 x 131,072")
     X, Y, _, _ = synth.precision_pair()
     Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)

@@ -225,7 +225,8 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
 template <typename T>
 fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipStream_t s);
 
-// iter.hip: one fused iteration (forces + ODE + moments + Kabsch step)
+// iter.hip: one iteration as two launches (pose, forces, ODE and per-block
+// moments; then the ordered moment sum and the Kabsch step)
 template <typename T>
 fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s);
 template <typename T>

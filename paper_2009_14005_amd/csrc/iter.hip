@@ -1,4 +1,5 @@
-// Steps a2-a7 of the hot path, fused into one launch per iteration:
+// Steps a2-a7 of the hot path, two launches per iteration (a2-a6 in the force
+// launch, the end of a6 and a7 in the reduction launch):
 //   a2  template pose y_i = R q_i + mu                  (FP64 state -> FP32 lanes)
 //   a3/a4 acceleration g_i by direct sum or Barnes-Hut  (Eq. GAForce; Alg. 2)
 //   a5  damped velocity and displacement               (Eqs. GAForceDissipative,
@@ -202,7 +203,7 @@ __device__ void reduce_step(const PairDev& pd, const IterConsts& c, int b, doubl
   }
 }
 
-// One item of the fused iteration with one particle per S lanes (the direct
+// One item of the force launch with one particle per S lanes (the direct
 // sum with S = 1, or the per-particle Barnes-Hut traversal).
 template <typename T, bool BH, int PREC, int S>
 __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,

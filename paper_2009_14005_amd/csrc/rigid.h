@@ -1,8 +1,8 @@
 // FP64 rigid step of the FGA loop body: Kabsch rotation (Eq. R_Kabsch),
 // translation (Eq. transEst) and the template update / composition of Alg. 2.
 // Compiled for both host and device: the device runs it once per iteration in
-// the last block of the fused iteration kernel; the host entry fga_kabsch
-// exposes the same solver for tests.
+// the last block of the reduction launch; the host entry fga_kabsch exposes
+// the same solver for tests.
 #pragma once
 #include <math.h>
 
