@@ -123,3 +123,22 @@ def test_lidar_registration_bench_config():
             assert abs(rep.interactions - ref["interactions"]) <= 1e-3 * ref["interactions"]
         else:
             assert rep.interactions >= (1 - 1e-3) * ref["interactions"]
+
+
+def test_batched_256_pairs_sampled_against_plain_fp64():
+    """The 256-pair serving workload in one batched call (group walk, FP32
+    forces, per-pair stop rule) against plain FP64 registrations of a sample
+    of pairs: equal final rotation and translation within the registration
+    gates, every pair stopped by the rule within the iteration cap."""
+    pairs = synth.batch_pairs()
+    prm = fga.default_params(theta=0.5, max_iter=200)
+    R, t, reps = fga.register_batch([dev(p[0]) for p in pairs], [dev(p[1]) for p in pairs], prm)
+    assert np.isfinite(R).all() and np.isfinite(t).all()
+    assert all(r.traversal == 64 and 0 < r.iters <= 200 for r in reps)
+    p64 = fga.default_params(theta=0.5, max_iter=200, precision=fga.PREC_FP64)
+    for k in np.random.default_rng(5).choice(len(pairs), 8, replace=False):
+        X, Y = pairs[k][0], pairs[k][1]
+        Rp, tp, _ = fga.register(dev(X, torch.float64), dev(Y, torch.float64), p64)
+        phi = oracle.angular_deviation_deg(Rp, R[k])
+        dtn = np.linalg.norm(tp - t[k]) / np.linalg.norm(X.max(0) - X.min(0))
+        assert phi < 0.05 and dtn < 1e-4, (k, phi, dtn)
