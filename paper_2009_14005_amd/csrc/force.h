@@ -422,7 +422,36 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
   bool ok = true;
   int cnt = 0;  // list entries
   int sp = 1;   // stack entries; the root is a block of one node at index 0
-  if (lane == 0) g.stk[0] = kLargeParent;
+  {
+    // The top two levels, decided up front: when the root, and then every
+    // child of the root, is an internal node that is not a twig, holds more
+    // than kSplitPts points (so every part walks it) and fails the MAC
+    // against the group's box, the walk starts from their child blocks
+    // instead: the same nodes are visited and accepted, two steps sooner.
+    auto walked_open = [&](const BHWide& b) {
+      float d2 = 0.f;
+      const float c3[3] = {b.cm.x, b.cm.y, b.cm.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float u = fmaxf(fmaxf(lo[a] - c3[a], c3[a] - hi[a]), 0.f);
+        d2 = fmaf(u, u, d2);
+      }
+      return b.child != -1 && !(__float_as_uint(b.l2) >> 31) && b.last - b.first + 1 > kSplitPts &&
+             !(fabsf(b.l2) < theta2 * d2);
+    };
+    const BHWide root = nodes[0];
+    int top = kLargeParent;
+    if (walked_open(root)) {
+      top = root.child | kLargeParent;
+      const int nc = (int)((unsigned)root.child >> kChildShift) + 1;
+      const BHWide ch = nodes[min((root.child & ((1 << kChildShift) - 1)) + lane, n_nodes - 1)];
+      if (__ballot(lane < nc && !walked_open(ch)) == 0ull) {
+        if (lane < nc) g.stk[lane] = ch.child | kLargeParent;
+        sp = nc;
+      }
+    }
+    if (sp == 1 && lane == 0) g.stk[0] = top;
+  }
   auto flush = [&]() {
     if (R == 1) {
       group_sum<K, KAHAN>(g.list, cnt, y, eps2, sel, acc, cmp);
