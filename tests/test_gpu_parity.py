@@ -290,6 +290,30 @@ def test_register_config0_bh_traversals(gw):
     assert rep.traversal == gw
 
 
+@pytest.mark.parametrize("tile", [3, 5])
+def test_register_group_walk_user_split_cap(tile):
+    """A user part cap that is not a power of two: heavy groups are split into
+    the largest power of two of parts within it."""
+    X, Y, _, _ = synth.mixture_pair(17, per_comp=512, m=3000)
+    ref = oracle_run(X, Y, 0.5, 60)
+    R, t, rep = fga_run(X, Y, theta=0.5, max_iter=60, group_width=64, tile=tile)
+    assert rep.traversal == 64
+    check_transform(R, t, ref, X)
+
+
+@pytest.mark.parametrize("per", [4, 5])
+def test_register_group_walk_tiny_reference(per):
+    """32 reference points (the root is not walked by every part, so the walk
+    starts at the root) and 40 (the root is, its children are not, so the
+    walk starts one level down). Smaller clouds are too ill-conditioned for
+    the registration gates: at 16 points FP32 and FP64 runs of the same
+    per-particle walk already end 1.7 degrees apart."""
+    X, Y, _, _ = synth.mixture_pair(18, per_comp=per, m=8 * per - 3)
+    ref = oracle_run(X, Y, 0.5, 80)
+    R, t, rep = fga_run(X, Y, theta=0.5, max_iter=80, group_width=64)
+    check_transform(R, t, ref, X)
+
+
 @pytest.mark.parametrize("prec", [fga.PREC_FP32, fga.PREC_FP32_ALL])
 def test_register_group_precisions(prec):
     X, Y, _, _ = synth.mixture_pair(15, per_comp=512, m=3000)
