@@ -1256,6 +1256,15 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     xs[k] = {xoff[k], n[k]};
   }
   FGA_TRY(sort_points_morton<T>(npairs, ys.data(), Qp, NY, nullptr, s));
+  // the host builds the group tables from the sorted templates: copy them
+  // before the trees are built, so that the table building overlaps the build
+  const bool grouped = sizeof(T) == 4 && p.theta > 0 && p.group_width != 1;
+  std::vector<float> qh;
+  if (grouped) {
+    qh.resize((size_t)NY * 4);
+    FGA_HIP(hipMemcpyAsync(qh.data(), Qp, sizeof(float) * 4 * NY, hipMemcpyDeviceToHost, s));
+    FGA_HIP(hipEventRecord(B.ev, s));
+  }
   BHWide* nodes = nullptr;
   std::vector<int> noff(npairs + 1, 0);
   int tstats[3];
@@ -1273,14 +1282,11 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
   // the group walk (FP32 Barnes-Hut unless group_width = 1) with one particle
   // per lane: groups bounded by twice the median box of fixed 64-runs, split
   // by measured cost
-  const bool grouped = sizeof(T) == 4 && p.theta > 0 && p.group_width != 1;
   std::vector<PairDev> pds(npairs);
   std::vector<std::vector<int2>> groups(npairs);
   std::vector<int> goff(npairs + 1, 0);
   if (grouped) {
-    std::vector<float> qh((size_t)NY * 4);
-    FGA_HIP(hipMemcpyAsync(qh.data(), Qp, sizeof(float) * 4 * NY, hipMemcpyDeviceToHost, s));
-    FGA_HIP(hipStreamSynchronize(s));
+    FGA_HIP(hipEventSynchronize(B.ev));
     for (int k = 0; k < npairs; ++k) {
       make_groups(qh.data() + 4 * yoff[k], m[k], kWave, kGroupTau[2], groups[k]);
       goff[k + 1] = goff[k] + (int)groups[k].size();
