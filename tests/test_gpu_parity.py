@@ -452,6 +452,25 @@ def test_batch_matches_plain(gw):
         assert np.linalg.norm(t1 - t[k]) / np.linalg.norm(X.max(0) - X.min(0)) < 1e-4
 
 
+def test_batch_zero_and_one_iteration():
+    """No iteration leaves every pair at its start (identity rotation); one
+    iteration (the one that measures the group costs) agrees with the plain
+    path's first iteration within the registration gates."""
+    pairs = [synth.mixture_pair(200 + k, per_comp=64, m=400) for k in range(3)]
+    Xs, Ys = [dev(p[0]) for p in pairs], [dev(p[1]) for p in pairs]
+    for it in (0, 1):
+        prm = fga.default_params(theta=0.5, max_iter=it, tol=0.0)
+        R, t, reps = fga.register_batch(Xs, Ys, prm)
+        for k, (X, Y, _, _) in enumerate(pairs):
+            R1, t1, rep1 = fga.register(Xs[k], Ys[k], prm)
+            assert reps[k].iters == rep1.iters == it
+            if it == 0:
+                assert np.array_equal(R[k], np.eye(3)) and np.allclose(t[k], t1)
+            else:
+                assert phi_deg(R1, R[k]) < 0.05
+                assert np.linalg.norm(t1 - t[k]) / np.linalg.norm(X.max(0) - X.min(0)) < 1e-4
+
+
 @pytest.mark.parametrize("prec", [fga.PREC_FP32, fga.PREC_FP32_ALL])
 def test_batch_precisions_match_oracle(prec):
     pairs = [synth.batch_pair(k) for k in range(2)]
