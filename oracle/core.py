@@ -77,6 +77,8 @@ def lib():
         L.oracle_gpe.restype = d
         L.oracle_bh_build.argtypes = [v, v, l]
         L.oracle_bh_build.restype = v
+        L.oracle_bh_build_leaf.argtypes = [v, v, l, l]
+        L.oracle_bh_build_leaf.restype = v
         L.oracle_bh_free.argtypes = [v]
         L.oracle_bh_stats.argtypes = [v, v]
         L.oracle_bh_root.argtypes = [v, v]
@@ -205,12 +207,14 @@ def gpe(Y, X, mX, mY=None, G=66.7, eps=0.2):
 
 
 class BHTree:
-    """Alg. 1 tree on (X, mX), uncompressed, built once (X is static)."""
+    """Alg. 1 tree on (X, mX), uncompressed, built once (X is static).
+    ``leaf`` > 1 stops the split at cells of at most that many points (the
+    leaf-size variant; 1 is Alg. 1 itself)."""
 
-    def __init__(self, X, mX):
+    def __init__(self, X, mX, leaf=1):
         self.X = _c(X)
         self.mX = _c(mX)
-        self.h = lib().oracle_bh_build(_p(self.X), _p(self.mX), len(self.X))
+        self.h = lib().oracle_bh_build_leaf(_p(self.X), _p(self.mX), len(self.X), int(leaf))
         if not self.h:
             raise ValueError("empty reference")
 

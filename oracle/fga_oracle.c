@@ -13,6 +13,9 @@
  *                            plain double loop.
  *   - oracle_bh_build      : Alg. 1 (Build BH tree), recursive 2^D split of
  *                            the reference bounding box, uncompressed.
+ *   - oracle_bh_build_leaf : the same split stopped at cells of at most L
+ *                            points (L = 1 is Alg. 1 itself), the leaf-size
+ *                            variant of the tree that the GPU path can build.
  *   - oracle_bh_forces     : Alg. 2, function BHForce, recursive descent with
  *                            the multipole acceptance criterion Eq. (MAC).
  *   - oracle_gpe           : Plummer potential energy, a diagnostic whose
@@ -112,6 +115,7 @@ typedef struct otree {
   unsigned* q;           /* n x 3 quantised coordinates */
   double lo[3], hi[3];
   long n_nodes, n_leaves, n_internal, n_branching, max_depth;
+  long leaf;             /* cells with at most this many points are leaves (Alg. 1: 1) */
   long* pool;            /* index storage: one slice per depth level */
 } otree;
 
@@ -144,7 +148,9 @@ static void create_child(otree* t, onode* nd, const double diag_root) {
   nd->com[2] = cz / m;
   t->n_nodes++;
   if (nd->depth > t->max_depth) t->max_depth = nd->depth;
-  if (nd->npts < 2 || nd->depth >= QBITS) {  /* singleton or depth-20 leaf */
+  /* Alg. 1 splits a cell while it holds more than one point; the leaf-size
+   * variant stops at cells of at most `leaf` points. Depth-20 cells are leaves. */
+  if (nd->npts <= t->leaf || nd->depth >= QBITS) {
     t->n_leaves++;
     return;
   }
@@ -188,12 +194,14 @@ static void create_child(otree* t, onode* nd, const double diag_root) {
   if (nonempty >= 2) t->n_branching++;
 }
 
-/* Alg. 1: build the BH tree on the reference X (n x 3) with masses mX.
- * Returns an opaque handle, or NULL for n < 1. */
-void* oracle_bh_build(const double* X, const double* mX, long n) {
-  if (n < 1) return NULL;
+/* Alg. 1 with leaves of at most `leaf` points (leaf = 1: Alg. 1 itself) on
+ * the reference X (n x 3) with masses mX. Returns an opaque handle, or NULL
+ * for n < 1 or leaf < 1. */
+void* oracle_bh_build_leaf(const double* X, const double* mX, long n, long leaf) {
+  if (n < 1 || leaf < 1) return NULL;
   otree* t = (otree*)calloc(1, sizeof(otree));
   t->n = n;
+  t->leaf = leaf;
   t->X = X;
   t->mX = mX;
   for (int a = 0; a < 3; ++a) {
@@ -224,6 +232,11 @@ void* oracle_bh_build(const double* X, const double* mX, long n) {
   t->root = new_node(0, t->pool, n);
   create_child(t, t->root, sqrt(d2));
   return t;
+}
+
+/* Alg. 1: build the BH tree on the reference X (n x 3) with masses mX. */
+void* oracle_bh_build(const double* X, const double* mX, long n) {
+  return oracle_bh_build_leaf(X, mX, n, 1);
 }
 
 static void free_node(onode* nd) {

@@ -546,55 +546,17 @@ def test_host_pointer_rejected():
 
 
 # ------------------------------------------------------------ leaf size
-def _literal_leaf_tree_forces(X, m, Y, theta, L):
-    """Alg. 2 BHForce on the Alg. 1 tree with leaf size L (cells of at most L
-    points are not split), written out in Python from the quantised codes."""
-    q = oracle.BHTree(X, m).quant().astype(np.int64)
-    lo, hi = X.min(0), X.max(0)
-    lroot = np.linalg.norm(hi - lo)
-    digits = np.stack([((q[:, 0] >> (19 - k)) & 1) * 4 + ((q[:, 1] >> (19 - k)) & 1) * 2
-                       + ((q[:, 2] >> (19 - k)) & 1) for k in range(20)], 1)
-
-    def build(idx, depth):
-        node = dict(idx=idx, l=lroot / 2 ** depth, mass=m[idx].sum(),
-                    com=(m[idx, None] * X[idx]).sum(0) / m[idx].sum(), kids=[])
-        if len(idx) > L and depth < 20:
-            for dgt in range(8):
-                sub = idx[digits[idx, depth] == dgt]
-                if len(sub):
-                    node["kids"].append(build(sub, depth + 1))
-        return node
-
-    root = build(np.arange(len(X)), 0)
-    out = np.zeros_like(Y)
-    for i, y in enumerate(Y):
-        acc = np.zeros(3)
-        stack = [root]
-        while stack:
-            nd = stack.pop()
-            d = y - nd["com"]
-            r = np.sqrt(d @ d)
-            if r > 0 and nd["l"] / r < theta:
-                acc -= nd["mass"] * d / (d @ d + 0.04) ** 1.5
-            elif not nd["kids"]:
-                e = y - X[nd["idx"]]
-                acc -= (m[nd["idx"], None] * e / ((e * e).sum(1) + 0.04)[:, None] ** 1.5).sum(0)
-            else:
-                stack.extend(nd["kids"])
-        out[i] = 66.7 * acc
-    return out
-
-
 @pytest.mark.parametrize("L", [4, 16])
 def test_leaf_size_matches_literal_tree(L):
     X, m = _tree_case(17, 3000)
     rng = np.random.default_rng(18)
     Y = (X[rng.choice(len(X), 200, replace=False)] + rng.normal(size=(200, 3)) * 0.02)
     Y = Y.astype(np.float32).astype(np.float64)
-    ref = _literal_leaf_tree_forces(X, m, Y, 0.5, L)
-    F, _ = fga.forces(dev(Y), dev(X), dev(m), None, 0.5, fga.default_params(leaf_size=L))
+    ref, cnt = oracle.BHTree(X, m, leaf=L).forces(Y, None, 66.7, 0.2, 0.5, count=True)
+    F, c = fga.forces(dev(Y), dev(X), dev(m), None, 0.5, fga.default_params(leaf_size=L, group_width=1))
     e = rel_err(F.cpu().numpy().astype(np.float64), ref)
     assert np.median(e) <= 1e-5, np.median(e)
+    assert abs(c - cnt) <= 1e-3 * cnt, (c, cnt)
     t = fga.Tree(dev(X), dev(m), fga.default_params(leaf_size=L))
     ex = t.export()
     leaf = ex["skip"] == np.arange(t.info()["nodes"]) + 1

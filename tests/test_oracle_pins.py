@@ -420,3 +420,232 @@ def test_stop_rule_waits_for_shrinking_steps(oracle_lib):
     assert h[0] < h[5]                       # accelerating start
     assert h[-1] < 1e-8 and h[-1] < h[-2]    # stopped on a shrinking, small step
     assert all(not (h[k] < 1e-8 and h[k] < h[k - 1]) for k in range(1, len(h) - 1))
+
+
+# ------------------------------------- node length below the root (Alg. 1)
+# Four unit masses: A at the origin and B1, B2, B3 on the main diagonal. The
+# root box is [0, 8]^3 (diagonal 8 sqrt 3). By the midpoint splits of Alg. 1,
+# B1 = (8,8,8), B2 = (5,5,5), B3 = (6.5,6.5,6.5) share the depth-1 cell
+# [4,8]^3; B1 and B3 share the depth-2 cell [6,8]^3 and part at depth 3; A and
+# B2 end up alone. The query sits far out on the other side of the origin, so
+# that each internal cell flips between accepted and opened at its own
+# theta = l_k / r_k with l_k the root diagonal halved k times.
+_NODE_PTS = np.array([[0.0, 0, 0], [8.0, 8, 8], [5.0, 5, 5], [6.5, 6.5, 6.5]])
+_NODE_Y = np.array([[-20.0, -20.0, -20.0]])
+
+
+def _single_body(y, pts):
+    """Eq. (GAForce) of unit masses `pts` merged into one body at their mean."""
+    d = y - pts.mean(0)
+    r2 = d @ d + EPS ** 2
+    return -G * len(pts) * d / r2 ** 1.5
+
+
+def _point_sum(y, pts):
+    return sum(_single_body(y, p[None]) for p in pts)
+
+
+def _check_node_lengths(bh_force):
+    """bh_force(theta) -> force on _NODE_Y[0]. Raises AssertionError when the
+    accept/open flips do not happen at l_k = diag(root) 2^-k."""
+    y = _NODE_Y[0]
+    A, B1, B2, B3 = _NODE_PTS
+    diag = 8.0 * np.sqrt(3.0)
+    c1 = np.array([B1, B2, B3])
+    c2 = np.array([B1, B3])
+    th1 = (diag / 2) / np.linalg.norm(y - c1.mean(0))
+    th2 = (diag / 4) / np.linalg.norm(y - c2.mean(0))
+    fA = _point_sum(y, A[None])
+    cases = [
+        (th1 * (1 + 1e-9), fA + _single_body(y, c1)),                       # depth-1 cell accepted
+        (th1 * (1 - 1e-9), fA + _point_sum(y, B2[None]) + _single_body(y, c2)),  # opened; depth 2 accepted
+        (th2 * (1 + 1e-9), fA + _point_sum(y, B2[None]) + _single_body(y, c2)),
+        (th2 * (1 - 1e-9), _point_sum(y, _NODE_PTS)),                       # everything exact
+    ]
+    for th, ref in cases:
+        got = bh_force(th)
+        assert np.allclose(got, ref, rtol=1e-13, atol=0), (th, got, ref)
+    # the four cases are distinct, so a shifted threshold cannot pass by accident
+    refs = [c[1] for c in cases]
+    assert not np.allclose(refs[0], refs[1], rtol=1e-8)
+    assert not np.allclose(refs[2], refs[3], rtol=1e-8)
+
+
+def test_bh_node_length_halves_per_level(oracle_lib):
+    t = oracle.BHTree(_NODE_PTS, np.ones(4))
+    assert t.stats()["internal"] == 3  # root, [4,8]^3, [6,8]^3
+    _check_node_lengths(lambda th: t.forces(_NODE_Y, None, G, EPS, th)[0])
+
+
+def _mutated_oracle(tmp_path, old, new):
+    """The oracle's C source with one planted change, built into a separate
+    library (the planted mistake lives in the oracle, on the CPU)."""
+    import ctypes
+    import subprocess
+    src = open(os.path.join(os.path.dirname(oracle.core.__file__), "fga_oracle.c")).read()
+    assert old in src
+    path = tmp_path / "mut.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmut.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", str(path), "-o", str(so), "-lm"])
+    L = ctypes.CDLL(str(so))
+    v, l, d = ctypes.c_void_p, ctypes.c_long, ctypes.c_double
+    L.oracle_bh_build.argtypes = [v, v, l]
+    L.oracle_bh_build.restype = v
+    L.oracle_bh_forces.argtypes = [v, v, l, v, d, d, d, v, v]
+    X = np.ascontiguousarray(_NODE_PTS)
+    m = np.ones(4)
+    h = L.oracle_bh_build(X.ctypes.data, m.ctypes.data, 4)
+
+    def force(th):
+        F = np.zeros((1, 3))
+        Y = np.ascontiguousarray(_NODE_Y)
+        L.oracle_bh_forces(h, Y.ctypes.data, 1, None, G, EPS, th, F.ctypes.data, None)
+        return F[0]
+    return force
+
+
+@pytest.mark.parametrize("old,new", [
+    # one level off: the root's children get the root's length
+    ("nd->l = ldexp(diag_root, -nd->depth);", "nd->l = ldexp(diag_root, 1 - nd->depth);"),
+    # one level too short
+    ("nd->l = ldexp(diag_root, -nd->depth);", "nd->l = ldexp(diag_root, -nd->depth - 1);"),
+    # the longest side instead of the diagonal
+    ("for (int a = 0; a < 3; ++a) d2 += (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]);",
+     "for (int a = 0; a < 3; ++a) d2 = fmax(d2, (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]));"),
+])
+def test_node_length_pin_catches_planted_mistakes(oracle_lib, tmp_path, old, new):
+    force = _mutated_oracle(tmp_path, old, new)
+    with pytest.raises(AssertionError):
+        _check_node_lengths(force)
+
+
+# --------------------------------------------- leaf-size variant of Alg. 1
+def _independent_leaves_cap(X, L):
+    """Leaf sets of the tree whose cells of at most L points are not split:
+    a point's leaf is the shortest octal prefix of its quantised code shared
+    by at most L points (or the full 20 digits)."""
+    lo, hi = X.min(0), X.max(0)
+    ext = hi - lo
+    q = np.zeros(X.shape, dtype=np.int64)
+    for a in range(3):
+        if ext[a] > 0:
+            q[:, a] = np.minimum(np.floor((X[:, a] - lo[a]) / ext[a] * 2.0 ** 20), 2 ** 20 - 1)
+    digits = np.stack([((q[:, 0] >> b) & 1) * 4 + ((q[:, 1] >> b) & 1) * 2 + ((q[:, 2] >> b) & 1)
+                       for b in range(19, -1, -1)], 1)
+    keys = [tuple(r) for r in digits]
+    leaves = {}
+    for j, key in enumerate(keys):
+        for k in range(0, 21):
+            pre = key[:k]
+            share = sum(1 for kk in keys if kk[:k] == pre)
+            if share <= L or k == 20:
+                leaves.setdefault(pre, []).append(j)
+                break
+    return sorted(tuple(sorted(v)) for v in leaves.values())
+
+
+@pytest.mark.parametrize("L", [2, 5, 16])
+def test_leaf_size_tree_leaves(oracle_lib, L):
+    rng = np.random.default_rng(40 + L)
+    X = np.vstack([rng.normal(size=(150, 3)), rng.normal(size=(6, 3)) * 1e-6])
+    X = np.vstack([X, X[:2], X[:2]])  # triplicates: depth-20 leaves above L = 2
+    t = oracle.BHTree(X, np.ones(len(X)), leaf=L)
+    n, ids = t.leaves()
+    got = sorted(tuple(sorted(np.flatnonzero(ids == k))) for k in range(n))
+    assert got == _independent_leaves_cap(X, L)
+
+
+def test_leaf_size_one_is_alg1(oracle_lib):
+    X, Y, _, _ = synth.mixture_pair(41, per_comp=64, m=200)
+    mX = np.random.default_rng(2).uniform(0.5, 1.5, len(X))
+    a = oracle.BHTree(X, mX).forces(Y, None, G, EPS, 0.5, count=True)
+    b = oracle.BHTree(X, mX, leaf=1).forces(Y, None, G, EPS, 0.5, count=True)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
+
+
+@pytest.mark.parametrize("L", [4, 16])
+def test_leaf_size_theta_zero_is_direct(oracle_lib, L):
+    X, Y, _, _ = synth.mixture_pair(42, per_comp=64, m=200)
+    mX = np.full(len(X), 1.0 / len(X))
+    F, cnt = oracle.BHTree(X, mX, leaf=L).forces(Y, None, G, EPS, 0.0, count=True)
+    Fd = oracle.direct_forces(Y, X, mX, None, G, EPS)
+    assert cnt == len(X) * len(Y)
+    assert np.allclose(F, Fd, rtol=1e-12, atol=1e-12 * np.abs(Fd).max())
+
+
+def test_leaf_size_whole_set_is_one_leaf(oracle_lib):
+    """With L >= n the root is the only node: a query it does not accept gets
+    the exact sum over every point, one it accepts the single-body term."""
+    rng = np.random.default_rng(43)
+    X = rng.normal(size=(40, 3))
+    m = np.ones(40)
+    t = oracle.BHTree(X, m, leaf=40)
+    assert t.stats()["nodes"] == 1
+    near, far = rng.normal(size=(1, 3)), np.array([[300.0, 0, 0]])
+    F, c = t.forces(near, None, G, EPS, 0.5, count=True)
+    assert c == 40 and np.allclose(F[0], _point_sum(near[0], X), rtol=1e-12)
+    F, c = t.forces(far, None, G, EPS, 0.5, count=True)
+    assert c == 1 and np.allclose(F[0], _single_body(far[0], X), rtol=1e-12)
+
+
+# ------------------------------- mass normalisation (Eq. FinalSPM, B = 1)
+def test_masses_normalisation_two_cells():
+    """Three points in one lattice cell and one in another: NIV is inversely
+    proportional to the cell count (1/3, 1/3, 1/3, 1), so the reference weights
+    normalised to sum 1 are (1/6, 1/6, 1/6, 1/2) and the template masses
+    normalised to mean 1 are (2/3, 2/3, 2/3, 2)."""
+    P = np.array([[0.0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.01], [1.0, 1, 1]])
+    mX, mY = oracle.masses(P, P.copy(), oracle.Params())
+    assert np.allclose(mX, [1 / 6, 1 / 6, 1 / 6, 1 / 2], rtol=1e-14)
+    assert np.allclose(mY, [2 / 3, 2 / 3, 2 / 3, 2.0], rtol=1e-14)
+    assert np.isclose(mX.sum(), 1.0, rtol=1e-15) and np.isclose(mY.mean(), 1.0, rtol=1e-15)
+    uX, uY = oracle.masses(P, P[:3], oracle.Params(masses="uniform"))
+    assert np.allclose(uX, 0.25) and np.allclose(uY, 1.0) and len(uY) == 3
+
+
+def test_masses_pin_catches_swapped_normalisation(monkeypatch):
+    P = np.array([[0.0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.01], [1.0, 1, 1]])
+    real = oracle.core.niv_masses
+    # planted: template masses normalised to sum 1 like the reference weights
+    monkeypatch.setattr(oracle.core, "masses",
+                        lambda a, b, p: (real(a) / real(a).sum(), real(b) / real(b).sum()))
+    with pytest.raises(AssertionError):
+        mX, mY = oracle.core.masses(P, P.copy(), oracle.Params())
+        assert np.allclose(mY, [2 / 3, 2 / 3, 2 / 3, 2.0], rtol=1e-14)
+
+
+# ------------------------------- per-particle velocity (Eq. PreviousVelocity)
+def _particle_velocity_unrolled(velocity):
+    """With fraction damping and no projection of the velocity, v after k
+    steps is the damped sum of the past accelerations:
+    v_2 = (1 - eta) dt g(Y_0) + dt g(Y_1). Returns (stepper V, unrolled sum)."""
+    X, Y, _, _ = synth.mixture_pair(44, per_comp=32, m=150)
+    Xn, Yn, _ = oracle.normalise(X, Y)
+    mX = np.full(len(Xn), 1 / len(Xn))
+    p = oracle.Params(velocity=velocity)
+    st = oracle.Stepper(Xn, Yn, mX, np.ones(len(Yn)), p)
+    Y0 = st.Y.copy()
+    st.step()
+    Y1 = st.Y.copy()
+    st.step()
+    g0 = oracle.direct_forces(Y0, Xn, mX, None, p.G, p.eps)
+    g1 = oracle.direct_forces(Y1, Xn, mX, None, p.G, p.eps)
+    return st.V, (1 - p.eta) * p.dt * g0 + p.dt * g1
+
+
+def test_particle_velocity_is_damped_sum_of_accelerations(oracle_lib):
+    V, ref = _particle_velocity_unrolled("particle")
+    assert np.allclose(V, ref, rtol=1e-12, atol=1e-14)
+    # the rigid reading carries a different state: the planted swap fails the pin
+    Vr, refr = _particle_velocity_unrolled("rigid")
+    assert not np.allclose(Vr, refr, rtol=1e-6)
+
+
+def test_particle_velocity_exact_recovery(oracle_lib):
+    """Noise-free full overlap with uniform masses: the per-particle velocity
+    reading converges to the ground-truth transform like the rigid one."""
+    X, Y, R_gt, t_gt = synth.uniform_grid_pair(24, n_side=7, max_deg=30.0)
+    res = oracle.register(X, Y, oracle.Params(max_iter=400, masses="uniform", velocity="particle"))
+    assert oracle.angular_deviation_deg(R_gt, res["R"]) < 1e-3
+    assert np.linalg.norm(res["t"] - t_gt) < 1e-4
