@@ -352,8 +352,9 @@ def register(X, Y, p: Params = None, trace=False):
             hist.append((st.R.copy(), st.t.copy(), dT2))
         # stop rule of Alg. 2 (reading): the step has fallen below tol while
         # shrinking; the test is skipped while the motion is still speeding up
-        # from rest, where the first steps are also small
-        if p.tol > 0 and dT2 < p.tol and dT2 < prev:
+        # from rest, where the first steps are also small, and at the first
+        # iteration, which has no earlier step to compare with
+        if p.tol > 0 and st.iters >= 2 and dT2 < p.tol and dT2 < prev:
             converged = True
             break
         prev = dT2

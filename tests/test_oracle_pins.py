@@ -649,3 +649,16 @@ def test_particle_velocity_exact_recovery(oracle_lib):
     res = oracle.register(X, Y, oracle.Params(max_iter=400, masses="uniform", velocity="particle"))
     assert oracle.angular_deviation_deg(R_gt, res["R"]) < 1e-3
     assert np.linalg.norm(res["t"] - t_gt) < 1e-4
+
+
+def test_stop_rule_never_fires_at_the_first_iteration(oracle_lib):
+    """A threshold above every step size (1e-4 on the squared norm, the
+    printed value read as a bound on the square): the first iteration has no
+    earlier step to be smaller than, so the earliest stop is the second
+    iteration, and then only if that step is smaller than the first."""
+    X, Y, _, _ = synth.mixture_pair()
+    res = oracle.register(X, Y, oracle.Params(max_iter=300, tol=1e-4), trace=True)
+    h = [x[2] for x in res["history"]]
+    assert res["converged"] and res["iters"] >= 2
+    k = next(k for k in range(1, len(h)) if h[k] < 1e-4 and h[k] < h[k - 1])
+    assert res["iters"] == k + 1
