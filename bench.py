@@ -1,23 +1,32 @@
 """Benchmark of the FGA hot path on one MI355X.
 
-One step = one whole registration of the LiDAR-shaped pair (two 64-beam x
-1024-azimuth ring scans, 65,536 points each; Barnes-Hut theta = 0.5, FP32
-forces with Kahan tiles, FP64 rigid state, NIV masses): normalisation and
-masses, tree build, 100 iterations of Alg. 2 (two launches each: forces,
-ODE and per-block moments; then the moment sum and the Kabsch step),
-de-normalisation. The
-iteration count is fixed (tol = 0) so every step does the same work.
+One step = one whole registration of the large inhomogeneous pair: two
+independent 1,048,576-point samples of a weighted 2,000-triangle mesh
+(template rotated up to 45 degrees), Barnes-Hut theta = 0.5, FP32 forces with
+Kahan tiles, FP64 moments and rigid state, NIV masses: normalisation and
+masses, tree build, 100 iterations of Alg. 2 (two launches each: forces, ODE
+and per-block moments; then the moment sum and the Kabsch step), and the
+de-normalisation. The iteration count is fixed (tol = 0) so every step does
+the same work.
 
-Printed on stdout: one JSON line. `value` is force interactions per second
-over the whole step (inputs already resident in HBM). Extra fields report the
-Barnes-Hut iteration against the FP32 vector peak (`roofline`), the
-direct-sum kernel on the 131,072 x 131,072 precision-study shape, batched
-versus plain registrations/s on the 256-pair workload, the 1,024-point FP64
-mixture, the 1,048,576-point mesh (Barnes-Hut theta sweep against the
-direct sum), and the FP64 oracle timed on the host cores on a bounded sample
-(`cpu_baseline`).
+`value` counts the method's own work: the interactions that Alg. 2 makes for
+every particle (accepted nodes plus the points of opened leaves), taken from a
+registration with the per-particle walk, which makes exactly those
+decisions, over the same inputs and parameters. The default group walk shares
+one walk between 64 particles and evaluates more terms than that (its MAC is
+tested against the group's box); those are reported as
+`interactions_evaluated`. `roofline` is the force launch of the group walk
+against the FP32 vector peak, timed with HIP events around every launch on
+the library's stream.
+
+Printed on stdout: one JSON line. Progress goes to stderr. Every reported
+pose carries its error against the FP64 oracle, read from
+tests/golden/oracle_runs.json (written by tests/golden/make_oracle_runs.py,
+which calls only the oracle) or computed live where the oracle is fast enough.
+`cpu_baseline` times the oracle on the host cores on bounded samples.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -31,6 +40,11 @@ sys.path.insert(0, ROOT)
 FLOP_PER_INTERACTION = 20          # conventional n-body count (3 sub, 3+3 fma, rsqrt, 3 mul, 3 fma)
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (packed), FLOP/s
 PEAK_FP32_NONPACKED = 78.6e12      # 256 CU x 64 lanes x 2 flop x 2.4 GHz
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+KERNEL_NAMES = {0: "k_iteration<float, direct, FP32_KAHAN>",
+                1: "k_iteration<float, BH per-particle walk, FP32_KAHAN>",
+                64: "k_iteration_group<FP32_KAHAN, 1> (group walk, 64 particles per wave)",
+                128: "k_iteration_group<FP32_KAHAN, 2> (group walk, 128 particles per wave)"}
 
 
 def log(*a):
@@ -40,23 +54,149 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra workloads")
-    ap.add_argument("--extras", default="direct,batched,mixture,mesh",
-                    help="comma list of extra workloads to run: direct, batched, mixture, mesh")
+    ap.add_argument("--extras", default="sweep,lidar,direct,precision,batched,mixture",
+                    help="comma list of extra workloads: sweep (mesh theta 0.3/0.8 and direct), "
+                         "lidar, direct, precision, batched, mixture")
     ap.add_argument("--batch-pairs", type=int, default=256)
-    ap.add_argument("--plain-pairs", type=int, default=32,
-                    help="pairs of the batch timed with sequential plain solves")
-    ap.add_argument("--precision-study", action="store_true",
-                    help="also run the 131,072-point precision study (force errors and final pose per mode)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (a known-size kernel for HBM counters)")
     return ap.parse_args()
 
 
+# ------------------------------------------------------------------ helpers
+def phi_deg(Ra, Rb):
+    """Rotation angle of Ra^T Rb, accurate for small angles too."""
+    A = Ra.T @ Rb
+    s = 0.5 * np.linalg.norm([A[2, 1] - A[1, 2], A[0, 2] - A[2, 0], A[1, 0] - A[0, 1]])
+    c = 0.5 * (np.trace(A) - 1.0)
+    return float(np.degrees(np.arctan2(s, c)))
+
+
+def diag_of(X):
+    return float(np.linalg.norm(X.max(0) - X.min(0)))
+
+
+def golden():
+    try:
+        return json.load(open(GOLDEN))
+    except (OSError, ValueError):
+        return {}
+
+
+def vs_oracle(rec, R, t, X, at=None):
+    """Pose error against a stored FP64 oracle registration (None if absent)."""
+    if not rec:
+        return None
+    if at is not None:
+        rec = rec.get("at", {}).get(str(at))
+        if rec is None:
+            return None
+    Ro, to = np.array(rec["R"]), np.array(rec["t"])
+    return {"phi_deg": phi_deg(Ro, R), "dt_over_diag": float(np.linalg.norm(t - to) / diag_of(X))}
+
+
+def omp_threads(n):
+    """Sets the OpenMP thread count of this thread's parallel regions (the
+    oracle's loops)."""
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def all_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+class Registration:
+    """Timed registrations of one pair, the Alg. 2 interaction count of the
+    same registration, and a profiled pass with per-launch HIP events."""
+
+    def __init__(self, fga, torch, X, Y, params, dtype=None):
+        self.fga, self.torch = fga, torch
+        dtype = dtype or torch.float32
+        self.X, self.Y = X, Y
+        self.Xd = torch.as_tensor(X, dtype=dtype, device="cuda:0")
+        self.Yd = torch.as_tensor(Y, dtype=dtype, device="cuda:0")
+        self.p = params
+
+    def timed(self, steps, warmup, label=""):
+        fga, torch = self.fga, self.torch
+        for k in range(warmup):
+            fga.register(self.Xd, self.Yd, self.p)
+            log(f"  {label}warmup {k + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        evaluated = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            R, t, rep = fga.register(self.Xd, self.Yd, self.p)
+            evaluated += rep.interactions
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        self.R, self.t, self.rep = R, t, rep
+        return el, evaluated / steps
+
+    def alg2_count(self):
+        """Interactions of Alg. 2's per-particle decisions over one whole
+        registration: the per-particle walk makes exactly those decisions."""
+        p = type(self.p).from_buffer_copy(self.p)
+        p.group_width, p.tile = 1, 1
+        _, _, rep = self.fga.register(self.Xd, self.Yd, p)
+        return rep.interactions
+
+    def profile(self, iters):
+        """Per-launch HIP-event times (force launch, reduction launch) over
+        `iters` iterations after the first, and the interactions evaluated."""
+        st = self.fga.State(self.Xd, self.Yd, self.p)
+        st.step(1)
+        _, _, r0 = st.get()
+        f_ms, r_ms = st.step_profile(iters)
+        _, _, r1 = st.get()
+        st.close()
+        return f_ms / iters, r_ms / iters, (r1.interactions - r0.interactions) / iters, r1.traversal
+
+
+def roofline(kernel, alg2_per_launch, force_ms, traffic=None, evaluated=None):
+    achieved = alg2_per_launch * FLOP_PER_INTERACTION / (force_ms * 1e-3)
+    out = {"kernel": kernel, "bound": "alu", "achieved": achieved / 1e12,
+           "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+           "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED, "traffic": traffic,
+           "avg_launch_us": force_ms * 1e3, "alg2_interactions_per_launch": alg2_per_launch,
+           "flop_per_interaction": FLOP_PER_INTERACTION}
+    if evaluated is not None:
+        out["interactions_evaluated_per_launch"] = evaluated
+    return out
+
+
+def measured_traffic(name):
+    """HBM bytes per force launch from a committed FETCH_SIZE / WRITE_SIZE
+    summary, scaled by the calibration kernel; None when the kernel sources
+    have changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+    except (OSError, ValueError, KeyError):
+        return None
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
+# ----------------------------------------------------------------- headline
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -69,57 +209,28 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
-
+    torch.cuda.set_device(0)
+    gold = golden()
     if args.calibrate_copy:  # one elementwise kernel reading 256 MiB and writing 256 MiB
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    log("generating LiDAR-shaped pair (65,536 + 65,536 points)")
-    X, Y, R_gt, t_gt = synth.lidar_pair()
-    Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)
-    Yd = torch.as_tensor(Y, dtype=torch.float32, device=dev)
+
+    log("mesh pair: 1,048,576 + 1,048,576 points, Barnes-Hut theta 0.5")
+    X, Y, R_gt, t_gt = synth.mesh_pair()
     p = fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0)
-
-    for k in range(args.warmup):
-        fga.register(Xd, Yd, p)
-        log(f"warmup {k + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    inter = 0
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        R, t, rep = fga.register(Xd, Yd, p)
-        inter += rep.interactions
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    reg = Registration(fga, torch, X, Y, p)
+    elapsed, evaluated = reg.timed(args.steps, args.warmup)
     ms_step = 1e3 * elapsed / args.steps
-    value = inter / elapsed
-    log(f"timed {args.steps} registrations: {ms_step:.2f} ms/step, {value:.3e} interactions/s")
-    phi = float(np.degrees(np.arccos(np.clip(0.5 * (np.trace(R_gt.T @ R) - 1), -1, 1))))
-    diag = float(np.linalg.norm(X.max(0) - X.min(0)))
-
-    # the dominant work: one BH iteration (force launch + reduction launch),
-    # timed with events on the library's stream
-    st = fga.State(Xd, Yd, p)
-    st.step(5)
-    torch.cuda.synchronize()
-    _, _, r0 = st.get()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    n_it = args.iters
-    e0.record(stream)
-    st.step(n_it)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    _, _, r1 = st.get()
-    st.close()
-    it_ms = e0.elapsed_time(e1) / n_it
-    it_inter = (r1.interactions - r0.interactions) / n_it
-    achieved = it_inter * FLOP_PER_INTERACTION / (it_ms * 1e-3)
-    log(f"BH iteration: {it_ms * 1e3:.1f} us, {it_inter:.3e} interactions/iteration, "
-        f"{achieved / 1e12:.2f} TFLOP/s")
+    alg2 = reg.alg2 = reg.alg2_count()
+    value = alg2 * args.steps / elapsed
+    f_ms, r_ms, ev_it, trav = reg.profile(args.iters)
+    log(f"timed {args.steps} registrations: {ms_step:.2f} ms/step; Alg. 2 interactions "
+        f"{alg2:.4e} per registration -> {value:.3e}/s; force launch {f_ms * 1e3:.1f} us, "
+        f"reduction launch {r_ms * 1e3:.1f} us")
+    R, t = reg.R, reg.t
     out = {
         "metric": "force interactions/s (% FP32 VALU peak) + registrations/s, batched vs plain",
         "value": value,
@@ -133,152 +244,261 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "lidar_ring_scan_pair_65536_bh_theta0.5", "points": [len(X), len(Y)],
+        "config": {"workload": "weighted_mesh_pair_1048576_bh_theta0.5", "points": [len(X), len(Y)],
                    "theta": 0.5, "iterations": args.iters, "masses": "niv",
                    "precision": "fp32_kahan_forces_fp64_state", "parallelism": "single_gpu"},
         "registrations_per_s": args.steps / elapsed,
         "pct_fp32_vector_peak": 100.0 * value * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
-        "accuracy_vs_ground_truth": {"phi_deg": phi, "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag)},
-        "roofline": {
-            "kernel": KERNEL_NAMES.get(r1.traversal, "?") + " + k_reduce_step (one iteration: pose, forces, "
-                      "ODE, moments; then ordered moment sum and Kabsch step)",
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR,
-            "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
-            "traffic": measured_traffic(),
-            "avg_launch_us": it_ms * 1e3,
-            "launches_per_iteration": 2,
-            "interactions_per_launch": it_inter,
-            "flop_per_interaction": FLOP_PER_INTERACTION,
-        },
+        "alg2_interactions_per_registration": alg2,
+        "interactions_evaluated_per_registration": evaluated,
+        "interactions_evaluated_per_s": evaluated * args.steps / elapsed,
+        "ms_per_iteration": {"force_launch": f_ms, "reduction_launch": r_ms},
+        "error_vs_oracle": vs_oracle(gold.get("mesh_1048576_bh0.5"), R, t, X),
+        "oracle_alg2_interactions_per_registration": (gold.get("mesh_1048576_bh0.5") or {}).get("interactions"),
+        "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, R),
+                                     "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag_of(X))},
+        "roofline": roofline(KERNEL_NAMES.get(trav, "?") + " force launch", alg2 / args.iters, f_ms,
+                             measured_traffic("bh_group_iteration_mesh1048576_traffic.json"), ev_it),
     }
 
     extras = set() if args.no_extras else set(args.extras.split(","))
+    ctx = dict(fga=fga, torch=torch, synth=synth, gold=gold, args=args)
+    if "sweep" in extras:
+        out["mesh_theta_sweep"] = bench_sweep(reg, **ctx)
+    if "lidar" in extras:
+        out["lidar"] = bench_lidar(**ctx)
     if "direct" in extras:
-        out["direct"] = bench_direct(fga, torch, synth, dev, stream)
+        out["direct"] = bench_direct(**ctx)
+    if "precision" in extras:
+        out["precision_study"] = precision_study(**ctx)
     if "batched" in extras:
-        out["batched"] = bench_batched(fga, torch, synth, dev, args)
+        out["batched"] = bench_batched(**ctx)
     if "mixture" in extras:
-        out["mixture_fp64_direct"] = bench_mixture(fga, torch, synth, dev)
-    if "mesh" in extras:
-        out["mesh"] = bench_mesh(fga, torch, synth, dev, stream)
-    if args.precision_study:
-        out["precision_study"] = precision_study(fga, torch, synth, dev)
+        out["mixture_fp64_direct"] = bench_mixture(**ctx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(X, Y)
+        out["cpu_baseline"] = cpu_baseline(X, Y, extras, out, **ctx)
     print(json.dumps(out), flush=True)
 
 
-KERNEL_NAMES = {0: "k_iteration<float, direct, FP32_KAHAN>",
-                1: "k_iteration<float, BH per-particle walk, FP32_KAHAN>",
-                64: "k_iteration_group<FP32_KAHAN, 1> (group walk, 64 particles per wave)",
-                128: "k_iteration_group<FP32_KAHAN, 2> (group walk, 128 particles per wave)"}
+# ------------------------------------------------------------------- extras
+def bench_sweep(reg, fga, torch, synth, gold, args):
+    """The same mesh pair at theta 0.3 and 0.8 (whole registrations, poses
+    against the oracle's) and with the direct sum (one iteration); forces of
+    every variant on 4,096 sampled template points against the FP64 oracle's
+    direct sum (uniform masses, the mesh's own coordinates)."""
+    import oracle
+    oracle.build(force=False)
+    X, Y = reg.X, reg.Y
+    res = {}
+    idx = np.random.default_rng(2).choice(len(Y), 4096, replace=False)
+    X64 = np.ascontiguousarray(X, dtype=np.float32).astype(np.float64)
+    Ys64 = np.ascontiguousarray(Y[idx], dtype=np.float32).astype(np.float64)
+    mX = np.full(len(X), 1.0 / len(X))
+    omp_threads(all_threads())
+    t0 = time.perf_counter()
+    Fo = oracle.direct_forces(Ys64, X64, mX)
+    res["oracle_direct_sample_s"] = time.perf_counter() - t0
+    no = np.linalg.norm(Fo, axis=1)
+    Ys = torch.as_tensor(Ys64, dtype=torch.float32, device="cuda:0")
+    mXd = torch.full((len(X),), 1.0 / len(X), dtype=torch.float32, device="cuda:0")
+
+    def ferr(theta, **kw):
+        F, _ = fga.forces(Ys, reg.Xd, mXd, None, theta, fga.default_params(**kw))
+        e = np.linalg.norm(F.cpu().numpy().astype(np.float64) - Fo, axis=1) / no
+        return {"median": float(np.median(e)), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
+
+    # direct sum: one registration iteration, timed with events
+    st = fga.State(reg.Xd, reg.Yd, fga.default_params(theta=0.0, tol=0.0))
+    st.step(1)
+    f_ms, r_ms = st.step_profile(2)
+    st.close()
+    f_ms /= 2
+    ips = len(X) * len(Y) / (f_ms * 1e-3)
+    res["direct"] = {"ms_per_iteration": f_ms + r_ms / 2, "force_launch_ms": f_ms, "interactions_per_s": ips,
+                     "frac_fp32_vector_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
+                     "force_rel_err_vs_oracle": ferr(0.0)}
+    log(f"  direct: {f_ms:.1f} ms per force launch, {ips:.3e} interactions/s")
+    for th in (0.3, 0.5, 0.8):
+        if th == 0.5:  # the headline's registrations
+            sub, r, a2 = reg, {}, reg.alg2
+        else:
+            sub = Registration(fga, torch, X, Y, fga.default_params(theta=th, max_iter=args.iters, tol=0.0))
+            el, _ = sub.timed(3, 1, f"theta {th} ")
+            r, a2 = {"ms_per_registration": el / 3 * 1e3}, sub.alg2_count()
+        f_ms, r_ms, ev, _ = sub.profile(args.iters)
+        r.update({"force_launch_us": f_ms * 1e3, "reduction_launch_us": r_ms * 1e3,
+                  "interactions_evaluated_per_particle": ev / len(Y),
+                  "force_rel_err_vs_oracle_direct": {"group_walk": ferr(th, group_width=64),
+                                                     "per_particle_walk": ferr(th, group_width=1)},
+                  "speedup_vs_direct": res["direct"]["force_launch_ms"] / f_ms})
+        r["alg2_interactions_per_particle"] = a2 / args.iters / len(Y)
+        r["alg2_interactions_per_s_force_launch"] = a2 / args.iters / (f_ms * 1e-3)
+        r["error_vs_oracle"] = vs_oracle(gold.get(f"mesh_1048576_bh{th}"), sub.R, sub.t, X)
+        res[f"theta_{th}"] = r
+        log(f"  theta {th}: force launch {f_ms * 1e3:.0f} us, error vs oracle direct median "
+            f"{r['force_rel_err_vs_oracle_direct']['group_walk']['median']:.1e}")
+    return res
 
 
-def measured_traffic():
-    """HBM bytes per launch of the iteration kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, scaled by the calibration kernel; None
-    when the kernel sources have changed since those counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "bh_group_iteration_lidar65536_traffic.json")
-    try:
-        rec = json.load(open(path))
-        h = hashlib.sha256()
-        for src in rec["sources"]:
-            h.update(open(os.path.join(ROOT, src), "rb").read())
-    except (OSError, ValueError, KeyError):
-        return None
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+def bench_lidar(fga, torch, synth, gold, args):
+    """The 65,536-point LiDAR-shaped pair (two 64-beam ring scans), theta 0.5,
+    100 iterations per registration."""
+    log("LiDAR pair: 65,536 + 65,536 points")
+    X, Y, R_gt, t_gt = synth.lidar_pair()
+    reg = Registration(fga, torch, X, Y, fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0))
+    el, evaluated = reg.timed(10, 2)
+    alg2 = reg.alg2_count()
+    f_ms, r_ms, ev_it, trav = reg.profile(args.iters)
+    log(f"  {el / 10 * 1e3:.2f} ms per registration; force launch {f_ms * 1e3:.1f} us")
+    return {"ms_per_registration": el / 10 * 1e3, "registrations_per_s": 10 / el,
+            "alg2_interactions_per_s": alg2 * 10 / el, "alg2_interactions_per_registration": alg2,
+            "interactions_evaluated_per_registration": evaluated,
+            "oracle_alg2_interactions_per_registration": (gold.get("lidar_65536_bh0.5") or {}).get("interactions"),
+            "error_vs_oracle": vs_oracle(gold.get("lidar_65536_bh0.5"), reg.R, reg.t, X),
+            "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, reg.R),
+                                         "dt_over_diag": float(np.linalg.norm(reg.t - t_gt) / diag_of(X))},
+            "roofline": roofline(KERNEL_NAMES.get(trav, "?") + " force launch", alg2 / args.iters, f_ms,
+                                 measured_traffic("bh_group_iteration_lidar65536_traffic.json"), ev_it),
+            "reduction_launch_us": r_ms * 1e3}
 
 
-def bench_direct(fga, torch, synth, dev, stream):
+def bench_direct(fga, torch, synth, gold, args):
     """Direct all-pairs kernel on the 131,072 x 131,072 precision-study shape,
-    as the iteration of a registration (FP32 Kahan tiles)."""
+    as the force launch of a registration iteration."""
     log("direct kernel: 131,072 x 131,072")
     X, Y, _, _ = synth.precision_pair()
-    Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)
-    Yd = torch.as_tensor(Y, dtype=torch.float32, device=dev)
+    Xd = torch.as_tensor(X, dtype=torch.float32, device="cuda:0")
+    Yd = torch.as_tensor(Y, dtype=torch.float32, device="cuda:0")
     res = {}
     for name, prec in (("fp32_kahan", fga.PREC_FP32_KAHAN), ("fp32", fga.PREC_FP32)):
         st = fga.State(Xd, Yd, fga.default_params(theta=0.0, tol=0.0, precision=prec))
         st.step(1)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        n_it = 5
-        e0.record(stream)
-        st.step(n_it)
-        e1.record(stream)
-        torch.cuda.synchronize()
+        f_ms, r_ms = st.step_profile(5)
         st.close()
-        ms = e0.elapsed_time(e1) / n_it
-        ips = len(X) * len(Y) / (ms * 1e-3)
-        res[name] = {"ms_per_iteration": ms, "interactions_per_s": ips,
+        f_ms /= 5
+        ips = len(X) * len(Y) / (f_ms * 1e-3)
+        res[name] = {"force_launch_ms": f_ms, "reduction_launch_ms": r_ms / 5, "interactions_per_s": ips,
                      "tflops": ips * FLOP_PER_INTERACTION / 1e12,
-                     "frac_fp32_vector_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR}
-        log(f"  {name}: {ms:.2f} ms/iteration, {ips:.3e} interactions/s")
+                     "frac_fp32_vector_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
+                     "frac_of_nonpacked_peak": ips * FLOP_PER_INTERACTION / PEAK_FP32_NONPACKED}
+        log(f"  {name}: {f_ms:.2f} ms per force launch, {ips:.3e} interactions/s")
     return res
 
 
-def bench_mesh(fga, torch, synth, dev, stream):
-    """1,048,576 + 1,048,576 points on a weighted triangle mesh: one
-    iteration of the registration with Barnes-Hut at theta 0.3, 0.5, 0.8
-    (group walk, autotuned) and with the direct sum, and the Barnes-Hut force
-    error against the direct sum on 4,096 template points (uniform masses,
-    the mesh's own coordinates)."""
-    log("mesh workload: 1,048,576 + 1,048,576 points")
-    X, Y, _, _ = synth.mesh_pair()
-    Xd = torch.as_tensor(X, dtype=torch.float32, device=dev)
-    Yd = torch.as_tensor(Y, dtype=torch.float32, device=dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+def precision_study(fga, torch, synth, gold, args):
+    """131,072 x 131,072 direct sums in the three precision modes: relative
+    force error on 512 sampled template points against the FP64 oracle (max,
+    median), and the pose after 10 and 100 registration iterations against the
+    oracle's registration of the same FP32-rounded pair."""
+    import oracle
+    oracle.build(force=False)
+    log("precision study: 131,072 x 131,072")
+    X, Y, _, _ = synth.precision_pair()
+    X32 = np.ascontiguousarray(X, dtype=np.float32).astype(np.float64)
+    Y32 = np.ascontiguousarray(Y, dtype=np.float32).astype(np.float64)
+    n = len(X32)
+    mX = np.full(n, 1.0 / n)
+    idx = np.random.default_rng(1).choice(len(Y32), 512, replace=False)
+    omp_threads(all_threads())
+    ref = oracle.direct_forces(Y32[idx], X32, mX)
+    rec = gold.get("precision_131072_direct")
+    modes = (("pure_fp32", fga.PREC_FP32_ALL), ("fp32_tiles_fp64_reductions", fga.PREC_FP32),
+             ("fp32_kahan_tiles_fp64_reductions", fga.PREC_FP32_KAHAN))
+    Xd = torch.as_tensor(X32, dtype=torch.float32, device="cuda:0")
+    Yd = torch.as_tensor(Y32, dtype=torch.float32, device="cuda:0")
+    mXd = torch.as_tensor(mX, dtype=torch.float32, device="cuda:0")
     res = {}
-
-    def timed(theta, warm, n_it):
-        st = fga.State(Xd, Yd, fga.default_params(theta=theta, tol=0.0))
-        st.step(warm)
-        torch.cuda.synchronize()
-        _, _, r0 = st.get()
-        e0.record(stream)
-        st.step(n_it)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        _, _, r1 = st.get()
+    for name, prec in modes:
+        F, _ = fga.forces(Yd, Xd, mXd, None, 0.0, fga.default_params(precision=prec))
+        Fs = F.cpu().numpy().astype(np.float64)[idx]
+        e = np.linalg.norm(Fs - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        st = fga.State(Xd, Yd, fga.default_params(theta=0.0, tol=0.0, precision=prec))
+        st.step(10)
+        R10, t10, _ = st.get()
+        st.step(90)
+        R, t, _ = st.get()
         st.close()
-        ms = e0.elapsed_time(e1) / n_it
-        inter = (r1.interactions - r0.interactions) / n_it
-        return {"ms_per_iteration": ms, "interactions_per_particle": inter / len(Y),
-                "interactions_per_s": inter / (ms * 1e-3)}
-
-    res["direct"] = timed(0.0, 1, 2)
-    log(f"  direct: {res['direct']['ms_per_iteration']:.1f} ms/iteration")
-    idx = np.random.default_rng(2).choice(len(Y), 4096, replace=False)
-    Ys = Yd[torch.as_tensor(idx, device=dev)].contiguous()
-    mX = torch.full((len(X),), 1.0 / len(X), dtype=torch.float32, device=dev)
-    Fd, _ = fga.forces(Ys, Xd, mX, None, 0.0)
-    Fd = Fd.cpu().numpy().astype(np.float64)
-    nd = np.linalg.norm(Fd, axis=1)
-    for th in (0.3, 0.5, 0.8):
-        r = timed(th, 2, 10)
-        Fb, _ = fga.forces(Ys, Xd, mX, None, th, fga.default_params(group_width=64))
-        e = np.linalg.norm(Fb.cpu().numpy().astype(np.float64) - Fd, axis=1) / nd
-        r["force_rel_err_vs_direct_median"] = float(np.median(e))
-        r["force_rel_err_vs_direct_p99"] = float(np.percentile(e, 99))
-        r["speedup_vs_direct"] = res["direct"]["ms_per_iteration"] / r["ms_per_iteration"]
-        res[f"theta_{th}"] = r
-        log(f"  theta {th}: {r['ms_per_iteration'] * 1e3:.0f} us/iteration, "
-            f"{r['interactions_per_particle']:.0f} interactions/particle, "
-            f"error vs direct median {r['force_rel_err_vs_direct_median']:.1e}")
+        res[name] = {"force_rel_err_max": float(e.max()), "force_rel_err_median": float(np.median(e)),
+                     "pose_vs_oracle_10_iterations": vs_oracle(rec, R10, t10, X32, at=10),
+                     "pose_vs_oracle_100_iterations": vs_oracle(rec, R, t, X32)}
+        log(f"  {name}: force err max {e.max():.2e} median {np.median(e):.2e}")
     return res
 
 
-def bench_mixture(fga, torch, synth, dev):
+def bench_batched(fga, torch, synth, gold, args):
+    """256 mixture pairs with log-uniform sizes: one batched registration
+    (persistent work-queue launches replayed from a HIP graph, FP32 forces)
+    against sequential plain registrations of every pair (FP64 forces and
+    reductions), both with the per-pair Alg. 2 stop rule (at most 200
+    iterations), at tol 1e-8 (the default) and 1e-4 on the squared step.
+    Pose errors of both against the oracle's registrations of every pair."""
+    k = args.batch_pairs
+    log(f"batched workload: {k} pairs")
+    pairs = synth.batch_pairs(k)
+    Xs = [torch.as_tensor(pp[0], dtype=torch.float32, device="cuda:0") for pp in pairs]
+    Ys = [torch.as_tensor(pp[1], dtype=torch.float32, device="cuda:0") for pp in pairs]
+    X64 = [torch.as_tensor(np.ascontiguousarray(pp[0], dtype=np.float32), dtype=torch.float64,
+                           device="cuda:0") for pp in pairs]
+    Y64 = [torch.as_tensor(np.ascontiguousarray(pp[1], dtype=np.float32), dtype=torch.float64,
+                           device="cuda:0") for pp in pairs]
+    res = {"pairs": k}
+    for tol in (1e-8, 1e-4):
+        pb = fga.default_params(theta=0.5, max_iter=200, tol=tol)
+        fga.register_batch(Xs[:4], Ys[:4], pb)  # warm the code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Rb, tb, reps = fga.register_batch(Xs, Ys, pb)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        pp64 = fga.default_params(theta=0.5, max_iter=200, tol=tol, precision=fga.PREC_FP64)
+        fga.register(X64[0], Y64[0], pp64)
+        torch.cuda.synchronize()
+        plain = []
+        t0 = time.perf_counter()
+        for j in range(k):
+            plain.append(fga.register(X64[j], Y64[j], pp64))
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        recs = gold.get(f"batch_256_bh0.5_tol{tol:g}") or []
+        eb, ep, ebp = [], [], []
+        for j in range(k):
+            diag = diag_of(pairs[j][0])
+            Rp, tp, _ = plain[j]
+            ebp.append((phi_deg(Rp, Rb[j]), float(np.linalg.norm(tp - tb[j]) / diag)))
+            if j < len(recs):
+                e1 = vs_oracle(recs[j], Rb[j], tb[j], pairs[j][0])
+                e2 = vs_oracle(recs[j], Rp, tp, pairs[j][0])
+                eb.append((e1["phi_deg"], e1["dt_over_diag"]))
+                ep.append((e2["phi_deg"], e2["dt_over_diag"]))
+        gt = [phi_deg(pairs[j][2], Rb[j]) for j in range(k)]
+
+        def summ(a):
+            if not a:
+                return None
+            a = np.array(a)
+            return {"phi_deg_max": float(a[:, 0].max()), "phi_deg_median": float(np.median(a[:, 0])),
+                    "dt_over_diag_max": float(a[:, 1].max()), "dt_over_diag_median": float(np.median(a[:, 1])),
+                    "pairs": len(a)}
+        res[f"tol_{tol:g}"] = {
+            "batched_registrations_per_s": k / t_batch, "plain_registrations_per_s": k / t_plain,
+            "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
+            "median_iters_batched": float(np.median([r.iters for r in reps])),
+            "median_iters_plain": float(np.median([pl[2].iters for pl in plain])),
+            "batched_vs_oracle": summ(eb), "plain_vs_oracle": summ(ep), "batched_vs_plain": summ(ebp),
+            "median_phi_vs_ground_truth_deg": float(np.median(gt))}
+        log(f"  tol {tol:g}: batched {t_batch * 1e3:.1f} ms, plain FP64 {t_plain * 1e3:.1f} ms for {k} pairs")
+    return res
+
+
+def bench_mixture(fga, torch, synth, gold, args):
     """The 1,024 / 900-point Gaussian-mixture registration: direct sum in
-    FP64, 200 fixed iterations (launch-bound at this size)."""
+    FP64, 200 fixed iterations (launch-bound at this size); pose against the
+    oracle's registration (run live: it takes well under a second)."""
+    import oracle
+    oracle.build(force=False)
     X, Y, Rg, tg = synth.mixture_pair()
-    Xd = torch.as_tensor(X, dtype=torch.float64, device=dev)
-    Yd = torch.as_tensor(Y, dtype=torch.float64, device=dev)
+    Xd = torch.as_tensor(X, dtype=torch.float64, device="cuda:0")
+    Yd = torch.as_tensor(Y, dtype=torch.float64, device="cuda:0")
     p = fga.default_params(theta=0.0, tol=0.0, max_iter=200, precision=fga.PREC_FP64)
     fga.register(Xd, Yd, p)
     torch.cuda.synchronize()
@@ -288,134 +508,123 @@ def bench_mixture(fga, torch, synth, dev):
         R, t, rep = fga.register(Xd, Yd, p)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / n * 1e3
-    phi = float(np.degrees(np.arccos(np.clip(0.5 * (np.trace(Rg.T @ R) - 1), -1, 1))))
+    omp_threads(all_threads())
+    o = oracle.register(X, Y, oracle.Params(max_iter=200))
     log(f"mixture FP64 direct: {ms:.2f} ms per 200-iteration registration")
-    return {"ms_per_registration": ms, "iterations": rep.iters, "interactions_per_s": rep.interactions / (ms * 1e-3),
-            "phi_deg_vs_ground_truth": phi}
+    return {"ms_per_registration": ms, "iterations": rep.iters,
+            "interactions_per_s": rep.interactions / (ms * 1e-3),
+            "error_vs_oracle": vs_oracle(o, R, t, X), "phi_deg_vs_ground_truth": phi_deg(Rg, R)}
 
 
-def precision_study(fga, torch, synth, dev):
-    """131,072 x 131,072 direct sums: per precision mode, the relative force
-    error on 512 sampled template points against the FP64 oracle (max and
-    median), and the final pose after 100 iterations against the FP64 device
-    path on the same FP32-rounded coordinates (whose agreement with the
-    oracle's Alg. 2 is pinned on the 1,024-point mixture to 1e-11), as rotation
-    angle and translation / diagonal."""
+# ------------------------------------------------------------- CPU baseline
+def cpu_baseline(X, Y, extras, out, fga, torch, synth, gold, args):
+    """The FP64 oracle (plain C loops, OpenMP over template particles) on the
+    host cores, on bounded samples of each workload. The headline figure is
+    one Alg. 2 iteration of the mesh pair with the literal tree at theta 0.5
+    (tree build timed apart) on all threads."""
     import oracle
     oracle.build(force=False)
-    X, Y, _, _ = synth.precision_pair()
-    X32 = np.ascontiguousarray(X, dtype=np.float32).astype(np.float64)
-    Y32 = np.ascontiguousarray(Y, dtype=np.float32).astype(np.float64)
-    n = len(X32)
-    mX = np.full(n, 1.0 / n)
-    idx = np.random.default_rng(1).choice(len(Y32), 512, replace=False)
-    ref = oracle.direct_forces(Y32[idx], X32, mX)
-    diag = float(np.linalg.norm(X.max(0) - X.min(0)))
-    log("precision study: FP64 reference registration")
-    p64 = fga.default_params(theta=0.0, tol=0.0, max_iter=100, precision=fga.PREC_FP64)
-    R64, t64, _ = fga.register(torch.as_tensor(X32, dtype=torch.float64, device=dev),
-                               torch.as_tensor(Y32, dtype=torch.float64, device=dev), p64)
-    res = {}
-    # pure FP32 (force tiles and moment sums); FP32 tiles with FP64 moment
-    # and state reductions; the same with Kahan-compensated tiles
-    modes = (("pure_fp32", fga.PREC_FP32_ALL), ("fp32_tiles_fp64_reductions", fga.PREC_FP32),
-             ("fp32_kahan_tiles_fp64_reductions", fga.PREC_FP32_KAHAN))
-    Xd = torch.as_tensor(X32, dtype=torch.float32, device=dev)
-    Yd = torch.as_tensor(Y32, dtype=torch.float32, device=dev)
-    for name, prec in modes:
-        prm = fga.default_params(precision=prec)
-        F, _ = fga.forces(Yd, Xd, torch.as_tensor(mX, dtype=torch.float32, device=dev), None, 0.0, prm)
-        Fs = F.cpu().numpy().astype(np.float64)[idx]
-        e = np.linalg.norm(Fs - ref, axis=1) / np.linalg.norm(ref, axis=1)
-        R, t, _ = fga.register(Xd, Yd,
-                               fga.default_params(theta=0.0, tol=0.0, max_iter=100, precision=prec))
-        A = R64.T @ R  # small-angle form: arccos of the trace saturates below ~1e-6 deg
-        phi = float(np.degrees(np.arcsin(min(1.0, 0.5 * np.linalg.norm(
-            [A[2, 1] - A[1, 2], A[0, 2] - A[2, 0], A[1, 0] - A[0, 1]])))))
-        res[name] = {"force_rel_err_max": float(e.max()), "force_rel_err_median": float(np.median(e)),
-                     "rotation_deg_vs_fp64": phi, "translation_vs_fp64_over_diag": float(np.linalg.norm(t - t64) / diag)}
-        log(f"  {name}: force err max {e.max():.2e} median {np.median(e):.2e}; pose {phi:.2e} deg")
-    return res
+    nth = all_threads()
+    log(f"cpu baseline: FP64 oracle, {nth} threads ({cpu_model()})")
 
+    def f64(a):
+        return np.ascontiguousarray(a, dtype=np.float32).astype(np.float64)
 
-def bench_batched(fga, torch, synth, dev, args):
-    """256 mixture pairs with log-uniform sizes: one batched registration
-    (persistent work-queue launches replayed from a HIP graph, FP32 forces)
-    against sequential plain registrations (FP64 forces and reductions) of a
-    subset, both with per-pair convergence (Alg. 2 stop rule, tol 1e-8 on the
-    squared step, at most 200 iterations)."""
-    k = args.batch_pairs
-    log(f"batched workload: {k} pairs")
-    pairs = synth.batch_pairs(k)
-    Xs = [torch.as_tensor(pp[0], dtype=torch.float32, device=dev) for pp in pairs]
-    Ys = [torch.as_tensor(pp[1], dtype=torch.float32, device=dev) for pp in pairs]
-    pb = fga.default_params(theta=0.5, max_iter=200)
-    fga.register_batch(Xs[:4], Ys[:4], pb)  # warm the code paths
-    torch.cuda.synchronize()
+    Xn, Yn, _ = oracle.normalise(f64(X), f64(Y))
+    prm = oracle.Params(theta=0.5)
+    mX, mY = oracle.masses(Xn, Yn, prm)
+    omp_threads(nth)
     t0 = time.perf_counter()
-    R, t, reps = fga.register_batch(Xs, Ys, pb)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    log(f"  batched: {tb * 1e3:.1f} ms for {k} pairs")
-    nplain = min(args.plain_pairs, k)
-    Xs64 = [torch.as_tensor(pp[0], dtype=torch.float64, device=dev) for pp in pairs[:nplain]]
-    Ys64 = [torch.as_tensor(pp[1], dtype=torch.float64, device=dev) for pp in pairs[:nplain]]
-    pp64 = fga.default_params(theta=0.5, max_iter=200, precision=fga.PREC_FP64)
-    fga.register(Xs64[0], Ys64[0], pp64)
-    torch.cuda.synchronize()
+    tree = oracle.BHTree(Xn, mX)
+    t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
-    errs = []
-    for j in range(nplain):
-        Rp, tp, rp = fga.register(Xs64[j], Ys64[j], pp64)
-        diag = np.linalg.norm(pairs[j][0].max(0) - pairs[j][0].min(0))
-        c = np.clip(0.5 * (np.trace(Rp.T @ R[j]) - 1), -1, 1)
-        errs.append((float(np.degrees(np.arccos(c))), float(np.linalg.norm(tp - t[j]) / diag)))
-    torch.cuda.synchronize()
-    tp_total = time.perf_counter() - t0
-    log(f"  plain FP64: {tp_total * 1e3:.1f} ms for {nplain} pairs")
-    errs = np.array(errs)
-    gt = []
-    for j in range(k):
-        Rg, tg = pairs[j][2], pairs[j][3]
-        c = np.clip(0.5 * (np.trace(Rg.T @ R[j]) - 1), -1, 1)
-        gt.append(float(np.degrees(np.arccos(c))))
-    return {
-        "pairs": k,
-        "batched_registrations_per_s": k / tb,
-        "plain_registrations_per_s": nplain / tp_total,
-        "plain_pairs_timed": nplain,
-        "speedup": (k / tb) / (nplain / tp_total),
-        "batched_vs_plain_max_phi_deg": float(errs[:, 0].max()),
-        "batched_vs_plain_max_dt_over_diag": float(errs[:, 1].max()),
-        "median_iters": float(np.median([r.iters for r in reps])),
-        "median_phi_vs_ground_truth_deg": float(np.median(gt)),
-    }
-
-
-def cpu_baseline(X, Y):
-    """The FP64 oracle (plain C, OpenMP over template particles) on the host
-    cores: Alg. 2 with the literal BH tree on the same LiDAR pair, timed over
-    a bounded number of iterations after its one-off setup."""
-    import oracle
-    oracle.build(force=False)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"cpu baseline: FP64 oracle, {threads} threads")
-    Xn, Yn, _ = oracle.normalise(X, Y)
-    p = oracle.Params(theta=0.5)
-    mX, mY = oracle.masses(Xn, Yn, p)
-    st = oracle.Stepper(Xn, Yn, mX, mY, p)
-    t0 = time.perf_counter()
-    iters = 0
-    while iters < 100 and (iters < 2 or time.perf_counter() - t0 < 15.0):
-        st.step()
-        iters += 1
+    _, cnt = tree.forces(Yn, None, prm.G, prm.eps, prm.theta, count=True)
     el = time.perf_counter() - t0
-    log(f"  oracle: {iters} iterations in {el:.1f} s")
-    return {"value": st.interactions / el, "unit": "interactions/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{iters} Alg. 2 iterations (literal BH tree, theta 0.5, FP64) of the "
-                      f"65,536-point LiDAR pair; tree build excluded",
-            "ms_per_iteration": 1e3 * el / iters}
+    sub = np.random.default_rng(3).choice(len(Yn), 16384, replace=False)
+    omp_threads(1)
+    t0 = time.perf_counter()
+    _, cnt1 = tree.forces(Yn[sub], None, prm.G, prm.eps, prm.theta, count=True)
+    el1 = time.perf_counter() - t0
+    del tree
+    res = {"value": cnt / el, "unit": "interactions/s", "cores": nth, "kind": "oracle",
+           "sample": "one Alg. 2 force evaluation (literal uncompressed tree, theta 0.5, FP64) of the "
+                     "1,048,576-point mesh pair at its initial pose; tree build timed apart",
+           "cpu_model": cpu_model(), "tree_build_s": t_tree, "iteration_s": el,
+           "one_thread": {"interactions_per_s": cnt1 / el1,
+                          "sample": "the same evaluation for 16,384 random template points"}}
+    if out.get("ms_per_step"):
+        est = (t_tree + args.iters * el) * 1e3
+        res["registration_ms_estimate"] = est
+        res["registration_estimate_note"] = ("extrapolated: tree build + iterations x the measured iteration "
+                                             "(the pose changes little the count)")
+    per = {}
+    # C0: the whole 200-iteration FP64 direct registration, all threads and one
+    Xm, Ym, _, _ = synth.mixture_pair()
+    for th in (nth, 1):
+        omp_threads(th)
+        t0 = time.perf_counter()
+        oracle.register(Xm, Ym, oracle.Params(max_iter=200))
+        per.setdefault("mixture_1024_direct_200it", {})[f"threads_{th}_s"] = time.perf_counter() - t0
+    # C1: one BH iteration with one thread, the whole 100-iteration registration with all
+    if "lidar" in extras:
+        Xl, Yl, _, _ = synth.lidar_pair()
+        Xn, Yn, _ = oracle.normalise(f64(Xl), f64(Yl))
+        mX, mY = oracle.masses(Xn, Yn, prm)
+        omp_threads(nth)
+        stp = oracle.Stepper(Xn, Yn, mX, mY, oracle.Params(theta=0.5))
+        t0 = time.perf_counter()
+        for _ in range(args.iters):
+            stp.step()
+        t_all = time.perf_counter() - t0
+        c_all = stp.interactions
+        omp_threads(1)
+        t0 = time.perf_counter()
+        stp.step()
+        t_one = time.perf_counter() - t0
+        per["lidar_65536_bh0.5"] = {f"threads_{nth}_registration_s": t_all, "threads_1_iteration_s": t_one,
+                                    "interactions_per_s_all_threads": c_all / t_all,
+                                    "interactions_per_s_one_thread": (stp.interactions - c_all) / t_one,
+                                    "note": "tree build excluded"}
+    # C2 direct: the oracle's direct sum on 4,096 template points was timed by the sweep
+    sw = out.get("mesh_theta_sweep")
+    if sw:
+        t = sw["oracle_direct_sample_s"]
+        per["mesh_1048576_direct"] = {"threads": nth, "sample": "4,096 template points x 1,048,576 references",
+                                      "interactions_per_s": 4096 * len(X) / t,
+                                      "iteration_s_extrapolated": t * len(Y) / 4096}
+    # C3: one full FP64 direct force evaluation, all threads (the 100-iteration
+    # registration is extrapolated from it); one thread on 1,024 template points
+    if "precision" in extras:
+        Xp, Yp, _, _ = synth.precision_pair()
+        Xp, Yp = f64(Xp), f64(Yp)
+        mp_ = np.full(len(Xp), 1.0 / len(Xp))
+        omp_threads(nth)
+        t0 = time.perf_counter()
+        oracle.direct_forces(Yp, Xp, mp_)
+        t_all = time.perf_counter() - t0
+        omp_threads(1)
+        t0 = time.perf_counter()
+        oracle.direct_forces(Yp[:1024], Xp, mp_)
+        t_one = time.perf_counter() - t0
+        per["precision_131072_direct"] = {f"threads_{nth}_iteration_s": t_all,
+                                          "threads_1_interactions_per_s": 1024 * len(Xp) / t_one,
+                                          "registration_100it_s_extrapolated": 100 * t_all}
+    # C4: 8 randomly chosen pairs registered sequentially, extrapolated to 256
+    if "batched" in extras:
+        sel = np.random.default_rng(4).choice(synth.BATCH_PAIRS, 8, replace=False)
+        omp_threads(nth)
+        t0 = time.perf_counter()
+        for j in sel:
+            Xb, Yb, _, _ = synth.batch_pair(int(j))
+            oracle.register(f64(Xb), f64(Yb), oracle.Params(theta=0.5, max_iter=200, tol=1e-8))
+        t8 = time.perf_counter() - t0
+        per["batch_256_bh0.5"] = {"pairs_timed": [int(j) for j in sel], "seconds": t8,
+                                  "registrations_per_s": 8 / t8,
+                                  "batch_s_extrapolated": t8 / 8 * synth.BATCH_PAIRS}
+    omp_threads(nth)
+    res["per_workload"] = per
+    log(f"  oracle: {res['value']:.3e} interactions/s on {nth} threads")
+    return res
 
 
 if __name__ == "__main__":

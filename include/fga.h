@@ -166,6 +166,16 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
  * early only if p->tol > 0 and the tolerance is met. */
 fga_status fga_step(fga_state* st, int n_iters);
 
+/* fga_step for exactly n_iters >= 1 iterations (no early stop) with HIP events
+ * recorded on the state's stream around the two launches of every iteration:
+ * ms[0] receives the summed duration of the force launches (template pose,
+ * Eq. GAForce forces, the damped ODE step and the per-block displacement
+ * moments), ms[1] that of the reduction launches (moment sum and the Kabsch
+ * step of Eqs. R_Kabsch and transEst). A registration's first iteration that
+ * measures the group walk's costs, if still pending, runs first, untimed.
+ * ms is host memory. Synchronises the stream. */
+fga_status fga_step_profile(fga_state* st, int n_iters, double ms[2]);
+
 /* Current transform in the caller's coordinates (de-normalised as in
  * Appendix A) and an optional report. R, t, rep are host memory; rep may be NULL. */
 fga_status fga_state_get(const fga_state* st, double R[9], double t[3], fga_report* rep);

@@ -114,6 +114,7 @@ def lib():
                                 ctypes.POINTER(ctypes.c_longlong), vp]),
             "fga_state_create": (st, [vp, i64, vp, i64, dt, P, vp, ctypes.POINTER(vp)]),
             "fga_step": (st, [vp, ctypes.c_int]),
+            "fga_step_profile": (st, [vp, ctypes.c_int, dp]),
             "fga_state_get": (st, [vp, dp, dp, ctypes.POINTER(_CReport)]),
             "fga_state_get_normalised": (st, [vp, dp, dp]),
             "fga_state_save": (st, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -280,6 +281,13 @@ class State:
 
     def step(self, n_iters: int = 1):
         _check(lib().fga_step(self._h, int(n_iters)))
+
+    def step_profile(self, n_iters: int):
+        """Runs n_iters iterations; returns the summed milliseconds of the
+        force launches and of the reduction launches (HIP events)."""
+        ms = (ctypes.c_double * 2)()
+        _check(lib().fga_step_profile(self._h, int(n_iters), ms))
+        return ms[0], ms[1]
 
     def get(self):
         import numpy as np

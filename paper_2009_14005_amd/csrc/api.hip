@@ -1091,6 +1091,48 @@ fga_status fga_step(fga_state* S, int n_iters) {
   return FGA_OK;
 }
 
+fga_status fga_step_profile(fga_state* S, int n_iters, double ms[2]) {
+  FGA_TRY(check_ptr(S, "state"));
+  FGA_TRY(check_ptr(ms, "ms"));
+  if (n_iters < 1) {
+    set_error("n_iters must be >= 1");
+    return FGA_E_INVALID_ARG;
+  }
+  if (S->pend_K) FGA_TRY(first_step_measured(S));  // the measuring launch is not timed
+  // three events per iteration: before the force launch, between the two
+  // launches, after the reduction launch; all queued before one wait, so the
+  // host never idles the stream between iterations
+  std::vector<hipEvent_t> ev((size_t)3 * n_iters, nullptr);
+  fga_status st = FGA_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      st = FGA_E_DEVICE;
+      break;
+    }
+  for (int k = 0; k < n_iters && st == FGA_OK; ++k) {
+    if (hipEventRecord(ev[3 * k], S->s) != hipSuccess) st = FGA_E_DEVICE;
+    if (st == FGA_OK)
+      st = S->f64 ? launch_iteration<double>(S->pd, S->c, S->s, ev[3 * k + 1])
+                  : launch_iteration<float>(S->pd, S->c, S->s, ev[3 * k + 1]);
+    if (st == FGA_OK && hipEventRecord(ev[3 * k + 2], S->s) != hipSuccess) st = FGA_E_DEVICE;
+  }
+  if (st == FGA_OK && hipStreamSynchronize(S->s) != hipSuccess) st = FGA_E_DEVICE;
+  ms[0] = ms[1] = 0.0;
+  for (int k = 0; k < n_iters && st == FGA_OK; ++k) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]) != hipSuccess)
+      st = FGA_E_DEVICE;
+    ms[0] += a;
+    ms[1] += b;
+  }
+  for (auto e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st == FGA_E_DEVICE) set_error("profiled iterations failed");
+  return st;
+}
+
 fga_status fga_state_get_normalised(const fga_state* S, double R[9], double t[3]) {
   FGA_TRY(check_ptr(S, "state"));
   FGA_TRY(check_ptr(R, "R"));

@@ -217,6 +217,14 @@ int direct_ranges(int64_t m, int64_t n);
 template <typename T>
 fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
                          const void* mY, const fga_params& p, void* F, hipStream_t s);
+// Bytes of device scratch the direct sum needs (packed reference, then the
+// per-range partial forces), and its launches into caller-provided scratch
+// (aligned to 256 bytes); queues the work without waiting for it.
+size_t forces_direct_scratch(int64_t m, int64_t n, bool f64);
+template <typename T>
+fga_status forces_direct_into(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                              const void* mY, const fga_params& p, void* F, void* scratch,
+                              hipStream_t s);
 template <typename T>
 fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
                           int n_nodes, const void* Xs, int64_t n, double theta,
@@ -228,7 +236,8 @@ fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipS
 // iter.hip: one iteration as two launches (pose, forces, ODE and per-block
 // moments; then the ordered moment sum and the Kabsch step)
 template <typename T>
-fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s);
+fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s,
+                            hipEvent_t between = nullptr);
 template <typename T>
 fga_status launch_batch_iteration(const PairDev* pairs_dev, int npairs, int reduce_blocks,
                                   const int2* items, int n_items, unsigned* queue, int n_blocks,

@@ -387,7 +387,7 @@ inline void reduce_launch(const PairDev& pd, const IterConsts& c, hipStream_t s)
 }  // namespace
 
 template <typename T>
-fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s) {
+fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s, hipEvent_t between) {
   const bool bh = pd.nodes != nullptr;
   const dim3 grid((unsigned)pd.n_items);
   if (sizeof(T) == 4 && bh && pd.group > 0) {  // group traversal, K particles per lane
@@ -425,6 +425,7 @@ fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t 
         }
     }
   }
+  if (between) FGA_HIP(hipEventRecord(between, s));  // splits the force and reduction launches
   if (sizeof(T) == 8) reduce_launch<FGA_PREC_FP64>(pd, c, s);
   else if (c.prec == FGA_PREC_FP32_ALL) reduce_launch<FGA_PREC_FP32_ALL>(pd, c, s);
   else reduce_launch<FGA_PREC_FP32_KAHAN>(pd, c, s);
@@ -463,8 +464,8 @@ fga_status launch_batch_iteration(const PairDev* pairs_dev, int npairs, int redu
   return FGA_OK;
 }
 
-template fga_status launch_iteration<float>(const PairDev&, const IterConsts&, hipStream_t);
-template fga_status launch_iteration<double>(const PairDev&, const IterConsts&, hipStream_t);
+template fga_status launch_iteration<float>(const PairDev&, const IterConsts&, hipStream_t, hipEvent_t);
+template fga_status launch_iteration<double>(const PairDev&, const IterConsts&, hipStream_t, hipEvent_t);
 template fga_status launch_batch_iteration<float>(const PairDev*, int, int, const int2*, int,
                                                   unsigned*, int, const IterConsts&, hipStream_t,
                                                   bool, bool);
@@ -605,33 +606,54 @@ int direct_ranges(int64_t m, int64_t n) {
   return (int)jr;
 }
 
+// Scratch of the direct sum: the packed reference (n vec4) at offset 0, the
+// partial forces of the jrn reference ranges (jrn x m x 3) after it, each part
+// starting on a 256-byte boundary.
+static size_t direct_part_offset(int64_t n, bool f64) {
+  const size_t x4 = (f64 ? sizeof(double4) : sizeof(float4)) * (size_t)n;
+  return (x4 + 255) / 256 * 256;
+}
+
+size_t forces_direct_scratch(int64_t m, int64_t n, bool f64) {
+  return direct_part_offset(n, f64) + (f64 ? 8 : 4) * 3 * (size_t)m * direct_ranges(m, n);
+}
+
 template <typename T>
-fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
-                         const void* mY, const fga_params& p, void* F, hipStream_t s) {
+fga_status forces_direct_into(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                              const void* mY, const fga_params& p, void* F, void* scratch,
+                              hipStream_t s) {
   const int jrn = direct_ranges(m, n);
-  void *X4 = nullptr, *part = nullptr;
-  FGA_TRY(pool_get(&X4, sizeof(vec4_t<T>) * n, s));
-  if (pool_get(&part, sizeof(T) * 3 * (size_t)m * jrn, s) != FGA_OK) {
-    pool_free(X4, s);
-    return FGA_E_NOMEM;
-  }
-  k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, (vec4_t<T>*)X4);
+  vec4_t<T>* X4 = (vec4_t<T>*)scratch;
+  T* part = (T*)((char*)scratch + direct_part_offset(n, sizeof(T) == 8));
+  k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, X4);
   const dim3 grid((unsigned)((m + kBlock - 1) / kBlock), (unsigned)jrn);
   const T eps2 = (T)(p.eps * p.eps);
   if (sizeof(T) == 8 || p.precision == FGA_PREC_FP32_KAHAN)
-    k_forces_direct<T, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
+    k_forces_direct<T, FGA_PREC_FP32_KAHAN><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, X4, (int)n, jrn, eps2, part);
   else
-    k_forces_direct<T, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, (const vec4_t<T>*)X4, (int)n, jrn, eps2, (T*)part);
-  k_forces_combine<T><<<(int)((m + 255) / 256), 256, 0, s>>>((const T*)part, (int)m, jrn, (const T*)mY, p.G, (T*)F);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  pool_free(X4, s);
-  pool_free(part, s);
+    k_forces_direct<T, FGA_PREC_FP32><<<grid, kBlock, 0, s>>>((const T*)Y, (int)m, X4, (int)n, jrn, eps2, part);
+  k_forces_combine<T><<<(int)((m + 255) / 256), 256, 0, s>>>(part, (int)m, jrn, (const T*)mY, p.G, (T*)F);
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
-    set_error("direct force kernels failed: %s", hipGetErrorString(e));
+    set_error("direct force kernels failed to launch: %s", hipGetErrorString(e));
     return FGA_E_DEVICE;
   }
   return FGA_OK;
+}
+
+template <typename T>
+fga_status forces_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, const fga_params& p, void* F, hipStream_t s) {
+  void* scratch = nullptr;
+  FGA_TRY(pool_get(&scratch, forces_direct_scratch(m, n, sizeof(T) == 8), s));
+  fga_status st = forces_direct_into<T>(Y, m, X, n, mX, mY, p, F, scratch, s);
+  const hipError_t e = hipStreamSynchronize(s);
+  pool_free(scratch, s);
+  if (st == FGA_OK && e != hipSuccess) {
+    set_error("direct force kernels failed: %s", hipGetErrorString(e));
+    return FGA_E_DEVICE;
+  }
+  return st;
 }
 
 template <typename T>
@@ -693,6 +715,10 @@ template fga_status forces_direct<float>(const void*, int64_t, const void*, int6
                                          const void*, const fga_params&, void*, hipStream_t);
 template fga_status forces_direct<double>(const void*, int64_t, const void*, int64_t, const void*,
                                           const void*, const fga_params&, void*, hipStream_t);
+template fga_status forces_direct_into<float>(const void*, int64_t, const void*, int64_t, const void*,
+                                              const void*, const fga_params&, void*, void*, hipStream_t);
+template fga_status forces_direct_into<double>(const void*, int64_t, const void*, int64_t, const void*,
+                                               const void*, const fga_params&, void*, void*, hipStream_t);
 template fga_status forces_bh_tree<float>(const void*, int64_t, const int*, const BHWide*, int,
                                           const void*, int64_t, double, const fga_params&,
                                           const void*, void*, long long*, hipStream_t);

@@ -1,0 +1,112 @@
+"""Writes tests/golden/oracle_runs.json: FP64 oracle registrations of the
+benchmark workloads at their full sizes, for the parity tests and the
+benchmark's error columns (the oracle is far too slow to run there live).
+
+Only `oracle/` and the seeded input generators in `synth/` are used. Every
+input is rounded to FP32 first, exactly as the HIP path receives it; each
+record stores a SHA-256 of those FP32 inputs so that a reader can tell when
+the generators have changed since the record was written.
+
+Usage:  python tests/golden/make_oracle_runs.py [section ...]
+Sections: lidar, mesh, precision, batch (default: all). Existing records of
+other sections are kept. The whole run takes about an hour on 8 cores.
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_runs.json")
+
+
+def f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def input_hash(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(f32(a).tobytes())
+    return h.hexdigest()
+
+
+def run(X, Y, checkpoints=(), **kw):
+    """Oracle registration of the FP32-rounded pair; poses (caller frame) at
+    the listed iteration counts and at the end."""
+    X64, Y64 = f32(X).astype(np.float64), f32(Y).astype(np.float64)
+    p = oracle.Params(**kw)
+    t0 = time.time()
+    res = oracle.register(X64, Y64, p, trace=bool(checkpoints))
+    rec = {"R": res["R"].tolist(), "t": res["t"].tolist(), "iters": res["iters"],
+           "converged": bool(res["converged"]), "interactions": int(res["interactions"]),
+           "params": {k: v for k, v in vars(p).items() if k != "extras"},
+           "seconds": time.time() - t0}
+    if checkpoints:
+        rec["at"] = {}
+        for k in checkpoints:
+            R, tn, _ = res["history"][k - 1]
+            rec["at"][str(k)] = {"R": R.tolist(), "t": oracle.denormalise_t(R, tn, res["info"]).tolist()}
+    return rec
+
+
+def save(db):
+    tmp = OUT + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1)
+    os.replace(tmp, OUT)
+
+
+def main(sections):
+    db = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    db["_about"] = ("FP64 oracle (oracle/) registrations of the FP32-rounded synthetic workloads "
+                    "(synth/); written by tests/golden/make_oracle_runs.py")
+    if "lidar" in sections:
+        X, Y, _, _ = synth.lidar_pair()
+        rec = run(X, Y, checkpoints=(6,), theta=0.5, max_iter=100)
+        rec["input_sha256"] = input_hash(X, Y)
+        db["lidar_65536_bh0.5"] = rec
+        save(db)
+        print("lidar", rec["seconds"], flush=True)
+    if "precision" in sections:
+        X, Y, _, _ = synth.precision_pair()
+        rec = run(X, Y, checkpoints=(10,), theta=0.0, max_iter=100)
+        rec["input_sha256"] = input_hash(X, Y)
+        db["precision_131072_direct"] = rec
+        save(db)
+        print("precision", rec["seconds"], flush=True)
+    if "mesh" in sections:
+        X, Y, _, _ = synth.mesh_pair()
+        for th in (0.5, 0.8, 0.3):
+            rec = run(X, Y, checkpoints=(3,), theta=th, max_iter=100)
+            rec["input_sha256"] = input_hash(X, Y)
+            db[f"mesh_1048576_bh{th}"] = rec
+            save(db)
+            print("mesh", th, rec["seconds"], flush=True)
+    if "batch" in sections:
+        for tol in (1e-8, 1e-4):
+            key = f"batch_256_bh0.5_tol{tol:g}"
+            recs = db.get(key, [])
+            for pidx in range(len(recs), synth.BATCH_PAIRS):
+                X, Y, _, _ = synth.batch_pair(pidx)
+                rec = run(X, Y, theta=0.5, max_iter=200, tol=tol)
+                rec["input_sha256"] = input_hash(X, Y)
+                recs.append(rec)
+                if pidx % 16 == 15:
+                    db[key] = recs
+                    save(db)
+                    print(key, pidx + 1, flush=True)
+            db[key] = recs
+            save(db)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch"])

@@ -141,3 +141,4 @@ def test_kabsch_rank_one_is_degenerate():
     with pytest.raises(fga.FGAError) as e:
         fga.kabsch(np.full((3, 3), np.nan))
     assert e.value.name == "NONFINITE"
+
