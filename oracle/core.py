@@ -9,6 +9,9 @@ Each function cites the part of the paper it writes out:
   niv_masses                : Sec. "Normalized Intrinsic Volume Measure",
                               Eq. (Normalized_IntrinsicVol); SPM Eq. (FinalSPM)
                               with B = 1 when there are no landmarks.
+  rbf_weights / masses      : Sec. "RBF Mass Interpolation", Eq. (RBF_function),
+                              and the Hadamard product S = N o B of Eq. (FinalSPM)
+                              when landmark correspondences are given.
   direct_forces             : Eq. (GAForce), in C (fga_oracle.c).
   BHTree / bh_forces        : Alg. 1 and the BHForce function of Alg. 2, in C.
   kabsch                    : Eq. (R_Kabsch) and Eq. (transEst).
@@ -30,6 +33,14 @@ the design notes):
     small too); tol <= 0 runs exactly max_iter steps. The paper's threshold
     1e-4 is read as a bound on the norm, i.e. tol = 1e-8 on its square.
   * dnorm(t): the centroid term that has to be added is (mean X - mean Y).
+  * RBF masses (Eq. RBF_function is garbled: its weights carry a point index
+    and the collocation targets are not stated): B interpolates a landmark
+    weight beta at the landmark points and returns to the landmark-free value 1
+    away from them, B(p) = 1 + sum_c lambda_c Phi(|p - a_c|) with
+    Phi(s) = exp(-s^2 / sigma^2) and lambda solving the m x m collocation
+    system sum_c' lambda_c' Phi(|a_c - a_c'|) = beta - 1 at every anchor a_c.
+    The anchors of B(Y) are the template points of the correspondences, those
+    of B(X) the reference points; sigma is taken in the normalised frame.
 """
 from __future__ import annotations
 
@@ -43,7 +54,7 @@ import numpy as np
 __all__ = [
     "build", "lib", "Params", "normalise", "denormalise_t", "niv_masses",
     "direct_forces", "BHTree", "kabsch", "Stepper", "register", "gpe",
-    "angular_deviation_deg", "masses",
+    "angular_deviation_deg", "masses", "rbf_weights",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -117,6 +128,8 @@ class Params:
     damping: str = "fraction"   # or "literal"
     velocity: str = "rigid"     # or "particle"
     masses: str = "niv"         # or "uniform"
+    rbf_sigma: float = 0.03     # RBF kernel width (normalised frame)
+    rbf_weight: float = 100.0   # B at a landmark point (the landmark-free value is 1)
     extras: dict = field(default_factory=dict)
 
 
@@ -178,14 +191,40 @@ def niv_masses(P, rho=16, a=-5.0, b=5.0, depth=20):
     return v_cell / v_union
 
 
-def masses(Xn, Yn, p: Params):
-    """SPM masses S = N o B with B = 1 (no landmarks, Eq. RBF_function second
-    case): reference weights normalised to sum 1, template masses to mean 1.
-    ``uniform`` gives 1/N and 1 (the constant-NIV case)."""
+def rbf_weights(P, anchors, sigma, beta):
+    """Eq. (RBF_function) for the points P (n x 3) and the landmark anchors
+    (m x 3), with the reading in the module docstring: the m x m collocation
+    system for lambda, then B at every point. No anchors: B = 1 (the
+    equation's second case)."""
+    P = np.asarray(P, np.float64)
+    A = np.asarray(anchors, np.float64).reshape(-1, 3)
+    if len(A) == 0:
+        return np.ones(len(P))
+
+    def phi(U, V):
+        d2 = ((U[:, None, :] - V[None, :, :]) ** 2).sum(-1)
+        return np.exp(-d2 / sigma ** 2)
+    lam = np.linalg.solve(phi(A, A), np.full(len(A), beta - 1.0))
+    return 1.0 + phi(P, A) @ lam
+
+
+def masses(Xn, Yn, p: Params, landmarks=None):
+    """SPM masses S = N o B (Eq. FinalSPM): N the NIV values (1 in ``uniform``
+    mode), B the RBF weights of Eq. (RBF_function) for the landmark
+    correspondences ``landmarks = (idx_X, idx_Y)`` (B = 1 without them).
+    Reference weights normalised to sum 1, template masses to mean 1; without
+    landmarks ``uniform`` gives exactly 1/N and 1 (the constant-NIV case)."""
     if p.masses == "uniform":
+        nx, ny = np.ones(len(Xn)), np.ones(len(Yn))
+    else:
+        nx = niv_masses(Xn, p.rho, p.a, p.b, p.depth)
+        ny = niv_masses(Yn, p.rho, p.a, p.b, p.depth)
+    if landmarks is not None and len(landmarks[0]) > 0:
+        ix, iy = (np.asarray(a, np.int64) for a in landmarks)
+        nx = nx * rbf_weights(Xn, Xn[ix], p.rbf_sigma, p.rbf_weight)
+        ny = ny * rbf_weights(Yn, Yn[iy], p.rbf_sigma, p.rbf_weight)
+    elif p.masses == "uniform":
         return np.full(len(Xn), 1.0 / len(Xn)), np.ones(len(Yn))
-    nx = niv_masses(Xn, p.rho, p.a, p.b, p.depth)
-    ny = niv_masses(Yn, p.rho, p.a, p.b, p.depth)
     return nx / nx.sum(), ny / ny.mean()
 
 
@@ -335,13 +374,14 @@ class Stepper:
         return self.last_dT2
 
 
-def register(X, Y, p: Params = None, trace=False):
+def register(X, Y, p: Params = None, trace=False, landmarks=None):
     """Alg. 2 end to end: normalise, masses, (tree), iterate, de-normalise.
-    Returns dict(R, t, R_n, t_n, iters, converged, info, ...) with
-    X ~= R Y + t in the caller's coordinates."""
+    ``landmarks = (idx_X, idx_Y)`` are prior correspondences X[idx_X[k]] <->
+    Y[idx_Y[k]] for the RBF masses. Returns dict(R, t, R_n, t_n, iters,
+    converged, info, ...) with X ~= R Y + t in the caller's coordinates."""
     p = p or Params()
     Xn, Yn, info = normalise(X, Y, p.a, p.b)
-    mX, mY = masses(Xn, Yn, p)
+    mX, mY = masses(Xn, Yn, p, landmarks)
     st = Stepper(Xn, Yn, mX, mY, p)
     hist = []
     converged = False

@@ -662,3 +662,72 @@ def test_stop_rule_never_fires_at_the_first_iteration(oracle_lib):
     assert res["converged"] and res["iters"] >= 2
     k = next(k for k in range(1, len(h)) if h[k] < 1e-4 and h[k] < h[k - 1])
     assert res["iters"] == k + 1
+
+
+# ------------------------------------ RBF landmark masses (Eq. RBF_function)
+SIG, BETA = 0.03, 100.0
+
+
+def test_rbf_without_landmarks_is_one():
+    P = np.random.default_rng(50).normal(size=(20, 3))
+    assert np.array_equal(oracle.rbf_weights(P, np.zeros((0, 3)), SIG, BETA), np.ones(20))
+    X, Y, _, _ = synth.mixture_pair(51, per_comp=16, m=100)
+    a = oracle.masses(X, Y, oracle.Params())
+    b = oracle.masses(X, Y, oracle.Params(), landmarks=(np.zeros(0, int), np.zeros(0, int)))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_rbf_single_anchor_closed_form():
+    rng = np.random.default_rng(52)
+    a = rng.normal(size=3)
+    P = a + rng.normal(size=(30, 3)) * 0.05
+    B = oracle.rbf_weights(P, a[None], SIG, BETA)
+    ref = 1.0 + (BETA - 1.0) * np.exp(-((P - a) ** 2).sum(1) / SIG ** 2)
+    assert np.allclose(B, ref, rtol=1e-14)
+
+
+def test_rbf_two_anchors_closed_form():
+    """Two anchors at distance s: the 2 x 2 collocation system gives
+    lambda_1 = lambda_2 = (beta - 1) / (1 + exp(-s^2 / sigma^2))."""
+    a1, a2 = np.zeros(3), np.array([0.04, 0.0, 0.0])
+    e = np.exp(-0.04 ** 2 / SIG ** 2)
+    rng = np.random.default_rng(53)
+    P = rng.normal(size=(25, 3)) * 0.05
+    B = oracle.rbf_weights(P, np.stack([a1, a2]), SIG, BETA)
+    phi = lambda c: np.exp(-((P - c) ** 2).sum(1) / SIG ** 2)
+    ref = 1.0 + (BETA - 1.0) / (1.0 + e) * (phi(a1) + phi(a2))
+    assert np.allclose(B, ref, rtol=1e-13)
+    # interpolation: B equals beta at both anchors; a planted lambda = beta - 1
+    # (no collocation solve) misses it where the anchors overlap
+    assert np.allclose(oracle.rbf_weights(np.stack([a1, a2]), np.stack([a1, a2]), SIG, BETA), BETA, rtol=1e-13)
+    wrong = 1.0 + (BETA - 1.0) * (np.exp(-0.0) + e)
+    assert not np.isclose(wrong, BETA, rtol=1e-3)
+
+
+def test_rbf_interpolates_and_is_rigid_invariant():
+    rng = np.random.default_rng(54)
+    A = rng.normal(size=(5, 3))
+    P = np.vstack([A, rng.normal(size=(40, 3)), A[0] + 10.0])
+    B = oracle.rbf_weights(P, A, 0.8, BETA)
+    assert np.allclose(B[:5], BETA, rtol=1e-10)
+    assert np.isclose(B[-1], 1.0, atol=1e-12)   # far from every landmark
+    Q = synth.random_rotation(rng, 180.0)
+    c = rng.normal(size=3)
+    B2 = oracle.rbf_weights(P @ Q.T + c, A @ Q.T + c, 0.8, BETA)
+    assert np.allclose(B, B2, rtol=1e-10)
+
+
+def test_spm_hadamard_two_cells_with_landmark():
+    """The two-cell set of the NIV pin with a landmark on point 0 (its
+    neighbours lie far outside sigma): S is proportional to
+    (beta/3, 1/3, 1/3, 1) for both clouds."""
+    P = np.array([[0.0, 0, 0], [0.01, 0, 0], [0, 0.01, 0.01], [1.0, 1, 1]])
+    p = oracle.Params(rbf_sigma=1e-3)
+    mX, mY = oracle.masses(P, P.copy(), p, landmarks=(np.array([0]), np.array([0])))
+    raw = np.array([BETA / 3, 1 / 3, 1 / 3, 1.0])
+    assert np.allclose(mX, raw / raw.sum(), rtol=1e-12)
+    assert np.allclose(mY, raw / raw.mean(), rtol=1e-12)
+    uX, uY = oracle.masses(P, P.copy(), oracle.Params(rbf_sigma=1e-3, masses="uniform"),
+                           landmarks=(np.array([3]), np.array([3])))
+    ru = np.array([1.0, 1.0, 1.0, BETA])
+    assert np.allclose(uX, ru / ru.sum(), rtol=1e-12) and np.allclose(uY, ru / ru.mean(), rtol=1e-12)
