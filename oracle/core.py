@@ -18,6 +18,12 @@ Each function cites the part of the paper it writes out:
   register / Stepper        : Alg. 2, with Eqs. (GAForceDissipative),
                               (TotalGAForce), (PreviousVelocity) and the
                               displacement d = dt * v.
+  D = 2                     : every step takes n x 2 point sets as well: the
+                              quadtree of Alg. 1's 2^D split, Eq. (GAForce) in
+                              the plane, the 2 x 2 Kabsch step, and NIV with
+                              the 2D lattice (rho^2 cells) and disc areas.
+  BHTree.gpe / gpe          : the Plummer energy (diagnostic), direct and with
+                              the BHForce traversal.
 
 Readings of places where the paper is silent or garbled (kept identical in
 the design notes):
@@ -90,6 +96,12 @@ def lib():
         L.oracle_bh_build.restype = v
         L.oracle_bh_build_leaf.argtypes = [v, v, l, l]
         L.oracle_bh_build_leaf.restype = v
+        L.oracle_bh_build_dims.argtypes = [v, v, l, l, ctypes.c_int]
+        L.oracle_bh_build_dims.restype = v
+        L.oracle_direct_forces_2d.argtypes = [v, l, v, l, v, v, d, d, v]
+        L.oracle_direct_forces_2d.restype = None
+        L.oracle_bh_gpe.argtypes = [v, v, l, v, d, d, d, v]
+        L.oracle_bh_gpe.restype = d
         L.oracle_bh_free.argtypes = [v]
         L.oracle_bh_stats.argtypes = [v, v]
         L.oracle_bh_root.argtypes = [v, v]
@@ -158,8 +170,9 @@ def denormalise_t(R, t_n, info):
     s = (r - l)/(b - a); substituting Xn = R Yn + t_n yields the expression
     below."""
     s = (info["r"] - info["l"]) / (info["b"] - info["a"])
-    a1 = np.full(3, info["a"])
-    l1 = np.full(3, info["l"])
+    D = len(t_n)
+    a1 = np.full(D, info["a"])
+    l1 = np.full(D, info["l"])
     return info["xbar"] - R @ info["ybar"] + s * (R @ a1 + t_n - a1) + l1 - R @ l1
 
 
@@ -171,21 +184,24 @@ def niv_masses(P, rho=16, a=-5.0, b=5.0, depth=20):
     The cloud's own bounding box is split into rho cells per axis (a
     zero-extent axis counts as extent 1). Point p lies in cell
     min(floor(rho (p - lo) / ext), rho - 1) per axis. Each point carries a
-    ball of radius (b - a) / (2 depth rho); the volume of the union of the
-    balls in a cell of n_c points is taken as min(n_c V_ball, V_cell)
-    (disjoint balls, capped at full cover). The NIV value is
-    V_cell / V(union); the constant integral over the occupied lattice is
-    dropped because the masses are normalised afterwards."""
+    ball of radius (b - a) / (2 depth rho) (a disc in D = 2); the volume of
+    the union of the balls in a cell of n_c points is taken as
+    min(n_c V_ball, V_cell) (disjoint balls, capped at full cover). The NIV
+    value is V_cell / V(union); the constant integral over the occupied
+    lattice is dropped because the masses are normalised afterwards."""
     P = np.asarray(P, np.float64)
+    D = P.shape[1]
     lo = P.min(axis=0)
     ext = P.max(axis=0) - lo
     ext = np.where(ext > 0, ext, 1.0)
     cell = np.minimum(np.floor(rho * (P - lo) / ext), rho - 1).astype(np.int64)
-    flat = (cell[:, 0] * rho + cell[:, 1]) * rho + cell[:, 2]
-    counts = np.bincount(flat, minlength=rho ** 3)
+    flat = np.zeros(len(P), np.int64)
+    for ax in range(D):
+        flat = flat * rho + cell[:, ax]
+    counts = np.bincount(flat, minlength=rho ** D)
     n_c = counts[flat].astype(np.float64)
     r_ball = (b - a) / (2.0 * depth * rho)
-    v_ball = 4.0 / 3.0 * np.pi * r_ball ** 3
+    v_ball = np.pi * r_ball ** 2 if D == 2 else 4.0 / 3.0 * np.pi * r_ball ** 3
     v_cell = float(np.prod(ext / rho))
     v_union = np.minimum(n_c * v_ball, v_cell)
     return v_cell / v_union
@@ -197,7 +213,7 @@ def rbf_weights(P, anchors, sigma, beta):
     system for lambda, then B at every point. No anchors: B = 1 (the
     equation's second case)."""
     P = np.asarray(P, np.float64)
-    A = np.asarray(anchors, np.float64).reshape(-1, 3)
+    A = np.asarray(anchors, np.float64).reshape(-1, P.shape[1])
     if len(A) == 0:
         return np.ones(len(P))
 
@@ -230,11 +246,13 @@ def masses(Xn, Yn, p: Params, landmarks=None):
 
 # ----------------------------------------------------------------- forces
 def direct_forces(Y, X, mX, mY=None, G=66.7, eps=0.2):
-    """Eq. (GAForce) summed over all reference points (C loop)."""
+    """Eq. (GAForce) summed over all reference points (C loop); n x 3 or
+    n x 2 point sets."""
     Y, X, mX = _c(Y), _c(X), _c(mX)
     mY = None if mY is None else _c(mY)
     F = np.empty_like(Y)
-    lib().oracle_direct_forces(_p(Y), len(Y), _p(X), len(X), _p(mX), _p(mY), G, eps, _p(F))
+    f = lib().oracle_direct_forces_2d if Y.shape[1] == 2 else lib().oracle_direct_forces
+    f(_p(Y), len(Y), _p(X), len(X), _p(mX), _p(mY), G, eps, _p(F))
     return F
 
 
@@ -253,7 +271,9 @@ class BHTree:
     def __init__(self, X, mX, leaf=1):
         self.X = _c(X)
         self.mX = _c(mX)
-        self.h = lib().oracle_bh_build_leaf(_p(self.X), _p(self.mX), len(self.X), int(leaf))
+        self.dims = self.X.shape[1]
+        self.h = lib().oracle_bh_build_dims(_p(self.X), _p(self.mX), len(self.X), int(leaf),
+                                            int(self.dims))
         if not self.h:
             raise ValueError("empty reference")
 
@@ -279,7 +299,7 @@ class BHTree:
         return int(n), ids
 
     def quant(self):
-        q = np.zeros((len(self.X), 3), np.uint32)
+        q = np.zeros((len(self.X), self.dims), np.uint32)
         lib().oracle_bh_quant(self.h, _p(q))
         return q
 
@@ -291,6 +311,15 @@ class BHTree:
         lib().oracle_bh_forces(self.h, _p(Y), len(Y), _p(mY), G, eps, theta, _p(F),
                                ctypes.byref(cnt))
         return (F, int(cnt.value)) if count else F
+
+    def gpe(self, Y, mY=None, G=66.7, eps=0.2, theta=0.5, count=False):
+        """Plummer energy -G sum_i mY_i sum over the Alg. 2 traversal of
+        M / sqrt(r^2 + eps^2) (diagnostic)."""
+        Y = _c(Y)
+        mY = None if mY is None else _c(mY)
+        cnt = ctypes.c_long(0)
+        e = lib().oracle_bh_gpe(self.h, _p(Y), len(Y), _p(mY), G, eps, theta, ctypes.byref(cnt))
+        return (e, int(cnt.value)) if count else e
 
 
 # ----------------------------------------------------------------- Kabsch
@@ -305,12 +334,16 @@ def kabsch(Y, YD):
     d = np.sign(np.linalg.det(U @ Vt))
     if d == 0:
         d = 1.0
-    R = U @ np.diag([1.0, 1.0, d]) @ Vt
+    R = U @ np.diag([1.0] * (C.shape[0] - 1) + [d]) @ Vt
     return R, muD - R @ mu
 
 
 def angular_deviation_deg(R_gt, R):
-    """Eq. (GroundTruthAngularDev)."""
+    """Eq. (GroundTruthAngularDev) (the rotation angle of R_gt^T R; in 2D the
+    trace is 2 cos phi)."""
+    if R.shape[0] == 2:
+        return float(np.degrees(abs(np.arctan2(R_gt[0, 0] * R[1, 0] - R_gt[1, 0] * R[0, 0],
+                                               R_gt[0, 0] * R[0, 0] + R_gt[1, 0] * R[1, 0]))))
     c = np.clip(0.5 * (np.trace(R_gt.T @ R) - 1.0), -1.0, 1.0)
     return float(np.degrees(np.arccos(c)))
 
@@ -329,8 +362,9 @@ class Stepper:
         self.mX = _c(mX)
         self.mY = _c(mY)
         self.V = np.zeros_like(self.Y)
-        self.R = np.eye(3)
-        self.t = np.zeros(3)
+        D = self.Y.shape[1]
+        self.R = np.eye(D)
+        self.t = np.zeros(D)
         self.iters = 0
         self.last_dT2 = np.inf
         self.tree = BHTree(self.X, self.mX) if p.theta > 0 else None

@@ -20,6 +20,10 @@
  *                            the multipole acceptance criterion Eq. (MAC).
  *   - oracle_gpe           : Plummer potential energy, a diagnostic whose
  *                            negative gradient is Eq. (GAForce).
+ *   - oracle_direct_forces_2d, oracle_bh_build_dims : the same in D = 2 (the
+ *                            quadtree of Alg. 1's general 2^D split).
+ *   - oracle_bh_gpe        : the Plummer energy with the BHForce traversal
+ *                            (accepted nodes contribute M / sqrt(r^2 + eps^2)).
  *
  * Readings of the paper used here (all listed in the design notes):
  *   - Cell membership: per-axis integer quantisation of the tight bounding
@@ -74,6 +78,29 @@ void oracle_direct_forces(const double* Y, long m, const double* X, long n,
   }
 }
 
+/* Eq. (GAForce) in D = 2: Y m x 2, X n x 2, F m x 2. */
+void oracle_direct_forces_2d(const double* Y, long m, const double* X, long n,
+                             const double* mX, const double* mY, double G, double eps,
+                             double* F) {
+  const double eps2 = eps * eps;
+  long i;
+#pragma omp parallel for schedule(static)
+  for (i = 0; i < m; ++i) {
+    double fx = 0.0, fy = 0.0;
+    for (long j = 0; j < n; ++j) {
+      double dx = Y[2 * i + 0] - X[2 * j + 0];
+      double dy = Y[2 * i + 1] - X[2 * j + 1];
+      double r2 = dx * dx + dy * dy + eps2;
+      double w = mX[j] / (r2 * sqrt(r2));
+      fx += w * dx;
+      fy += w * dy;
+    }
+    double my = mY ? mY[i] : 1.0;
+    F[2 * i + 0] = -G * my * fx;
+    F[2 * i + 1] = -G * my * fy;
+  }
+}
+
 /* Plummer potential E = -G sum_i sum_j mY_i mX_j / sqrt(|y_i - x_j|^2 + eps^2).
  * Its negative gradient with respect to y_i is Eq. (GAForce). Diagnostic only. */
 double oracle_gpe(const double* Y, long m, const double* X, long n, const double* mX,
@@ -102,7 +129,7 @@ typedef struct onode {
   long* pts;             /* their indices (owned by the tree's index pool) */
   double l;              /* diagonal of the cell's box */
   double mass;           /* sum of the point masses */
-  double com[3];         /* centre of mass */
+  double com[3];         /* centre of mass (first D entries) */
   struct onode* child[8];/* NULL = empty child cell */
   int nchild;            /* number of non-empty children (0 for a leaf) */
 } onode;
@@ -116,6 +143,7 @@ typedef struct otree {
   double lo[3], hi[3];
   long n_nodes, n_leaves, n_internal, n_branching, max_depth;
   long leaf;             /* cells with at most this many points are leaves (Alg. 1: 1) */
+  int dims;              /* D = 3 (octree) or 2 (quadtree); points are n x D */
   long* pool;            /* index storage: one slice per depth level */
 } otree;
 
@@ -133,19 +161,16 @@ static void create_child(otree* t, onode* nd, const double diag_root) {
    * times, so its diagonal is the root diagonal times 2^-k. */
   nd->l = ldexp(diag_root, -nd->depth);
   /* mass and centre of mass of the points inside the cell */
-  double m = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
+  const int D = t->dims;
+  double m = 0.0, c[3] = {0.0, 0.0, 0.0};
   for (long k = 0; k < nd->npts; ++k) {
     long j = nd->pts[k];
     double w = t->mX[j];
     m += w;
-    cx += w * t->X[3 * j + 0];
-    cy += w * t->X[3 * j + 1];
-    cz += w * t->X[3 * j + 2];
+    for (int a = 0; a < D; ++a) c[a] += w * t->X[D * j + a];
   }
   nd->mass = m;
-  nd->com[0] = cx / m;
-  nd->com[1] = cy / m;
-  nd->com[2] = cz / m;
+  for (int a = 0; a < D; ++a) nd->com[a] = c[a] / m;
   t->n_nodes++;
   if (nd->depth > t->max_depth) t->max_depth = nd->depth;
   /* Alg. 1 splits a cell while it holds more than one point; the leaf-size
@@ -155,18 +180,20 @@ static void create_child(otree* t, onode* nd, const double diag_root) {
     return;
   }
   t->n_internal++;
-  /* split at the midpoint: bucket the points by the next quantisation bit */
+  /* split at the midpoint: bucket the points by the next quantisation bit of
+   * each of the D axes (2^D children) */
   const int bit = QBITS - 1 - nd->depth;
+  const int nch = 1 << D;
   long cnt[8] = {0};
   for (long k = 0; k < nd->npts; ++k) {
     long j = nd->pts[k];
-    int o = (int)(((t->q[3 * j + 0] >> bit) & 1u) << 2 | ((t->q[3 * j + 1] >> bit) & 1u) << 1 |
-                  ((t->q[3 * j + 2] >> bit) & 1u));
+    int o = 0;
+    for (int a = 0; a < D; ++a) o = o << 1 | (int)((t->q[D * j + a] >> bit) & 1u);
     cnt[o]++;
   }
   long start[8];
   long acc = 0;
-  for (int o = 0; o < 8; ++o) {
+  for (int o = 0; o < nch; ++o) {
     start[o] = acc;
     acc += cnt[o];
   }
@@ -176,14 +203,14 @@ static void create_child(otree* t, onode* nd, const double diag_root) {
   memcpy(pos, start, sizeof pos);
   for (long k = 0; k < nd->npts; ++k) {
     long j = nd->pts[k];
-    int o = (int)(((t->q[3 * j + 0] >> bit) & 1u) << 2 | ((t->q[3 * j + 1] >> bit) & 1u) << 1 |
-                  ((t->q[3 * j + 2] >> bit) & 1u));
+    int o = 0;
+    for (int a = 0; a < D; ++a) o = o << 1 | (int)((t->q[D * j + a] >> bit) & 1u);
     tmp[pos[o]++] = j;
   }
   memcpy(nd->pts, tmp, sizeof(long) * nd->npts);
   free(tmp);
   int nonempty = 0;
-  for (int o = 0; o < 8; ++o) {
+  for (int o = 0; o < nch; ++o) {
     if (cnt[o] == 0) continue;  /* empty cell: CreateChild does nothing */
     onode* c = new_node(nd->depth + 1, nd->pts + start[o], cnt[o]);
     nd->child[o] = c;
@@ -197,41 +224,48 @@ static void create_child(otree* t, onode* nd, const double diag_root) {
 /* Alg. 1 with leaves of at most `leaf` points (leaf = 1: Alg. 1 itself) on
  * the reference X (n x 3) with masses mX. Returns an opaque handle, or NULL
  * for n < 1 or leaf < 1. */
-void* oracle_bh_build_leaf(const double* X, const double* mX, long n, long leaf) {
-  if (n < 1 || leaf < 1) return NULL;
+void* oracle_bh_build_dims(const double* X, const double* mX, long n, long leaf, int dims) {
+  if (n < 1 || leaf < 1 || (dims != 2 && dims != 3)) return NULL;
+  const int D = dims;
   otree* t = (otree*)calloc(1, sizeof(otree));
   t->n = n;
   t->leaf = leaf;
+  t->dims = D;
   t->X = X;
   t->mX = mX;
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < D; ++a) {
     t->lo[a] = X[a];
     t->hi[a] = X[a];
   }
   for (long j = 1; j < n; ++j)
-    for (int a = 0; a < 3; ++a) {
-      if (X[3 * j + a] < t->lo[a]) t->lo[a] = X[3 * j + a];
-      if (X[3 * j + a] > t->hi[a]) t->hi[a] = X[3 * j + a];
+    for (int a = 0; a < D; ++a) {
+      if (X[D * j + a] < t->lo[a]) t->lo[a] = X[D * j + a];
+      if (X[D * j + a] > t->hi[a]) t->hi[a] = X[D * j + a];
     }
-  t->q = (unsigned*)malloc(sizeof(unsigned) * 3 * n);
+  t->q = (unsigned*)malloc(sizeof(unsigned) * D * n);
   const double cells = ldexp(1.0, QBITS);
   for (long j = 0; j < n; ++j)
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < D; ++a) {
       double ext = t->hi[a] - t->lo[a];
       unsigned q = 0;
       if (ext > 0.0) {
-        double f = floor((X[3 * j + a] - t->lo[a]) / ext * cells);
+        double f = floor((X[D * j + a] - t->lo[a]) / ext * cells);
         q = f >= cells - 1.0 ? (1u << QBITS) - 1u : (unsigned)f;
       }
-      t->q[3 * j + a] = q;
+      t->q[D * j + a] = q;
     }
   t->pool = (long*)malloc(sizeof(long) * n);
   for (long j = 0; j < n; ++j) t->pool[j] = j;
   double d2 = 0.0;
-  for (int a = 0; a < 3; ++a) d2 += (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]);
+  for (int a = 0; a < t->dims; ++a) d2 += (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]);
   t->root = new_node(0, t->pool, n);
   create_child(t, t->root, sqrt(d2));
   return t;
+}
+
+/* Alg. 1 in D = 3 with leaves of at most `leaf` points. */
+void* oracle_bh_build_leaf(const double* X, const double* mX, long n, long leaf) {
+  return oracle_bh_build_dims(X, mX, n, leaf, 3);
 }
 
 /* Alg. 1: build the BH tree on the reference X (n x 3) with masses mX. */
@@ -268,9 +302,7 @@ void oracle_bh_stats(const void* h, long* out5) {
 void oracle_bh_root(const void* h, double* out4) {
   const otree* t = (const otree*)h;
   out4[0] = t->root->mass;
-  out4[1] = t->root->com[0];
-  out4[2] = t->root->com[1];
-  out4[3] = t->root->com[2];
+  for (int a = 0; a < 3; ++a) out4[1 + a] = a < t->dims ? t->root->com[a] : 0.0;
 }
 
 /* Leaf membership: leaf_id[j] = index of the leaf holding reference point j,
@@ -292,10 +324,10 @@ long oracle_bh_leaves(const void* h, long* leaf_id) {
   return next;
 }
 
-/* Quantised coordinates (n x 3) used for cell membership. */
+/* Quantised coordinates (n x D) used for cell membership. */
 void oracle_bh_quant(const void* h, unsigned* q_out) {
   const otree* t = (const otree*)h;
-  memcpy(q_out, t->q, sizeof(unsigned) * 3 * t->n);
+  memcpy(q_out, t->q, sizeof(unsigned) * t->dims * t->n);
 }
 
 /* ----------------------------------------------------------- Alg. 2 BHForce */
@@ -308,35 +340,70 @@ typedef struct bh_ctx {
 /* Adds sum_j m_j (x_j - y) / (|y - x_j|^2 + eps^2)^(3/2) of node nd to acc
  * (the force per unit template mass and per unit G). cnt counts interactions:
  * one per accepted node and one per leaf point summed exactly. */
-static void bh_force(const bh_ctx* c, const onode* nd, const double y[3], double acc[3],
+static void bh_force(const bh_ctx* c, const onode* nd, const double* y, double acc[3],
                      long* cnt) {
   if (nd == NULL || nd->npts == 0) return;  /* empty node: no contribution */
-  const double dx = y[0] - nd->com[0], dy = y[1] - nd->com[1], dz = y[2] - nd->com[2];
-  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const int D = c->t->dims;
+  double d[3] = {0.0, 0.0, 0.0};
+  double rr = 0.0;
+  for (int a = 0; a < D; ++a) {
+    d[a] = y[a] - nd->com[a];
+    rr += d[a] * d[a];
+  }
+  const double r = sqrt(rr);
   if (nd->l / r < c->theta) {  /* Eq. (MAC): far enough, use the node's CoM */
     double r2 = r * r + c->eps2;
     double w = nd->mass / (r2 * sqrt(r2));
-    acc[0] -= w * dx;
-    acc[1] -= w * dy;
-    acc[2] -= w * dz;
+    for (int a = 0; a < D; ++a) acc[a] -= w * d[a];
     (*cnt)++;
     return;
   }
   if (nd->nchild == 0) {  /* leaf that is not accepted: exact sum over its points */
     for (long k = 0; k < nd->npts; ++k) {
       long j = nd->pts[k];
-      double ex = y[0] - c->t->X[3 * j + 0], ey = y[1] - c->t->X[3 * j + 1],
-             ez = y[2] - c->t->X[3 * j + 2];
-      double r2 = ex * ex + ey * ey + ez * ez + c->eps2;
+      double e[3] = {0.0, 0.0, 0.0};
+      double r2 = 0.0;
+      for (int a = 0; a < D; ++a) {
+        e[a] = y[a] - c->t->X[D * j + a];
+        r2 += e[a] * e[a];
+      }
+      r2 += c->eps2;
       double w = c->t->mX[j] / (r2 * sqrt(r2));
-      acc[0] -= w * ex;
-      acc[1] -= w * ey;
-      acc[2] -= w * ez;
+      for (int a = 0; a < D; ++a) acc[a] -= w * e[a];
       (*cnt)++;
     }
     return;
   }
   for (int o = 0; o < 8; ++o) bh_force(c, nd->child[o], y, acc, cnt);
+}
+
+/* Plummer energy of one template particle through the same traversal: an
+ * accepted node contributes mass / sqrt(r^2 + eps^2), a leaf that is not
+ * accepted the exact sum over its points. Returns the sum (per unit G and
+ * template mass, sign not applied). */
+static double bh_pot(const bh_ctx* c, const onode* nd, const double* y, long* cnt) {
+  if (nd == NULL || nd->npts == 0) return 0.0;
+  const int D = c->t->dims;
+  double rr = 0.0;
+  for (int a = 0; a < D; ++a) rr += (y[a] - nd->com[a]) * (y[a] - nd->com[a]);
+  const double r = sqrt(rr);
+  if (nd->l / r < c->theta) {
+    (*cnt)++;
+    return nd->mass / sqrt(rr + c->eps2);
+  }
+  double s = 0.0;
+  if (nd->nchild == 0) {
+    for (long k = 0; k < nd->npts; ++k) {
+      long j = nd->pts[k];
+      double r2 = 0.0;
+      for (int a = 0; a < D; ++a) r2 += (y[a] - c->t->X[D * j + a]) * (y[a] - c->t->X[D * j + a]);
+      s += c->t->mX[j] / sqrt(r2 + c->eps2);
+      (*cnt)++;
+    }
+    return s;
+  }
+  for (int o = 0; o < 8; ++o) s += bh_pot(c, nd->child[o], y, cnt);
+  return s;
 }
 
 /* Alg. 2: for every template particle, F_k = G mY_k * BHForce(root, Y_k).
@@ -348,16 +415,35 @@ void oracle_bh_forces(const void* h, const double* Y, long m, const double* mY, 
   bh_ctx c = {t, theta, eps * eps};
   long total = 0;
   long i;
+  const int D = t->dims;
 #pragma omp parallel for reduction(+ : total) schedule(dynamic, 64)
   for (i = 0; i < m; ++i) {
     double acc[3] = {0.0, 0.0, 0.0};
     long cnt = 0;
-    bh_force(&c, t->root, Y + 3 * i, acc, &cnt);
+    bh_force(&c, t->root, Y + D * i, acc, &cnt);
     double s = G * (mY ? mY[i] : 1.0);
-    F[3 * i + 0] = s * acc[0];
-    F[3 * i + 1] = s * acc[1];
-    F[3 * i + 2] = s * acc[2];
+    for (int a = 0; a < D; ++a) F[D * i + a] = s * acc[a];
     total += cnt;
   }
   if (interactions) *interactions = total;
+}
+
+/* Plummer energy E = -G sum_i mY_i (BH potential at y_i) with the Alg. 2
+ * traversal; Y m x D. interactions (may be NULL) as in oracle_bh_forces. */
+double oracle_bh_gpe(const void* h, const double* Y, long m, const double* mY, double G,
+                     double eps, double theta, long* interactions) {
+  const otree* t = (const otree*)h;
+  bh_ctx c = {t, theta, eps * eps};
+  long total = 0;
+  double e = 0.0;
+  long i;
+  const int D = t->dims;
+#pragma omp parallel for reduction(+ : total, e) schedule(dynamic, 64)
+  for (i = 0; i < m; ++i) {
+    long cnt = 0;
+    e += (mY ? mY[i] : 1.0) * bh_pot(&c, t->root, Y + D * i, &cnt);
+    total += cnt;
+  }
+  if (interactions) *interactions = total;
+  return -G * e;
 }

@@ -511,8 +511,8 @@ def _mutated_oracle(tmp_path, old, new):
     # one level too short
     ("nd->l = ldexp(diag_root, -nd->depth);", "nd->l = ldexp(diag_root, -nd->depth - 1);"),
     # the longest side instead of the diagonal
-    ("for (int a = 0; a < 3; ++a) d2 += (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]);",
-     "for (int a = 0; a < 3; ++a) d2 = fmax(d2, (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]));"),
+    ("for (int a = 0; a < t->dims; ++a) d2 += (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]);",
+     "for (int a = 0; a < t->dims; ++a) d2 = fmax(d2, (t->hi[a] - t->lo[a]) * (t->hi[a] - t->lo[a]));"),
 ])
 def test_node_length_pin_catches_planted_mistakes(oracle_lib, tmp_path, old, new):
     force = _mutated_oracle(tmp_path, old, new)
@@ -731,3 +731,168 @@ def test_spm_hadamard_two_cells_with_landmark():
                            landmarks=(np.array([3]), np.array([3])))
     ru = np.array([1.0, 1.0, 1.0, BETA])
     assert np.allclose(uX, ru / ru.sum(), rtol=1e-12) and np.allclose(uY, ru / ru.mean(), rtol=1e-12)
+
+
+# ------------------------------------------- D = 2 (quadtree, 2 x 2 Kabsch)
+def _rot2(deg):
+    a = np.deg2rad(deg)
+    return np.array([[np.cos(a), -np.sin(a)], [np.sin(a), np.cos(a)]])
+
+
+def test_2d_two_particle_closed_form():
+    c = json.load(open(os.path.join(GOLDEN, "two_particle_force.json")))["cases"][0]
+    F = oracle.direct_forces(np.array([c["y"][:2]]), np.array([c["x"][:2]]), np.array([c["mX"]]),
+                             np.array([c["mY"]]), c["G"], c["eps"])[0]
+    assert c["y"][2] == c["x"][2] == 0.0
+    assert np.allclose(F, [float(v) for v in c["F"][:2]], rtol=1e-14, atol=1e-14)
+
+
+def test_2d_brute_force_extended_precision():
+    rng = np.random.default_rng(70)
+    X, Y = rng.uniform(-2, 2, size=(7, 2)), rng.uniform(-2, 2, size=(5, 2))
+    mX, mY = rng.uniform(0.1, 1, 7), rng.uniform(0.5, 2, 5)
+    F = oracle.direct_forces(Y, X, mX, mY, G, EPS)
+    ref = _mp_forces(np.c_[Y, np.zeros(5)], np.c_[X, np.zeros(7)], mX, mY, G, EPS)
+    assert np.allclose(F, ref[:, :2], rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_quadtree_theta_zero_and_huge():
+    rng = np.random.default_rng(71)
+    X, Y = rng.normal(size=(300, 2)), rng.normal(size=(40, 2)) * 3
+    mX = rng.uniform(0.1, 1, 300)
+    t = oracle.BHTree(X, mX)
+    F0, c0 = t.forces(Y, None, G, EPS, 0.0, count=True)
+    assert c0 == 300 * 40
+    assert np.allclose(F0, oracle.direct_forces(Y, X, mX, None, G, EPS), rtol=1e-12)
+    Fh, ch = t.forces(Y, None, G, EPS, 1e12, count=True)
+    com = (mX[:, None] * X).sum(0) / mX.sum()
+    d = Y - com
+    r2 = (d ** 2).sum(1) + EPS ** 2
+    assert ch == 40 and np.allclose(Fh, -G * mX.sum() * d / (r2 ** 1.5)[:, None], rtol=1e-12)
+
+
+def test_quadtree_equals_octree_of_the_embedded_plane():
+    """Points on the plane z = 0 split into at most 4 children per cell with
+    the 2D box diagonal, so the octree of the embedded points makes the same
+    decisions as the quadtree (Alg. 1 for D = 2 and D = 3)."""
+    X, Y, _, _ = synth.mixture_pair(72, per_comp=64, m=200)
+    X2, Y2 = X[:, :2], Y[:, :2]
+    mX = np.random.default_rng(73).uniform(0.5, 1.5, len(X2))
+    for th in (0.3, 0.6):
+        F2, c2 = oracle.BHTree(X2, mX).forces(Y2, None, G, EPS, th, count=True)
+        F3, c3 = oracle.BHTree(np.c_[X2, np.zeros(len(X2))], mX).forces(np.c_[Y2, np.zeros(len(Y2))],
+                                                                         None, G, EPS, th, count=True)
+        assert c2 == c3 and np.allclose(F2, F3[:, :2], rtol=1e-13) and np.all(F3[:, 2] == 0)
+
+
+def test_quadtree_node_length_halves_per_level():
+    """The 2D version of the node-length pin: unit masses A = (0,0) and
+    B1 = (8,8), B2 = (5,5), B3 = (6.5,6.5); root diagonal 8 sqrt 2."""
+    P = np.array([[0.0, 0], [8.0, 8], [5.0, 5], [6.5, 6.5]])
+    y = np.array([-20.0, -20.0])
+    t = oracle.BHTree(P, np.ones(4))
+
+    def body(pts):
+        d = y - pts.mean(0)
+        return -G * len(pts) * d / (d @ d + EPS ** 2) ** 1.5
+    pts = lambda *ix: P[list(ix)]
+    c1, c2 = pts(1, 2, 3), pts(1, 3)
+    th1 = 4 * np.sqrt(2) / np.linalg.norm(y - c1.mean(0))
+    th2 = 2 * np.sqrt(2) / np.linalg.norm(y - c2.mean(0))
+    exact = sum(body(P[k:k + 1]) for k in range(4))
+    for th, ref in ((th1 * (1 + 1e-9), body(P[:1]) + body(c1)),
+                    (th1 * (1 - 1e-9), body(P[:1]) + body(P[2:3]) + body(c2)),
+                    (th2 * (1 - 1e-9), exact)):
+        assert np.allclose(t.forces(y[None], None, G, EPS, th)[0], ref, rtol=1e-13)
+
+
+def test_quadtree_leaves_match_prefix_grouping():
+    rng = np.random.default_rng(74)
+    X = np.vstack([rng.normal(size=(100, 2)), rng.normal(size=(4, 2)) * 1e-7])
+    X = np.vstack([X, X[:2]])
+    t = oracle.BHTree(X, np.ones(len(X)))
+    n, ids = t.leaves()
+    got = sorted(tuple(sorted(np.flatnonzero(ids == k))) for k in range(n))
+    lo, ext = X.min(0), X.max(0) - X.min(0)
+    q = np.minimum(np.floor((X - lo) / ext * 2.0 ** 20), 2 ** 20 - 1).astype(np.int64)
+    keys = [tuple(((q[j, 0] >> b) & 1) * 2 + ((q[j, 1] >> b) & 1) for b in range(19, -1, -1))
+            for j in range(len(X))]
+    leaves = {}
+    for j, key in enumerate(keys):
+        for k in range(21):
+            if sum(1 for kk in keys if kk[:k] == key[:k]) <= 1 or k == 20:
+                leaves.setdefault(key[:k], []).append(j)
+                break
+    assert got == sorted(tuple(sorted(v)) for v in leaves.values())
+    assert np.array_equal(t.quant(), q.astype(np.uint32))
+
+
+def test_2d_kabsch_and_reflection():
+    rng = np.random.default_rng(75)
+    Y = rng.normal(size=(30, 2))
+    R0 = _rot2(37.0)
+    R, t = oracle.kabsch(Y, Y @ R0.T + [0.3, -0.2])
+    assert np.allclose(R, R0, atol=1e-12) and np.allclose(t, [0.3, -0.2], atol=1e-12)
+    M = np.diag([1.0, -1.0])
+    R, _ = oracle.kabsch(Y, Y @ M.T)
+    assert np.isclose(np.linalg.det(R), 1.0)
+
+
+def test_2d_exact_recovery_full_overlap():
+    g = (np.arange(12) + 0.5) / 12
+    X = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    X = X + np.random.default_rng(76).uniform(-0.02, 0.02, X.shape)
+    Ry, ty = _rot2(25.0), np.array([0.05, -0.08])
+    Y = X @ Ry.T + ty
+    res = oracle.register(X, Y, oracle.Params(max_iter=400, masses="uniform"))
+    assert res["R"].shape == (2, 2)
+    assert oracle.angular_deviation_deg(Ry.T, res["R"]) < 1e-3
+    assert np.linalg.norm(res["t"] - (-Ry.T @ ty)) < 1e-4
+
+
+def test_2d_niv_uses_discs_and_the_planar_lattice():
+    """Two cells with 3 and 1 points: ratio 1 : 3 as in 3D; with rho = 1 and
+    six points the capped case uses the disc area pi r^2 of D = 2."""
+    P = np.array([[0.0, 0], [0.01, 0], [0, 0.01], [1.0, 1]])
+    w = oracle.niv_masses(P)
+    assert np.isclose(w[3] / w[0], 3.0, rtol=1e-14)
+    P = np.vstack([np.zeros((5, 2)), np.ones((1, 2))])
+    w = oracle.niv_masses(P, rho=1, a=-5, b=5, depth=20)
+    vb2, vb3 = np.pi * (10.0 / 40.0) ** 2, 4.0 / 3.0 * np.pi * (10.0 / 40.0) ** 3
+    assert 6 * vb2 > 1.0 > 6 * vb3  # six discs cover the unit cell, six balls would not
+    assert np.allclose(w, 1.0, rtol=1e-14)
+
+
+# ----------------------------------------------- Plummer energy (diagnostic)
+@pytest.mark.parametrize("dims", [2, 3])
+def test_bh_gpe_theta_zero_and_huge(dims):
+    rng = np.random.default_rng(77 + dims)
+    X, Y = rng.normal(size=(200, dims)), rng.normal(size=(30, dims)) * 3
+    mX, mY = rng.uniform(0.1, 1, 200), rng.uniform(0.5, 2, 30)
+    t = oracle.BHTree(X, mX)
+    e0, c0 = t.gpe(Y, mY, G, EPS, 0.0, count=True)
+    assert c0 == 200 * 30
+    ref = -G * sum(mY[i] * (mX / np.sqrt(((Y[i] - X) ** 2).sum(1) + EPS ** 2)).sum() for i in range(30))
+    assert np.isclose(e0, ref, rtol=1e-12)
+    if dims == 3:
+        assert np.isclose(e0, oracle.gpe(Y, X, mX, mY, G, EPS), rtol=1e-12)
+    eh, ch = t.gpe(Y, mY, G, EPS, 1e12, count=True)
+    com = (mX[:, None] * X).sum(0) / mX.sum()
+    assert ch == 30 and np.isclose(eh, -G * (mY * mX.sum() / np.sqrt(((Y - com) ** 2).sum(1) + EPS ** 2)).sum())
+
+
+def test_bh_gpe_gradient_is_bh_force():
+    """With the traversal's accept/open decisions unchanged, the BH energy of
+    one template point moves by -F . dy (its gradient is the BH force)."""
+    X, Y, _, _ = synth.mixture_pair(79, per_comp=64, m=20)
+    mX = np.full(len(X), 1.0 / len(X))
+    t = oracle.BHTree(X, mX)
+    y = Y[3:4].copy()
+    F, c = t.forces(y, None, G, EPS, 0.5, count=True)
+    for a in range(3):
+        h = np.zeros((1, 3))
+        h[0, a] = 1e-6
+        ep, cp = t.gpe(y + h, None, G, EPS, 0.5, count=True)
+        em, cm = t.gpe(y - h, None, G, EPS, 0.5, count=True)
+        assert cp == cm == c
+        assert np.isclose(-(ep - em) / 2e-6, F[0, a], rtol=1e-6, atol=1e-8 * np.abs(F).max())
