@@ -155,6 +155,27 @@ fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const 
                       const void* mY, fga_dtype dt, double theta, const fga_params* p,
                       void* F_out, long long* interactions, void* stream);
 
+/* Size of the static device scratch of fga_forces_direct_noalloc (64 MiB per GPU). */
+#define FGA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* fga_forces with theta = 0 (the exact all-pairs sum of Eq. GAForce) for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same kernels, with
+ * their scratch (the packed reference and the per-range partial forces,
+ * about 16 n + 12 m r bytes in FP32 for r reference ranges) in a fixed
+ * FGA_NOALLOC_SCRATCH_BYTES device array that each GPU holds from the
+ * library's first call there until the process ends. No allocation of any
+ * kind and no synchronisation: the work is queued on `stream` and F_out is
+ * ready when it completes; launch errors are reported, kernel faults surface
+ * at the caller's next synchronisation. Sizes whose scratch exceeds the array
+ * return FGA_E_INVALID_ARG before any device work. Every call on one GPU uses
+ * that GPU's single array, so calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be ordered by the caller; calls on
+ * one stream are ordered by it. Arguments as in fga_forces. */
+fga_status fga_forces_direct_noalloc(const void* Y, int64_t m, const void* X, int64_t n,
+                                     const void* mX, const void* mY, fga_dtype dt,
+                                     const fga_params* p, void* F_out, void* stream);
+
 /* Registration state for Alg. 2: normalises (Appendix A), computes masses,
  * builds the BH tree once if p->theta > 0, and sets T = [I | 0]. The state
  * owns device copies; X and Y may be freed after the call returns. */

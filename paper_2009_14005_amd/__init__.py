@@ -112,6 +112,7 @@ def lib():
             "fga_masses": (st, [vp, dt, i64, P, ctypes.c_int, vp, vp]),
             "fga_forces": (st, [vp, i64, vp, i64, vp, vp, dt, ctypes.c_double, P, vp,
                                 ctypes.POINTER(ctypes.c_longlong), vp]),
+            "fga_forces_direct_noalloc": (st, [vp, i64, vp, i64, vp, vp, dt, P, vp, vp]),
             "fga_state_create": (st, [vp, i64, vp, i64, dt, P, vp, ctypes.POINTER(vp)]),
             "fga_step": (st, [vp, ctypes.c_int]),
             "fga_step_profile": (st, [vp, ctypes.c_int, dp]),
@@ -219,6 +220,20 @@ def forces(Y, X, mX, mY=None, theta: float = 0.0, params: Params = None):
                             _dtype_code(Y), float(theta), ctypes.byref(p), _ptr(F),
                             ctypes.byref(cnt), _stream()))
     return F, cnt.value
+
+
+def forces_direct_noalloc(Y, X, mX, F, mY=None, params: Params = None):
+    """The direct sum of Eq. (GAForce) into the caller's F (m x 3, Y's dtype),
+    with the library's static device scratch: no allocation; queued on the
+    current stream."""
+    Y, X, F = _dev(Y, "Y"), _dev(X, "X"), _dev(F, "F")
+    mX = _dev(mX, "mX", cols=0)
+    mY = _dev(mY, "mY", cols=0) if mY is not None else None
+    p = params or default_params()
+    _check(lib().fga_forces_direct_noalloc(_ptr(Y), Y.shape[0], _ptr(X), X.shape[0], _ptr(mX),
+                                           _ptr(mY), _dtype_code(Y), ctypes.byref(p), _ptr(F),
+                                           _stream()))
+    return F
 
 
 def _mat(a):

@@ -846,6 +846,83 @@ fga_status fga_forces(const void* Y, int64_t m, const void* X, int64_t n, const 
   return st;
 }
 
+}  // extern "C"
+
+// Device scratch of fga_forces_direct_noalloc: a fixed array in the library's
+// code object, one copy per GPU, reached through the address that
+// hipGetSymbolAddress gives on each device (the array's name is only a host
+// stand-in). Every call on a GPU reuses that GPU's copy.
+static __device__ __align__(256) unsigned char scratch[FGA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up once per device.
+fga_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  FGA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d is beyond the %d devices this library tracks", dev, kMaxDevices);
+    return FGA_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      set_error("hipGetSymbolAddress of the static scratch failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return FGA_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FGA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fga_status fga_forces_direct_noalloc(const void* Y, int64_t m, const void* X, int64_t n,
+                                     const void* mX, const void* mY, fga_dtype dt,
+                                     const fga_params* p, void* F_out, void* stream) {
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(mX, "mX"));
+  FGA_TRY(check_ptr(F_out, "F_out"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(m, "m"));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  if (dt == FGA_F32 && p->precision == FGA_PREC_FP64) {
+    set_error("FP64 precision needs FP64 data");
+    return FGA_E_INVALID_ARG;
+  }
+  const size_t need = forces_direct_scratch(m, n, dt == FGA_F64);
+  if (need > (size_t)FGA_NOALLOC_SCRATCH_BYTES) {
+    set_error("m = %lld, n = %lld need %zu bytes of scratch; the static scratch holds %zu",
+              (long long)m, (long long)n, need, (size_t)FGA_NOALLOC_SCRATCH_BYTES);
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(mX, "mX"));
+  FGA_TRY(check_device_ptr(F_out, "F_out"));
+  if (mY) FGA_TRY(check_device_ptr(mY, "mY"));
+  void* buf = nullptr;
+  FGA_TRY(scratch_for_current_device(&buf));
+  hipStream_t s = (hipStream_t)stream;
+  return dt == FGA_F64 ? forces_direct_into<double>(Y, m, X, n, mX, mY, *p, F_out, buf, s)
+                       : forces_direct_into<float>(Y, m, X, n, mX, mY, *p, F_out, buf, s);
+}
+
+}  // extern "C"
+
+extern "C" {
+
 static fga_status validate_pair(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
                                 const fga_params* p) {
   FGA_TRY(check_ptr(X, "X"));

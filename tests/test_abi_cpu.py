@@ -142,3 +142,15 @@ def test_kabsch_rank_one_is_degenerate():
         fga.kabsch(np.full((3, 3), np.nan))
     assert e.value.name == "NONFINITE"
 
+
+def test_noalloc_direct_rejects_oversized_scratch_on_the_host():
+    """The size check of the static-scratch entry point runs before any
+    device call (fake, never-dereferenced pointers)."""
+    L = fga.lib()
+    p = fga.default_params()
+    fake = ctypes.c_void_p(0x1000)
+    st = L.fga_forces_direct_noalloc(fake, 1 << 20, fake, 1 << 23, fake, None, fga.F32,
+                                     ctypes.byref(p), fake, None)
+    assert st == 1 and b"scratch" in L.fga_last_error()
+    st = L.fga_forces_direct_noalloc(fake, 0, fake, 10, fake, None, fga.F32, ctypes.byref(p), fake, None)
+    assert st == 1
