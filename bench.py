@@ -59,10 +59,12 @@ def parse():
     ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra workloads")
-    ap.add_argument("--extras", default="sweep,lidar,direct,precision,batched,mixture",
+    ap.add_argument("--extras", default="sweep,lidar,direct,precision,batched,odometry,mixture,landmarks",
                     help="comma list of extra workloads: sweep (mesh theta 0.3/0.8 and direct), "
-                         "lidar, direct, precision, batched, mixture")
+                         "lidar, direct, precision, batched, odometry, mixture, landmarks")
     ap.add_argument("--batch-pairs", type=int, default=256)
+    ap.add_argument("--leaf", type=int, default=0,
+                    help="leaf size of the group-walk registrations (0 = autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (a known-size kernel for HBM counters)")
     return ap.parse_args()
@@ -152,7 +154,7 @@ class Registration:
         """Interactions of Alg. 2's per-particle decisions over one whole
         registration: the per-particle walk makes exactly those decisions."""
         p = type(self.p).from_buffer_copy(self.p)
-        p.group_width, p.tile = 1, 1
+        p.group_width, p.tile, p.leaf_size = 1, 1, 1
         _, _, rep = self.fga.register(self.Xd, self.Yd, p)
         return rep.interactions
 
@@ -220,7 +222,7 @@ def main():
 
     log("mesh pair: 1,048,576 + 1,048,576 points, Barnes-Hut theta 0.5")
     X, Y, R_gt, t_gt = synth.mesh_pair()
-    p = fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0)
+    p = fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0, leaf_size=args.leaf)
     reg = Registration(fga, torch, X, Y, p)
     elapsed, evaluated = reg.timed(args.steps, args.warmup)
     ms_step = 1e3 * elapsed / args.steps
@@ -246,7 +248,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "weighted_mesh_pair_1048576_bh_theta0.5", "points": [len(X), len(Y)],
                    "theta": 0.5, "iterations": args.iters, "masses": "niv",
-                   "precision": "fp32_kahan_forces_fp64_state", "parallelism": "single_gpu"},
+                   "precision": "fp32_kahan_forces_fp64_state", "parallelism": "single_gpu",
+                   "leaf_size": reg.rep.leaf_size, "traversal": reg.rep.traversal},
         "registrations_per_s": args.steps / elapsed,
         "pct_fp32_vector_peak": 100.0 * value * FLOP_PER_INTERACTION / PEAK_FP32_VECTOR,
         "alg2_interactions_per_registration": alg2,
@@ -273,8 +276,12 @@ def main():
         out["precision_study"] = precision_study(**ctx)
     if "batched" in extras:
         out["batched"] = bench_batched(**ctx)
+    if "odometry" in extras:
+        out["odometry"] = bench_odometry(**ctx)
     if "mixture" in extras:
         out["mixture_fp64_direct"] = bench_mixture(**ctx)
+    if "landmarks" in extras:
+        out["landmarks"] = bench_landmarks(**ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y, extras, out, **ctx)
     print(json.dumps(out), flush=True)
@@ -322,7 +329,8 @@ def bench_sweep(reg, fga, torch, synth, gold, args):
         if th == 0.5:  # the headline's registrations
             sub, r, a2 = reg, {}, reg.alg2
         else:
-            sub = Registration(fga, torch, X, Y, fga.default_params(theta=th, max_iter=args.iters, tol=0.0))
+            sub = Registration(fga, torch, X, Y, fga.default_params(theta=th, max_iter=args.iters, tol=0.0,
+                                                                    leaf_size=args.leaf))
             el, _ = sub.timed(3, 1, f"theta {th} ")
             r, a2 = {"ms_per_registration": el / 3 * 1e3}, sub.alg2_count()
         f_ms, r_ms, ev, _ = sub.profile(args.iters)
@@ -345,7 +353,8 @@ def bench_lidar(fga, torch, synth, gold, args):
     100 iterations per registration."""
     log("LiDAR pair: 65,536 + 65,536 points")
     X, Y, R_gt, t_gt = synth.lidar_pair()
-    reg = Registration(fga, torch, X, Y, fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0))
+    reg = Registration(fga, torch, X, Y, fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0,
+                                                            leaf_size=args.leaf))
     el, evaluated = reg.timed(10, 2)
     alg2 = reg.alg2_count()
     f_ms, r_ms, ev_it, trav = reg.profile(args.iters)
@@ -357,6 +366,7 @@ def bench_lidar(fga, torch, synth, gold, args):
             "error_vs_oracle": vs_oracle(gold.get("lidar_65536_bh0.5"), reg.R, reg.t, X),
             "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, reg.R),
                                          "dt_over_diag": float(np.linalg.norm(reg.t - t_gt) / diag_of(X))},
+            "leaf_size": reg.rep.leaf_size,
             "roofline": roofline(KERNEL_NAMES.get(trav, "?") + " force launch", alg2 / args.iters, f_ms,
                                  measured_traffic("bh_group_iteration_lidar65536_traffic.json"), ev_it),
             "reduction_launch_us": r_ms * 1e3}
@@ -443,9 +453,21 @@ def bench_batched(fga, torch, synth, gold, args):
                            device="cuda:0") for pp in pairs]
     res = {"pairs": k}
     for tol in (1e-8, 1e-4):
-        pb = fga.default_params(theta=0.5, max_iter=200, tol=tol)
-        fga.register_batch(Xs[:4], Ys[:4], pb)  # warm the code paths
+        # fixed configuration: tau option 2, part cap 16, Alg. 1 leaves
+        pf = fga.default_params(theta=0.5, max_iter=200, tol=tol, tile=16, leaf_size=1)
+        fga.register_batch(Xs[:4], Ys[:4], pf)  # warm the code paths
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fga.register_batch(Xs, Ys, pf)
+        torch.cuda.synchronize()
+        t_fixed = time.perf_counter() - t0
+        # autotuned: (tau option, part cap, leaf size) chosen on this batch by
+        # a first call, whose choice later calls of the same shape reuse
+        pb = fga.default_params(theta=0.5, max_iter=200, tol=tol, tile=0, leaf_size=0)
+        t0 = time.perf_counter()
+        fga.register_batch(Xs, Ys, pb)
+        torch.cuda.synchronize()
+        t_tuning = time.perf_counter() - t0
         t0 = time.perf_counter()
         Rb, tb, reps = fga.register_batch(Xs, Ys, pb)
         torch.cuda.synchronize()
@@ -481,13 +503,55 @@ def bench_batched(fga, torch, synth, gold, args):
                     "pairs": len(a)}
         res[f"tol_{tol:g}"] = {
             "batched_registrations_per_s": k / t_batch, "plain_registrations_per_s": k / t_plain,
+            "batched_fixed_config_registrations_per_s": k / t_fixed, "tuning_call_ms": t_tuning * 1e3,
+            "tuned_leaf_size": reps[0].leaf_size,
             "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
             "median_iters_batched": float(np.median([r.iters for r in reps])),
             "median_iters_plain": float(np.median([pl[2].iters for pl in plain])),
             "batched_vs_oracle": summ(eb), "plain_vs_oracle": summ(ep), "batched_vs_plain": summ(ebp),
             "median_phi_vs_ground_truth_deg": float(np.median(gt))}
-        log(f"  tol {tol:g}: batched {t_batch * 1e3:.1f} ms, plain FP64 {t_plain * 1e3:.1f} ms for {k} pairs")
+        log(f"  tol {tol:g}: batched {t_batch * 1e3:.1f} ms (fixed configuration {t_fixed * 1e3:.1f} ms), "
+            f"plain FP64 {t_plain * 1e3:.1f} ms for {k} pairs")
     return res
+
+
+def bench_odometry(fga, torch, synth, gold, args, nframes=32):
+    """Sequential LiDAR odometry: a 32-frame drive through the LiDAR scene
+    (65,536-point ring scans, 1 m per frame), every frame registered to the
+    previous one in one call (theta 0.5, 100 iterations per pair, each
+    frame's tree built once) and the poses composed. Frames per second,
+    relative-pose error against the ground truth, end-point drift over the
+    path length, and the first 8 pairs against the oracle's registrations."""
+    log(f"odometry: {nframes} frames of 65,536 points")
+    scans, poses = synth.lidar_sequence(nframes)
+    frames = [torch.as_tensor(np.ascontiguousarray(sc, np.float32), device="cuda:0") for sc in scans]
+    p = fga.default_params(theta=0.5, tol=0.0, max_iter=args.iters)
+    fga.register_sequence(frames[:3], p)  # warm the code paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Rr, tr, Ra, ta, reps = fga.register_sequence(frames, p)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    R0, p0 = poses[0]
+    rel, gt_abs = [], []
+    for k in range(nframes - 1):
+        Rk, pk = poses[k]
+        Rn, pn = poses[k + 1]
+        rel.append((phi_deg(Rk.T @ Rn, Rr[k]), float(np.linalg.norm(tr[k] - Rk.T @ (pn - pk)))))
+    path = sum(float(np.linalg.norm(poses[k + 1][1] - poses[k][1])) for k in range(nframes - 1))
+    end_err = float(np.linalg.norm(ta[-1] - R0.T @ (poses[-1][1] - p0)))
+    recs = gold.get("odometry_lidar_pairs_bh0.5") or []
+    vo = [vs_oracle(recs[k], Rr[k], tr[k], scans[k]) for k in range(min(len(recs), nframes - 1))]
+    rel = np.array(rel)
+    log(f"  {el * 1e3:.1f} ms for {nframes - 1} pairs ({(nframes - 1) / el:.1f} frames/s), drift {end_err / path:.4f}")
+    return {"frames": nframes, "ms_total": el * 1e3, "frames_per_s": (nframes - 1) / el,
+            "ms_per_frame": el * 1e3 / (nframes - 1),
+            "relative_phi_deg_vs_ground_truth_median": float(np.median(rel[:, 0])),
+            "relative_dt_m_vs_ground_truth_median": float(np.median(rel[:, 1])),
+            "end_point_drift_over_path_length": end_err / path, "path_length_m": path,
+            "vs_oracle_max_phi_deg": max((v["phi_deg"] for v in vo), default=None),
+            "vs_oracle_max_dt_over_diag": max((v["dt_over_diag"] for v in vo), default=None),
+            "pairs_vs_oracle": len(vo)}
 
 
 def bench_mixture(fga, torch, synth, gold, args):
@@ -514,6 +578,49 @@ def bench_mixture(fga, torch, synth, gold, args):
     return {"ms_per_registration": ms, "iterations": rep.iters,
             "interactions_per_s": rep.interactions / (ms * 1e-3),
             "error_vs_oracle": vs_oracle(o, R, t, X), "phi_deg_vs_ground_truth": phi_deg(Rg, R)}
+
+
+def bench_landmarks(fga, torch, synth, gold, args, samples=32):
+    """Registration under large misalignment (full overlap, Euler angles up
+    to 90 degrees about each axis, 1,888 points) with 0, 1 and 3 prior correspondences as
+    RBF landmark masses (Eq. RBF_function, S = N o B): success rate (RMSE of
+    the registered template under 1% of the bounding-box diagonal), time per
+    registration, and the pose against the oracle's for the first samples."""
+    import oracle
+    oracle.build(force=False)
+    log(f"landmark masses: {samples} misaligned pairs, 0 / 1 / 3 prior matches")
+    p = fga.default_params(theta=0.0, max_iter=300, tol=1e-8)
+    res = {}
+    omp_threads(all_threads())
+    for k in (0, 1, 3):
+        ok, ms, err = 0, [], []
+        for j in range(samples):
+            X, Y, Rg, tg, idx = synth.misaligned_pair(j, max_deg=90.0)
+            lm = None
+            if k:
+                pick = np.random.default_rng([7, j]).choice(len(Y), k, replace=False)
+                lm = (idx[pick], pick)
+            Xd = torch.as_tensor(X, dtype=torch.float32, device="cuda:0")
+            Yd = torch.as_tensor(Y, dtype=torch.float32, device="cuda:0")
+            fga.register(Xd, Yd, p, landmarks=lm) if j == 0 else None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R, t, rep = fga.register(Xd, Yd, p, landmarks=lm)
+            ms.append((time.perf_counter() - t0) * 1e3)
+            rmse = float(np.sqrt(np.mean(np.sum((Y @ R.T + t - X[idx]) ** 2, 1))))
+            ok += rmse < 0.01 * diag_of(X)
+            if j < 4:
+                o = oracle.register(np.ascontiguousarray(X, np.float32).astype(np.float64),
+                                    np.ascontiguousarray(Y, np.float32).astype(np.float64),
+                                    oracle.Params(max_iter=300, tol=1e-8), landmarks=lm)
+                err.append((phi_deg(o["R"], R), float(np.linalg.norm(t - o["t"]) / diag_of(X))))
+        e = np.array(err)
+        res[f"priors_{k}"] = {"success_rate": ok / samples, "ms_per_registration_median": float(np.median(ms)),
+                              "registrations_per_s": 1e3 / float(np.mean(ms)),
+                              "vs_oracle_max_phi_deg": float(e[:, 0].max()),
+                              "vs_oracle_max_dt_over_diag": float(e[:, 1].max())}
+        log(f"  {k} priors: success {ok}/{samples}, {np.median(ms):.2f} ms per registration")
+    return res
 
 
 # ------------------------------------------------------------- CPU baseline

@@ -94,8 +94,10 @@ typedef struct {
   int mass_mode;          /* fga_mass_mode */
   int precision;          /* fga_precision */
   int leaf_size;          /* BH leaf size L: cells with at most L points are not split.
-                             0 or 1 = Alg. 1 exactly (singleton leaves); 2..64 trade
-                             accuracy within the BH error for fewer node visits */
+                             1 = Alg. 1 exactly (singleton leaves); 2..64 sum more points
+                             exactly (at least Alg. 1's accuracy) for fewer node visits;
+                             0 = chosen by the autotuner among 1, 2, 4, 8 and 16 (FP32
+                             Barnes-Hut; FP64 and fga_forces use 1) */
   int tile;               /* work split of one iteration, 0..255: reference ranges per template
                              tile of 256 particles, or for the group walk the most parts a
                              heavy group is split into (the largest power of two <= tile);
@@ -107,6 +109,10 @@ typedef struct {
                              a node being accepted only if the MAC holds for the group's whole
                              bounding box (at least as accurate as per-particle); 0 = chosen
                              by the autotuner among these. FP64 uses 1. */
+  double rbf_sigma;       /* width sigma of the RBF kernel exp(-s^2 / sigma^2) of the landmark
+                             masses (Eq. RBF_function), in the normalised frame; 0.03 */
+  double rbf_weight;      /* value of the RBF weight B at a landmark point; away from every
+                             landmark B returns to the landmark-free value 1; 100 */
   int reserved[4];
 } fga_params;
 
@@ -118,6 +124,7 @@ typedef struct {
   double ms_total;        /* wall time of the call in milliseconds */
   int traversal;          /* force kernel in use: 0 = direct sum (theta = 0), 1 = per-particle
                              Barnes-Hut walk, 64 or 128 = group walk of that many particles */
+  int leaf_size;          /* leaf size of the Barnes-Hut tree in use (0 for the direct sum) */
 } fga_report;
 
 typedef struct fga_state fga_state;
@@ -143,6 +150,18 @@ const char* fga_version(void);
  * to mean 1. pts: n x 3 device, masses_out: n device values of dtype dt. */
 fga_status fga_masses(const void* pts, fga_dtype dt, int64_t n, const fga_params* p, int norm,
                       void* masses_out, void* stream);
+
+/* Smooth-particle masses with landmark points, Eq. (FinalSPM) S = N o B: N as
+ * in fga_masses, B the RBF interpolation of Eq. (RBF_function) over the
+ * landmark points pts[landmarks[k]], B(p) = 1 + sum_k lambda_k exp(-|p - a_k|^2 /
+ * sigma^2) with lambda from the collocation system B(a_k) = p->rbf_weight
+ * (solved on the device). landmarks: host array of n_landmarks indices in
+ * [0, n), at most 64; no landmarks gives fga_masses. Landmarks closer than the
+ * RBF width make the system singular: FGA_E_DEGENERATE. Coordinates are those
+ * of pts (no normalisation). */
+fga_status fga_masses_landmarks(const void* pts, fga_dtype dt, int64_t n, const int64_t* landmarks,
+                                int n_landmarks, const fga_params* p, int norm, void* masses_out,
+                                void* stream);
 
 /* Gravitational force on every template particle, Eq. (GAForce):
  *   F_i = -G sum_j mX_j mY_i (y_i - x_j) / (|y_i - x_j|^2 + eps^2)^(3/2).
@@ -176,11 +195,47 @@ fga_status fga_forces_direct_noalloc(const void* Y, int64_t m, const void* X, in
                                      const void* mX, const void* mY, fga_dtype dt,
                                      const fga_params* p, void* F_out, void* stream);
 
+/* Plummer energy of the template in the reference's field, the energy whose
+ * negative gradient is Eq. (GAForce) (a convergence diagnostic; Eq.
+ * GPE_Energy_GA prints |r| + eps where the force implies sqrt(|r|^2 + eps^2)):
+ *   E = -G sum_i mY_i sum_j mX_j / sqrt(|y_i - x_j|^2 + eps^2).
+ * theta == 0: exact double sum; theta > 0: the Alg. 2 traversal of the Alg. 1
+ * tree built here on X, an accepted node contributing M / sqrt(r^2 + eps^2).
+ * Arguments as in fga_forces; E (host) receives the FP64 total, summed in a
+ * fixed order (terms in the data's precision, tiles and totals in FP64). */
+fga_status fga_energy(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                      const void* mY, fga_dtype dt, double theta, const fga_params* p, double* E,
+                      long long* interactions, void* stream);
+
+/* D = 2 (Alg. 1's split with 2^D = 4 children per cell: the quadtree). Point
+ * sets are n x 2 device arrays; they are embedded at z = 0, where the octree
+ * build splits only the two planar axes (a quadtree with the planar box
+ * diagonal), forces stay in the plane, the NIV lattice has rho^2 cells with
+ * disc areas for the point balls, and the rigid step is the 2 x 2 Kabsch
+ * rotation. fga_forces_2d: as fga_forces, F_out m x 2. fga_register_2d:
+ * R row-major 2 x 2 and t (2), host, X ~= R Y + t. */
+fga_status fga_forces_2d(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, fga_dtype dt, double theta, const fga_params* p,
+                         void* F_out, long long* interactions, void* stream);
+fga_status fga_register_2d(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                           const fga_params* p, double R[4], double t[2], fga_report* rep,
+                           void* stream);
+
 /* Registration state for Alg. 2: normalises (Appendix A), computes masses,
  * builds the BH tree once if p->theta > 0, and sets T = [I | 0]. The state
  * owns device copies; X and Y may be freed after the call returns. */
 fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
                             const fga_params* p, void* stream, fga_state** out);
+
+/* fga_state_create with prior correspondences (Alg. 2's landmarks C):
+ * X[lm_X[k]] <-> Y[lm_Y[k]], k < n_landmarks <= 64, host arrays. The masses
+ * become S = N o B (Eq. FinalSPM) with B of Eq. (RBF_function) anchored at the
+ * normalised landmark points of each cloud (the reference's at X[lm_X], the
+ * template's at Y[lm_Y]); sigma = p->rbf_sigma in the normalised frame. */
+fga_status fga_state_create_landmarks(const void* X, int64_t n, const void* Y, int64_t m,
+                                      fga_dtype dt, const int64_t* lm_X, const int64_t* lm_Y,
+                                      int n_landmarks, const fga_params* p, void* stream,
+                                      fga_state** out);
 
 /* Runs n_iters iterations of the Alg. 2 loop body (forces, damped velocity,
  * displacements, Kabsch step, template update) on the state's stream. Stops
@@ -219,6 +274,12 @@ fga_status fga_register(const void* X, int64_t n, const void* Y, int64_t m, fga_
                         const fga_params* p, double R[9], double t[3], fga_report* rep,
                         void* stream);
 
+/* fga_register with landmark correspondences (see fga_state_create_landmarks). */
+fga_status fga_register_landmarks(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                                  const int64_t* lm_X, const int64_t* lm_Y, int n_landmarks,
+                                  const fga_params* p, double R[9], double t[3], fga_report* rep,
+                                  void* stream);
+
 /* npairs independent registrations run together: one set of launches builds
  * every pair's tree, and every iteration is one persistent launch over a work
  * queue replayed from a HIP graph. With FP32 Barnes-Hut (and group_width != 1)
@@ -233,6 +294,20 @@ fga_status fga_register_batch(int npairs, const void* const* X, const int64_t* n
                               const void* const* Y, const int64_t* m, fga_dtype dt,
                               const fga_params* p, double* R, double* t, fga_report* reps,
                               void* stream);
+
+/* Frame-to-frame registration of a sequence of scans (the LiDAR odometry
+ * application): frame k+1 (template) is registered to frame k (reference) for
+ * every k < nframes - 1, all pairs in one fga_register_batch call (every
+ * frame's tree is built once, as the reference of its pair), and the relative
+ * transforms are composed into the pose of every frame in frame 0's
+ * coordinates: T_0 = [I | 0], T_{k+1} = T_k T_rel(k), in FP64 on the host.
+ * frames[k]: device array of sizes[k] x 3 points. R_rel, t_rel: (nframes - 1)
+ * x 9 and x 3 with frame_k ~= R_rel(k) frame_{k+1} + t_rel(k); R_abs, t_abs:
+ * nframes x 9 and x 3 (both may be NULL); reps: nframes - 1 or NULL. All
+ * results are host memory. */
+fga_status fga_register_sequence(int nframes, const void* const* frames, const int64_t* sizes,
+                                 fga_dtype dt, const fga_params* p, double* R_rel, double* t_rel,
+                                 double* R_abs, double* t_abs, fga_report* reps, void* stream);
 
 /* The library keeps the device buffers of finished calls in a cache and reuses
  * them (a registration needs a few dozen buffers; allocating and freeing them

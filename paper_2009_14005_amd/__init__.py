@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
         ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("damping", ctypes.c_int),
         ("velocity", ctypes.c_int), ("mass_mode", ctypes.c_int), ("precision", ctypes.c_int),
         ("leaf_size", ctypes.c_int), ("tile", ctypes.c_int), ("check_every", ctypes.c_int),
-        ("group_width", ctypes.c_int), ("reserved", ctypes.c_int * 4),
+        ("group_width", ctypes.c_int), ("rbf_sigma", ctypes.c_double),
+        ("rbf_weight", ctypes.c_double), ("reserved", ctypes.c_int * 4),
     ]
 
     def replace(self, **kw) -> "Params":
@@ -67,7 +68,8 @@ class Params(ctypes.Structure):
 class _CReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int),
                 ("last_dT2", ctypes.c_double), ("interactions", ctypes.c_longlong),
-                ("ms_total", ctypes.c_double), ("traversal", ctypes.c_int)]
+                ("ms_total", ctypes.c_double), ("traversal", ctypes.c_int),
+                ("leaf_size", ctypes.c_int)]
 
 
 @dataclass
@@ -78,10 +80,12 @@ class Report:
     interactions: int
     ms_total: float
     traversal: int = 0
+    leaf_size: int = 0
 
     @staticmethod
     def _from(c: _CReport) -> "Report":
-        return Report(c.iters, bool(c.converged), c.last_dT2, c.interactions, c.ms_total, c.traversal)
+        return Report(c.iters, bool(c.converged), c.last_dT2, c.interactions, c.ms_total, c.traversal,
+                      c.leaf_size)
 
 
 _lib = None
@@ -110,6 +114,14 @@ def lib():
             "fga_last_error": (ctypes.c_char_p, []),
             "fga_version": (ctypes.c_char_p, []),
             "fga_masses": (st, [vp, dt, i64, P, ctypes.c_int, vp, vp]),
+            "fga_masses_landmarks": (st, [vp, dt, i64, ctypes.POINTER(i64), ctypes.c_int, P,
+                                          ctypes.c_int, vp, vp]),
+            "fga_state_create_landmarks": (st, [vp, i64, vp, i64, dt, ctypes.POINTER(i64),
+                                                ctypes.POINTER(i64), ctypes.c_int, P, vp,
+                                                ctypes.POINTER(vp)]),
+            "fga_register_landmarks": (st, [vp, i64, vp, i64, dt, ctypes.POINTER(i64),
+                                            ctypes.POINTER(i64), ctypes.c_int, P, dp, dp,
+                                            ctypes.POINTER(_CReport), vp]),
             "fga_forces": (st, [vp, i64, vp, i64, vp, vp, dt, ctypes.c_double, P, vp,
                                 ctypes.POINTER(ctypes.c_longlong), vp]),
             "fga_forces_direct_noalloc": (st, [vp, i64, vp, i64, vp, vp, dt, P, vp, vp]),
@@ -125,6 +137,13 @@ def lib():
             "fga_register_batch": (st, [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                         ctypes.POINTER(vp), ctypes.POINTER(i64), dt, P, dp, dp,
                                         ctypes.POINTER(_CReport), vp]),
+            "fga_register_sequence": (st, [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64), dt,
+                                           P, dp, dp, dp, dp, ctypes.POINTER(_CReport), vp]),
+            "fga_energy": (st, [vp, i64, vp, i64, vp, vp, dt, ctypes.c_double, P, dp,
+                                ctypes.POINTER(ctypes.c_longlong), vp]),
+            "fga_forces_2d": (st, [vp, i64, vp, i64, vp, vp, dt, ctypes.c_double, P, vp,
+                                   ctypes.POINTER(ctypes.c_longlong), vp]),
+            "fga_register_2d": (st, [vp, i64, vp, i64, dt, P, dp, dp, ctypes.POINTER(_CReport), vp]),
             "fga_tree_create": (st, [vp, vp, i64, dt, P, vp, ctypes.POINTER(vp)]),
             "fga_tree_info": (st, [vp, ctypes.POINTER(ctypes.c_int64)]),
             "fga_tree_export": (st, [vp, vp, vp, vp]),
@@ -190,14 +209,29 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def masses(pts, params: Params = None, norm: int = 0):
-    """NIV masses of one point set (sum 1 for norm=0, mean 1 for norm=1)."""
+def _idx(a):
+    """Host int64 index array for the C ABI (None for no landmarks)."""
+    import numpy as np
+    if a is None:
+        return None, 0
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return (ctypes.c_int64 * len(a))(*a.tolist()), len(a)
+
+
+def masses(pts, params: Params = None, norm: int = 0, landmarks=None):
+    """Masses of one point set (sum 1 for norm=0, mean 1 for norm=1): NIV, or
+    with ``landmarks`` (point indices) the SPM product with the RBF weights."""
     torch = _torch()
     pts = _dev(pts, "pts")
     p = params or default_params()
     out = torch.empty(pts.shape[0], dtype=pts.dtype, device=pts.device)
-    _check(lib().fga_masses(_ptr(pts), _dtype_code(pts), pts.shape[0], ctypes.byref(p), norm,
-                            _ptr(out), _stream()))
+    if landmarks is None:
+        _check(lib().fga_masses(_ptr(pts), _dtype_code(pts), pts.shape[0], ctypes.byref(p), norm,
+                                _ptr(out), _stream()))
+    else:
+        idx, k = _idx(landmarks)
+        _check(lib().fga_masses_landmarks(_ptr(pts), _dtype_code(pts), pts.shape[0], idx, k,
+                                          ctypes.byref(p), norm, _ptr(out), _stream()))
     return out
 
 
@@ -236,13 +270,61 @@ def forces_direct_noalloc(Y, X, mX, F, mY=None, params: Params = None):
     return F
 
 
+def energy(Y, X, mX, mY=None, theta: float = 0.0, params: Params = None):
+    """Plummer energy of the template in the reference's field (direct or
+    Barnes-Hut). Returns (E, interactions)."""
+    Y, X = _dev(Y, "Y"), _dev(X, "X")
+    mX = _dev(mX, "mX", cols=0)
+    mY = _dev(mY, "mY", cols=0) if mY is not None else None
+    p = params or default_params()
+    E = ctypes.c_double(0.0)
+    cnt = ctypes.c_longlong(0)
+    _check(lib().fga_energy(_ptr(Y), Y.shape[0], _ptr(X), X.shape[0], _ptr(mX), _ptr(mY),
+                            _dtype_code(Y), float(theta), ctypes.byref(p), ctypes.byref(E),
+                            ctypes.byref(cnt), _stream()))
+    return E.value, cnt.value
+
+
+def forces_2d(Y, X, mX, mY=None, theta: float = 0.0, params: Params = None):
+    """Eq. (GAForce) for planar point sets (n x 2); quadtree when theta > 0.
+    Returns (F m x 2, interactions)."""
+    torch = _torch()
+    Y, X = _dev(Y, "Y", cols=2), _dev(X, "X", cols=2)
+    mX = _dev(mX, "mX", cols=0)
+    mY = _dev(mY, "mY", cols=0) if mY is not None else None
+    p = params or default_params()
+    F = torch.empty_like(Y)
+    cnt = ctypes.c_longlong(0)
+    _check(lib().fga_forces_2d(_ptr(Y), Y.shape[0], _ptr(X), X.shape[0], _ptr(mX), _ptr(mY),
+                               _dtype_code(Y), float(theta), ctypes.byref(p), _ptr(F),
+                               ctypes.byref(cnt), _stream()))
+    return F, cnt.value
+
+
+def register_2d(X, Y, params: Params = None):
+    """Alg. 2 for planar point sets (n x 2). Returns (R 2 x 2, t (2), Report)."""
+    import numpy as np
+    X, Y = _dev(X, "X", cols=2), _dev(Y, "Y", cols=2)
+    if X.dtype != Y.dtype:
+        raise TypeError("X and Y must have the same dtype")
+    p = params or default_params()
+    R = (ctypes.c_double * 4)()
+    t = (ctypes.c_double * 2)()
+    rep = _CReport()
+    _check(lib().fga_register_2d(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _dtype_code(X),
+                                 ctypes.byref(p), R, t, ctypes.byref(rep), _stream()))
+    return np.array(R[:]).reshape(2, 2), np.array(t[:]), Report._from(rep)
+
+
 def _mat(a):
     import numpy as np
     return np.array(a[:9]).reshape(3, 3), np.array(a[9:12])
 
 
-def register(X, Y, params: Params = None):
-    """Alg. 2 end to end. Returns (R, t, Report) with X ~= R Y + t."""
+def register(X, Y, params: Params = None, landmarks=None):
+    """Alg. 2 end to end. Returns (R, t, Report) with X ~= R Y + t.
+    ``landmarks = (idx_X, idx_Y)``: prior correspondences X[idx_X[k]] <->
+    Y[idx_Y[k]] for the RBF masses."""
     import numpy as np
     X, Y = _dev(X, "X"), _dev(Y, "Y")
     if X.dtype != Y.dtype:
@@ -251,8 +333,17 @@ def register(X, Y, params: Params = None):
     R = (ctypes.c_double * 9)()
     t = (ctypes.c_double * 3)()
     rep = _CReport()
-    _check(lib().fga_register(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _dtype_code(X),
-                              ctypes.byref(p), R, t, ctypes.byref(rep), _stream()))
+    if landmarks is None:
+        _check(lib().fga_register(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _dtype_code(X),
+                                  ctypes.byref(p), R, t, ctypes.byref(rep), _stream()))
+    else:
+        ix, k = _idx(landmarks[0])
+        iy, k2 = _idx(landmarks[1])
+        if k != k2:
+            raise ValueError("landmark index lists differ in length")
+        _check(lib().fga_register_landmarks(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _dtype_code(X),
+                                            ix, iy, k, ctypes.byref(p), R, t, ctypes.byref(rep),
+                                            _stream()))
     return np.array(R[:]).reshape(3, 3), np.array(t[:]), Report._from(rep)
 
 
@@ -281,18 +372,55 @@ def register_batch(Xs, Ys, params: Params = None):
             [Report._from(r) for r in reps])
 
 
+def register_sequence(frames, params: Params = None):
+    """Frame-to-frame registration of a scan sequence: returns the relative
+    transforms (R_rel[k], t_rel[k]) with frame_k ~= R_rel frame_{k+1} + t_rel,
+    the composed poses (R_abs[k], t_abs[k]) of every frame in frame 0's
+    coordinates, and the per-pair reports."""
+    import numpy as np
+    if len(frames) < 2:
+        raise ValueError("need at least 2 frames")
+    frames = [_dev(f, "frames[k]") for f in frames]
+    dt = _dtype_code(frames[0])
+    for f in frames:
+        if _dtype_code(f) != dt:
+            raise TypeError("all frames must share one dtype")
+    k = len(frames)
+    p = params or default_params()
+    fp = (ctypes.c_void_p * k)(*[f.data_ptr() for f in frames])
+    n = (ctypes.c_int64 * k)(*[f.shape[0] for f in frames])
+    Rr = (ctypes.c_double * (9 * (k - 1)))()
+    tr = (ctypes.c_double * (3 * (k - 1)))()
+    Ra = (ctypes.c_double * (9 * k))()
+    ta = (ctypes.c_double * (3 * k))()
+    reps = (_CReport * (k - 1))()
+    _check(lib().fga_register_sequence(k, fp, n, dt, ctypes.byref(p), Rr, tr, Ra, ta, reps, _stream()))
+    return (np.array(Rr[:]).reshape(k - 1, 3, 3), np.array(tr[:]).reshape(k - 1, 3),
+            np.array(Ra[:]).reshape(k, 3, 3), np.array(ta[:]).reshape(k, 3),
+            [Report._from(r) for r in reps])
+
+
 class State:
     """Registration state of Alg. 2 (normalised clouds, masses, tree, FP64
     rigid state) for step-wise driving, checkpoint and resume."""
 
-    def __init__(self, X, Y, params: Params = None):
+    def __init__(self, X, Y, params: Params = None, landmarks=None):
         X, Y = _dev(X, "X"), _dev(Y, "Y")
         if X.dtype != Y.dtype:
             raise TypeError("X and Y must have the same dtype")
         self.params = params or default_params()
         self._h = ctypes.c_void_p()
-        _check(lib().fga_state_create(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _dtype_code(X),
-                                      ctypes.byref(self.params), _stream(), ctypes.byref(self._h)))
+        if landmarks is None:
+            _check(lib().fga_state_create(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _dtype_code(X),
+                                          ctypes.byref(self.params), _stream(), ctypes.byref(self._h)))
+        else:
+            ix, k = _idx(landmarks[0])
+            iy, k2 = _idx(landmarks[1])
+            if k != k2:
+                raise ValueError("landmark index lists differ in length")
+            _check(lib().fga_state_create_landmarks(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0],
+                                                    _dtype_code(X), ix, iy, k, ctypes.byref(self.params),
+                                                    _stream(), ctypes.byref(self._h)))
 
     def step(self, n_iters: int = 1):
         _check(lib().fga_step(self._h, int(n_iters)))

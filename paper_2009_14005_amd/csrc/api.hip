@@ -116,6 +116,30 @@ fga_status check_params(const fga_params* p) {
     set_error("tile must be in [0, 255] and check_every >= 0");
     return FGA_E_INVALID_ARG;
   }
+  if (!(std::isfinite(p->rbf_sigma) && p->rbf_sigma > 0 && std::isfinite(p->rbf_weight) &&
+        p->rbf_weight > 0)) {
+    set_error("rbf_sigma and rbf_weight must be finite and > 0 (got %g, %g)", p->rbf_sigma,
+              p->rbf_weight);
+    return FGA_E_INVALID_ARG;
+  }
+  return FGA_OK;
+}
+
+// Landmark indices (host memory): count in [0, 64], every index in [0, n).
+fga_status check_landmarks(const int64_t* idx, int count, int64_t n, const char* what) {
+  if (count < 0 || count > kMaxLandmarkPairs) {
+    set_error("landmark count must be in [0, %d] (got %d)", kMaxLandmarkPairs, count);
+    return FGA_E_INVALID_ARG;
+  }
+  if (count > 0 && !idx) {
+    set_error("%s is NULL with %d landmarks", what, count);
+    return FGA_E_INVALID_ARG;
+  }
+  for (int k = 0; k < count; ++k)
+    if (idx[k] < 0 || idx[k] >= n) {
+      set_error("%s[%d] = %lld is outside [0, %lld)", what, k, (long long)idx[k], (long long)n);
+      return FGA_E_INVALID_ARG;
+    }
   return FGA_OK;
 }
 
@@ -271,8 +295,13 @@ struct fga_state {
   int64_t n, m;
   void* X = nullptr;        // packed reference (Morton-sorted for BH)
   void* Q = nullptr;        // packed template (Morton-sorted)
-  BHWide* nodes = nullptr;  // BH tree in child-block layout
+  BHWide* nodes = nullptr;  // BH tree in child-block layout (the one in use)
   int n_nodes = 0;
+  // the trees of the leaf sizes the autotuner may choose from (one entry
+  // when the leaf size is given); a work-split code carries the index
+  std::vector<BHWide*> trees;
+  std::vector<int> tree_nodes, tree_leaf;
+  int leaf_used = 0;                    // leaf size of the tree in use
   RigidState* st = nullptr;
   double* partial = nullptr;
   unsigned* done = nullptr;
@@ -289,10 +318,10 @@ struct fga_state {
     std::vector<unsigned> cost;         // measured list entries per group (empty: not yet)
     std::map<int, std::pair<int4*, int>> items;  // range cap -> wave items, count
   };
-  std::map<int, Groups> groups;         // key K * 4 + tau option
+  std::map<int, Groups> groups;         // key 16 * tree index + 4 K + tau option
   // group walk whose costs are measured by the first iteration of fga_step
-  // (registrations): the K, tau option and part cap of the pending split
-  int pend_K = 0, pend_fi = 0, pend_cap = 0;
+  // (registrations): the K, tau option, part cap and tree of the pending split
+  int pend_K = 0, pend_fi = 0, pend_cap = 0, pend_li = 0;
   int4* ident_items = nullptr;          // one wave item per group, Morton order
 };
 
@@ -312,7 +341,7 @@ static void state_free(fga_state* S) {
   const hipStream_t s = S->s;
   pool_free(S->X, s);
   pool_free(S->Q, s);
-  pool_free(S->nodes, s);
+  for (BHWide* t : S->trees) pool_free(t, s);
   pool_free(S->st, s);
   pool_free(S->partial, s);
   pool_free(S->done, s);
@@ -331,6 +360,9 @@ static void state_free(fga_state* S) {
 // far apart) then form small groups with small boxes instead of one box that
 // opens everything between them.
 static const double kGroupTau[4] = {0.0, 1.0, 2.0, 4.0};
+// leaf sizes the autotuner chooses from (leaf_size 0)
+static const int kLeafOpts[] = {1, 2, 4, 8, 16};
+constexpr int kNumLeafOpts = 5;
 
 static void make_groups(const float* q4, int64_t m, int G, double f, std::vector<int2>& out) {
   out.clear();
@@ -385,7 +417,7 @@ static fga_status upload_items(fga_state* S, const std::vector<int4>& v, int4** 
 // Measures the cost of every group: one iteration with one wave per group
 // over the whole reference counts the list entries of each group; the state
 // is restored afterwards.
-static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
+static fga_status measure_groups(fga_state* S, int K, int li, fga_state::Groups& gt) {
   RigidState saved;
   FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
@@ -399,6 +431,8 @@ static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
     return FGA_E_NOMEM;
   }
   PairDev pd = S->pd;
+  pd.nodes = S->trees[li];
+  pd.n_nodes = S->tree_nodes[li];
   pd.group = K;
   pd.slots = 1;
   pd.tile = kBlock * K;
@@ -426,11 +460,21 @@ static fga_status measure_groups(fga_state* S, int K, fga_state::Groups& gt) {
   return st;
 }
 
-// Device groups of a state for (K, tau option), built on first use.
-static fga_status ensure_groups(fga_state* S, int K, int fi, fga_state::Groups** out) {
-  const int key = K * 4 + fi;
+// Device groups of a state for (K, tau option) on tree li, built on first use
+// (the group tables do not depend on the tree; their costs do).
+static fga_status ensure_groups(fga_state* S, int K, int fi, int li, fga_state::Groups** out) {
+  const int key = 16 * li + K * 4 + fi;
   auto it = S->groups.find(key);
   if (it == S->groups.end()) {
+    for (auto& kv : S->groups)
+      if (kv.first % 16 == key % 16) {  // the same tables for another tree
+        fga_state::Groups gt;
+        gt.host = kv.second.host;
+        gt.n = kv.second.n;
+        it = S->groups.emplace(key, std::move(gt)).first;
+        *out = &it->second;
+        return FGA_OK;
+      }
     if (S->qhost.empty()) {
       S->qhost.resize((size_t)S->m * 4);
       FGA_HIP(hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * S->m, hipMemcpyDeviceToHost, S->s));
@@ -452,11 +496,11 @@ static fga_status ensure_groups(fga_state* S, int K, int fi, fga_state::Groups**
 // the total over 8192 waves) is split over nr = 2, 4, ... <= cap waves by
 // subtrees. Items are ordered by estimated cost, heaviest first, so that the
 // expensive waves start first and the cheap ones fill in behind them.
-static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap,
+static fga_status wave_items(fga_state* S, int K, int li, fga_state::Groups& gt, int cap,
                              const int4** dev, int* count) {
   auto it = gt.items.find(cap);
   if (it == gt.items.end()) {
-    if (gt.cost.empty()) FGA_TRY(measure_groups(S, K, gt));
+    if (gt.cost.empty()) FGA_TRY(measure_groups(S, K, li, gt));
     std::vector<double> cs(gt.cost.begin(), gt.cost.end());
     double total = 0.0;
     for (double c : cs) total += c;
@@ -503,7 +547,12 @@ static fga_status wave_items(fga_state* S, int K, fga_state::Groups& gt, int cap
 // upper bound for the group walk) is set.
 static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = true,
                               bool defer = false) {
-  const int mode = code >> 8;
+  const int mode = (code >> 8) & 255;
+  const int li = code >> 16;  // tree (leaf size) index
+  if (!S->trees.empty()) {
+    pd.nodes = S->trees[li];
+    pd.n_nodes = S->tree_nodes[li];
+  }
   pd.jr = code & 255;
   pd.witems = nullptr;
   pd.gcost = nullptr;
@@ -514,7 +563,7 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
     pd.slots = 1;
     pd.tile = kBlock * pd.group;
     fga_state::Groups* gt = nullptr;
-    FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, &gt));
+    FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, li, &gt));
     pd.n_groups = gt->n;
     if (build && defer) {
       // one wave per group for now; the first iteration measures the costs
@@ -530,8 +579,9 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
       S->pend_K = pd.group;
       S->pend_fi = (mode - 16) >> 2;
       S->pend_cap = pd.jr;
+      S->pend_li = li;
     } else if (build) {
-      FGA_TRY(wave_items(S, pd.group, *gt, pd.jr, &pd.witems, &pd.n_witems));
+      FGA_TRY(wave_items(S, pd.group, li, *gt, pd.jr, &pd.witems, &pd.n_witems));
     } else {
       pd.n_witems = gt->n * pd.jr;  // at most `jr` parts per group
     }
@@ -609,6 +659,7 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands,
 // restored. The stop rule is off while tuning.
 constexpr int kTuneAdvance = 16;
 constexpr int kTuneFinal = 8;
+constexpr int kTuneLeafLead = 3;  // splits of the first tree retimed on every other tree
 static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* best) {
   RigidState init;
   FGA_HIP(hipMemcpyAsync(&init, S->st, sizeof init, hipMemcpyDeviceToHost, S->s));
@@ -618,6 +669,21 @@ static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* bes
   FGA_HIP(hipMemcpyAsync(S->st, &open, sizeof open, hipMemcpyHostToDevice, S->s));
   std::vector<std::pair<float, int>> times;
   fga_status st = tune_ranges(S, cands, &times);
+  if (st == FGA_OK && S->trees.size() > 1) {
+    // leaf sizes: the leading splits of the first tree (Alg. 1's singleton
+    // leaves) timed again on every other tree
+    std::vector<int> more;
+    for (size_t li = 1; li < S->trees.size(); ++li)
+      for (size_t k = 0; k < times.size() && k < (size_t)kTuneLeafLead; ++k)
+        more.push_back((int)li << 16 | (times[k].second & 0xffff));
+    std::vector<std::pair<float, int>> t2;
+    st = tune_ranges(S, more, &t2);
+    times.insert(times.end(), t2.begin(), t2.end());
+    std::stable_sort(times.begin(), times.end(),
+                     [](const std::pair<float, int>& x, const std::pair<float, int>& y) {
+                       return x.first < y.first;
+                     });
+  }
   if (st == FGA_OK) {
     *best = times[0].second;
     if (times.size() > 1) {
@@ -664,6 +730,8 @@ fga_status fga_default_params(fga_params* p) {
   p->tile = 0;
   p->check_every = 16;
   p->group_width = 0;
+  p->rbf_sigma = 0.03;
+  p->rbf_weight = 100.0;
   return FGA_OK;
 }
 
@@ -699,7 +767,25 @@ fga_status fga_masses(const void* pts, fga_dtype dt, int64_t n, const fga_params
   }
   FGA_TRY(check_device_ptr(pts, "pts"));
   FGA_TRY(check_device_ptr(masses_out, "masses_out"));
-  return masses_only(pts, dt, n, *p, norm, masses_out, (hipStream_t)stream);
+  return masses_only(pts, dt, n, nullptr, 0, *p, norm, masses_out, (hipStream_t)stream);
+}
+
+fga_status fga_masses_landmarks(const void* pts, fga_dtype dt, int64_t n, const int64_t* landmarks,
+                                int n_landmarks, const fga_params* p, int norm, void* masses_out,
+                                void* stream) {
+  FGA_TRY(check_ptr(pts, "pts"));
+  FGA_TRY(check_ptr(masses_out, "masses_out"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  FGA_TRY(check_landmarks(landmarks, n_landmarks, n, "landmarks"));
+  if (norm != 0 && norm != 1) {
+    set_error("norm must be 0 (sum 1) or 1 (mean 1)");
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_device_ptr(pts, "pts"));
+  FGA_TRY(check_device_ptr(masses_out, "masses_out"));
+  return masses_only(pts, dt, n, landmarks, n_landmarks, *p, norm, masses_out, (hipStream_t)stream);
 }
 
 fga_status fga_tree_create(const void* X, const void* mX, int64_t n, fga_dtype dt,
@@ -923,6 +1009,140 @@ fga_status fga_forces_direct_noalloc(const void* Y, int64_t m, const void* X, in
 
 extern "C" {
 
+// Registration state of Alg. 2 (defined below); lm_X / lm_Y: landmark
+// correspondences; dims = 2: planar clouds embedded at z = 0.
+static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                               const fga_params* p, void* stream, bool defer, fga_state** out,
+                               const int64_t* lm_X = nullptr, const int64_t* lm_Y = nullptr,
+                               int n_lm = 0, int dims = 3);
+
+fga_status fga_energy(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                      const void* mY, fga_dtype dt, double theta, const fga_params* p, double* E,
+                      long long* interactions, void* stream) {
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(mX, "mX"));
+  FGA_TRY(check_ptr(E, "E"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(m, "m"));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  if (!(std::isfinite(theta) && theta >= 0)) {
+    set_error("theta must be finite and >= 0 (got %g)", theta);
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(mX, "mX"));
+  if (mY) FGA_TRY(check_device_ptr(mY, "mY"));
+  hipStream_t s = (hipStream_t)stream;
+  const bool f64 = dt == FGA_F64;
+  if (theta == 0.0) {
+    fga_status st = f64 ? energy_direct<double>(Y, m, X, n, mX, mY, *p, E, s)
+                        : energy_direct<float>(Y, m, X, n, mX, mY, *p, E, s);
+    if (st == FGA_OK && interactions) *interactions = (long long)m * (long long)n;
+    return st;
+  }
+  fga_tree* tr = nullptr;
+  FGA_TRY(fga_tree_create(X, mX, n, dt, p, stream, &tr));
+  void* Y4 = nullptr;
+  int* yorder = nullptr;
+  const size_t v4 = f64 ? sizeof(double4) : sizeof(float4);
+  fga_status st = FGA_OK;
+  if (pool_get(&Y4, v4 * m, s) != FGA_OK || pool_get(&yorder, sizeof(int) * m, s) != FGA_OK)
+    st = FGA_E_NOMEM;
+  if (st == FGA_OK)
+    st = f64 ? pack_points<double>(Y, Y, m, Y4, s) : pack_points<float>(Y, Y, m, Y4, s);
+  TreeSeg seg{0, m};
+  if (st == FGA_OK)
+    st = f64 ? sort_points_morton<double>(1, &seg, Y4, m, yorder, s)
+             : sort_points_morton<float>(1, &seg, Y4, m, yorder, s);
+  if (st == FGA_OK)
+    st = f64 ? energy_bh_tree<double>(Y, m, yorder, tr->wide, tr->Xs, theta, *p, mY, E, interactions, s)
+             : energy_bh_tree<float>(Y, m, yorder, tr->wide, tr->Xs, theta, *p, mY, E, interactions, s);
+  pool_free(Y4, s);
+  pool_free(yorder, s);
+  fga_tree_destroy(tr);
+  return st;
+}
+
+// Planar input: n x 2 points copied to n x 3 with z = 0 in pool memory.
+static fga_status planar_copy(const void* P, int64_t n, fga_dtype dt, hipStream_t s, void** out) {
+  const size_t es = dt == FGA_F64 ? 8 : 4;
+  FGA_TRY(pool_get(out, es * 3 * (size_t)n, s));
+  fga_status st = embed_planar(P, n, dt == FGA_F64, *out, s);
+  if (st != FGA_OK) {
+    pool_free(*out, s);
+    *out = nullptr;
+  }
+  return st;
+}
+
+fga_status fga_forces_2d(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, fga_dtype dt, double theta, const fga_params* p,
+                         void* F_out, long long* interactions, void* stream) {
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(F_out, "F_out"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(m, "m"));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_params(p));
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(F_out, "F_out"));
+  hipStream_t s = (hipStream_t)stream;
+  void *Y3 = nullptr, *X3 = nullptr, *F3 = nullptr;
+  fga_status st = planar_copy(Y, m, dt, s, &Y3);
+  if (st == FGA_OK) st = planar_copy(X, n, dt, s, &X3);
+  if (st == FGA_OK && pool_get(&F3, (dt == FGA_F64 ? 8 : 4) * 3 * (size_t)m, s) != FGA_OK) st = FGA_E_NOMEM;
+  if (st == FGA_OK) st = fga_forces(Y3, m, X3, n, mX, mY, dt, theta, p, F3, interactions, stream);
+  if (st == FGA_OK) st = take_planar(F3, m, dt == FGA_F64, F_out, s);
+  if (st == FGA_OK && hipStreamSynchronize(s) != hipSuccess) st = FGA_E_DEVICE;
+  pool_free(Y3, s);
+  pool_free(X3, s);
+  pool_free(F3, s);
+  return st;
+}
+
+fga_status fga_register_2d(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                           const fga_params* p, double R[4], double t[2], fga_report* rep,
+                           void* stream) {
+  FGA_TRY(check_ptr(X, "X"));
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(R, "R"));
+  FGA_TRY(check_ptr(t, "t"));
+  FGA_TRY(check_dtype(dt));
+  FGA_TRY(check_count(n, "n"));
+  FGA_TRY(check_count(m, "m"));
+  FGA_TRY(check_params(p));
+  FGA_TRY(check_device_ptr(X, "X"));
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  const double t0 = now_ms();
+  hipStream_t s = (hipStream_t)stream;
+  void *X3 = nullptr, *Y3 = nullptr;
+  fga_status st = planar_copy(X, n, dt, s, &X3);
+  if (st == FGA_OK) st = planar_copy(Y, m, dt, s, &Y3);
+  fga_state* S = nullptr;
+  if (st == FGA_OK) st = state_create(X3, n, Y3, m, dt, p, stream, true, &S, nullptr, nullptr, 0, 2);
+  pool_free(X3, s);
+  pool_free(Y3, s);
+  double R3[9], t3[3];
+  if (st == FGA_OK) st = fga_step(S, p->max_iter);
+  if (st == FGA_OK) st = fga_state_get(S, R3, t3, rep);
+  if (S) fga_state_destroy(S);
+  if (st == FGA_OK) {
+    R[0] = R3[0];
+    R[1] = R3[1];
+    R[2] = R3[3];
+    R[3] = R3[4];
+    t[0] = t3[0];
+    t[1] = t3[1];
+  }
+  if (rep) rep->ms_total = now_ms() - t0;
+  return st;
+}
+
 static fga_status validate_pair(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
                                 const fga_params* p) {
   FGA_TRY(check_ptr(X, "X"));
@@ -935,9 +1155,12 @@ static fga_status validate_pair(const void* X, int64_t n, const void* Y, int64_t
 }
 
 static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
-                               const fga_params* p, void* stream, bool defer, fga_state** out) {
+                               const fga_params* p, void* stream, bool defer, fga_state** out,
+                               const int64_t* lm_X, const int64_t* lm_Y, int n_lm, int dims) {
   FGA_TRY(validate_pair(X, n, Y, m, dt, p));
   FGA_TRY(check_ptr(out, "out"));
+  FGA_TRY(check_landmarks(lm_X, n_lm, n, "lm_X"));
+  FGA_TRY(check_landmarks(lm_Y, n_lm, m, "lm_Y"));
   FGA_TRY(check_device_ptr(X, "X"));
   FGA_TRY(check_device_ptr(Y, "Y"));
   hipStream_t s = (hipStream_t)stream;
@@ -957,10 +1180,10 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
       pool_get(&S->st, sizeof(RigidState), s) != FGA_OK) {
     return fail(FGA_E_NOMEM);
   }
-  CloudIn cx{X, n}, cy{Y, m};
+  CloudIn cx{X, n, lm_X, n_lm}, cy{Y, m, lm_Y, n_lm};
   PrepOut po{S->X, S->Q, S->st};
   fga_params pp = *p;
-  fga_status st = prep_pairs(1, &cx, &cy, dt, pp, &po, &S->norm, s);
+  fga_status st = prep_pairs(1, &cx, &cy, dt, pp, &po, &S->norm, s, dims);
   if (st != FGA_OK) return fail(st);
   TreeSeg sy{0, m};
   st = S->f64 ? sort_points_morton<double>(1, &sy, S->Q, m, nullptr, s)
@@ -975,19 +1198,30 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
         hipEventRecord(S->qready, s) != hipSuccess)
       return fail(FGA_E_DEVICE);
   }
-  if (p->theta > 0) {
+  const bool bh = p->theta > 0;
+  // leaf sizes: the given one, or (leaf_size 0, FP32) every option for the
+  // autotuner; FP64 keeps Alg. 1's singleton leaves
+  const bool leaf_auto = bh && p->leaf_size == 0 && !S->f64;
+  if (bh) {
+    if (leaf_auto) S->tree_leaf.assign(kLeafOpts, kLeafOpts + kNumLeafOpts);
+    else S->tree_leaf.assign(1, p->leaf_size > 0 ? p->leaf_size : 1);
+    S->trees.assign(S->tree_leaf.size(), nullptr);
+    S->tree_nodes.assign(S->tree_leaf.size(), 0);
+  }
+  // builds tree li (leaf size tree_leaf[li]) on the Morton-sorted reference
+  auto build_tree = [&](size_t li) -> fga_status {
     TreeSeg sx{0, n};
     int off[2] = {0, 0};
     BHNode* pre = nullptr;
-    st = S->f64 ? build_trees<double>(1, &sx, S->X, n, p->leaf_size, &pre, off, nullptr, S->tree_stats, s)
-                : build_trees<float>(1, &sx, S->X, n, p->leaf_size, &pre, off, nullptr, S->tree_stats, s);
-    if (st != FGA_OK) return fail(st);
-    S->n_nodes = off[1] - off[0];
-    st = relayout_wide(pre, S->n_nodes, 1, off, &S->nodes, s);
+    const int L = S->tree_leaf[li];
+    fga_status bs = S->f64 ? build_trees<double>(1, &sx, S->X, n, L, &pre, off, nullptr, S->tree_stats, s)
+                           : build_trees<float>(1, &sx, S->X, n, L, &pre, off, nullptr, S->tree_stats, s);
+    if (bs != FGA_OK) return bs;
+    S->tree_nodes[li] = off[1] - off[0];
+    bs = relayout_wide(pre, S->tree_nodes[li], 1, off, &S->trees[li], s);
     pool_free(pre, s);
-    if (st != FGA_OK) return fail(st);
-  }
-  const bool bh = p->theta > 0;
+    return bs;
+  };
   // candidate work splits, encoded mode << 8 | reference ranges; mode is the
   // number of lanes per particle (1, 2, 4, 8) of the per-particle walk, or
   // 16 + K for the group walk with K particles per lane
@@ -1027,7 +1261,8 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   }
   // a cached tuning result needs only its own split; otherwise every
   // candidate is timed
-  const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width);
+  const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width) +
+                          (bh ? "_L" + std::to_string(leaf_auto ? 0 : S->tree_leaf[0]) : "");
   int best = cands[0];
   bool tuned = cands.size() == 1;
   if (!tuned) {
@@ -1039,6 +1274,10 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
       tuned = true;
     }
   }
+  // the trees: all of them when they are to be tuned, else only the chosen one
+  for (size_t li = 0; li < S->trees.size(); ++li)
+    if (!tuned || (int)li == (best >> 16))
+      if (fga_status bs = build_tree(li); bs != FGA_OK) return fail(bs);
   const std::vector<int> used = tuned ? std::vector<int>{best} : cands;
   size_t max_items = 0;
   for (int c : used) {
@@ -1088,6 +1327,19 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     g_tune[key] = best;
     tune_save_locked();
   }
+  if (bh) {  // the chosen tree stays; the others are released
+    const size_t lb = (size_t)(best >> 16);
+    for (size_t li = 0; li < S->trees.size(); ++li)
+      if (li != lb && S->trees[li]) {
+        pool_free(S->trees[li], s);
+        S->trees[li] = nullptr;
+      }
+    S->nodes = S->trees[lb];
+    S->n_nodes = S->tree_nodes[lb];
+    S->leaf_used = S->tree_leaf[lb];
+    pd.nodes = S->nodes;
+    pd.n_nodes = S->n_nodes;
+  }
   if (fga_status gs = apply_split(S, pd, best, true, defer); gs != FGA_OK) return fail(gs);
   if (S->V) {  // trial iterations wrote per-particle velocities; the state starts at rest
     const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
@@ -1103,12 +1355,19 @@ fga_status fga_state_create(const void* X, int64_t n, const void* Y, int64_t m, 
   return state_create(X, n, Y, m, dt, p, stream, false, out);
 }
 
+fga_status fga_state_create_landmarks(const void* X, int64_t n, const void* Y, int64_t m,
+                                      fga_dtype dt, const int64_t* lm_X, const int64_t* lm_Y,
+                                      int n_landmarks, const fga_params* p, void* stream,
+                                      fga_state** out) {
+  return state_create(X, n, Y, m, dt, p, stream, false, out, lm_X, lm_Y, n_landmarks);
+}
+
 // The first iteration of a deferred group split: one wave per group counts
 // every group's list entries while it iterates; the balanced wave items are
 // then built from those costs.
 static fga_status first_step_measured(fga_state* S) {
   fga_state::Groups* gt = nullptr;
-  FGA_TRY(ensure_groups(S, S->pend_K, S->pend_fi, &gt));
+  FGA_TRY(ensure_groups(S, S->pend_K, S->pend_fi, S->pend_li, &gt));
   unsigned* cost = nullptr;
   FGA_TRY(pool_get(&cost, sizeof(unsigned) * gt->n, S->s));
   PairDev pd = S->pd;
@@ -1129,7 +1388,7 @@ static fga_status first_step_measured(fga_state* S) {
   }
   for (auto& kv : gt->items) pool_free(kv.second.first, S->s);  // built from older costs
   gt->items.clear();
-  FGA_TRY(wave_items(S, S->pend_K, *gt, S->pend_cap, &S->pd.witems, &S->pd.n_witems));
+  FGA_TRY(wave_items(S, S->pend_K, S->pend_li, *gt, S->pend_cap, &S->pd.witems, &S->pd.n_witems));
   S->pd.n_items = (S->pd.n_witems + kBlock / kWave - 1) / (kBlock / kWave);
   S->pend_K = 0;
   return FGA_OK;
@@ -1236,6 +1495,7 @@ fga_status fga_state_get(const fga_state* S, double R[9], double t[3], fga_repor
     rep->interactions = h.interactions;
     rep->ms_total = 0.0;
     rep->traversal = !S->nodes ? 0 : S->pd.group ? kWave * S->pd.group : 1;
+    rep->leaf_size = S->leaf_used;
   }
   if (h.flags & 2) {
     set_error("Barnes-Hut group walk: traversal stack overflow (forces incomplete)");
@@ -1306,6 +1566,23 @@ fga_status fga_register(const void* X, int64_t n, const void* Y, int64_t m, fga_
   return st;
 }
 
+fga_status fga_register_landmarks(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
+                                  const int64_t* lm_X, const int64_t* lm_Y, int n_landmarks,
+                                  const fga_params* p, double R[9], double t[3], fga_report* rep,
+                                  void* stream) {
+  FGA_TRY(validate_pair(X, n, Y, m, dt, p));
+  FGA_TRY(check_ptr(R, "R"));
+  FGA_TRY(check_ptr(t, "t"));
+  const double t0 = now_ms();
+  fga_state* S = nullptr;
+  FGA_TRY(state_create(X, n, Y, m, dt, p, stream, true, &S, lm_X, lm_Y, n_landmarks));
+  fga_status st = fga_step(S, p->max_iter);
+  if (st == FGA_OK) st = fga_state_get(S, R, t, rep);
+  fga_state_destroy(S);
+  if (rep) rep->ms_total = now_ms() - t0;
+  return st;
+}
+
 }  // extern "C"
 
 namespace {
@@ -1316,6 +1593,8 @@ struct BatchBufs {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   hipEvent_t ev = nullptr;
+  int tuned_fi = 0, tuned_cap = 0;  // the group walk's tau option and part cap in use
+  int tuned_leaf = 0;               // leaf size of the trees in use
   ~BatchBufs() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1384,39 +1663,98 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     FGA_HIP(hipMemcpyAsync(qh.data(), Qp, sizeof(float) * 4 * NY, hipMemcpyDeviceToHost, s));
     FGA_HIP(hipEventRecord(B.ev, s));
   }
-  BHWide* nodes = nullptr;
-  std::vector<int> noff(npairs + 1, 0);
-  int tstats[3];
-  if (p.theta > 0) {
+  // the trees of all pairs for one leaf size (one set of launches)
+  struct TreeSet {
+    int leaf;
+    BHWide* nodes;
+    std::vector<int> off;
+  };
+  std::vector<TreeSet> tsets;
+  auto build_set = [&](int L) -> fga_status {
+    TreeSet ts{L, nullptr, std::vector<int>(npairs + 1, 0)};
     BHNode* pre = nullptr;
-    FGA_TRY(build_trees<T>(npairs, xs.data(), Xp, NX, p.leaf_size, &pre, noff.data(), nullptr, tstats, s));
+    int tstats[3];
+    FGA_TRY(build_trees<T>(npairs, xs.data(), Xp, NX, L, &pre, ts.off.data(), nullptr, tstats, s));
     B.ptrs.push_back(pre);
-    FGA_TRY(relayout_wide(pre, noff[npairs], npairs, noff.data(), &nodes, s));
-    B.ptrs.push_back(nodes);
-  }
+    FGA_TRY(relayout_wide(pre, ts.off[npairs], npairs, ts.off.data(), &ts.nodes, s));
+    B.ptrs.push_back(ts.nodes);
+    tsets.push_back(std::move(ts));
+    return FGA_OK;
+  };
+  if (p.theta > 0) FGA_TRY(build_set(p.leaf_size > 0 ? p.leaf_size : 1));
+  BHWide* nodes = p.theta > 0 ? tsets[0].nodes : nullptr;
+  std::vector<int> noff = p.theta > 0 ? tsets[0].off : std::vector<int>(npairs + 1, 0);
   int dev = 0, cus = 256;
   FGA_HIP(hipGetDevice(&dev));
   FGA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const IterConsts c = make_iter_consts(p);
   // the group walk (FP32 Barnes-Hut unless group_width = 1) with one particle
-  // per lane: groups bounded by twice the median box of fixed 64-runs, split
-  // by measured cost
+  // per lane: groups of consecutive template particles bounded by
+  // kGroupTau[fi] times the median box of fixed 64-runs, heavy groups split
+  // into at most `cap` parts by their measured cost. (fi, cap) are tuned on
+  // the batch itself (tile = 0) and cached for batches of the same shape
+  // class, or fixed by the caller (tile > 0: cap = the largest power of two
+  // <= tile, fi = 2).
   std::vector<PairDev> pds(npairs);
-  std::vector<std::vector<int2>> groups(npairs);
-  std::vector<int> goff(npairs + 1, 0);
+  const int kCap = 16;  // most parts per group (capacity of the wave-item arrays)
+  std::vector<int> fis{2}, caps{16};
+  std::vector<int> leaves{p.leaf_size > 0 ? p.leaf_size : 1};
+  std::string bkey;
+  bool btuned = true;
   if (grouped) {
-    FGA_HIP(hipEventSynchronize(B.ev));
-    for (int k = 0; k < npairs; ++k) {
-      make_groups(qh.data() + 4 * yoff[k], m[k], kWave, kGroupTau[2], groups[k]);
-      goff[k + 1] = goff[k] + (int)groups[k].size();
+    if (p.tile > 0) {
+      int cap = 1;
+      while (2 * cap <= std::min(p.tile, kCap)) cap *= 2;
+      caps = {cap};
+    } else {
+      auto lg = [](int64_t v) {
+        int q = 0;
+        while ((int64_t(1) << (q + 1)) <= v) ++q;
+        return q;
+      };
+      char buf[96];
+      snprintf(buf, sizeof buf, "batch_p%d_k%d_m%d_n%d_t%d_L%d", p.precision, lg(npairs), lg(NY),
+               lg(NX), (int)std::lround(p.theta * 1000), p.leaf_size);
+      bkey = buf;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_load_locked();
+      auto it = g_tune.find(bkey);
+      if (it != g_tune.end()) {
+        fis = {(it->second >> 8) & 255};
+        caps = {it->second & 255};
+        leaves = {it->second >> 16};
+      } else {
+        fis = {1, 2, 3};
+        caps = {4, 16};
+        if (p.leaf_size == 0) leaves = {1, 4, 8};
+        btuned = false;
+      }
     }
+    FGA_HIP(hipEventSynchronize(B.ev));
   }
-  const int kCap = 16;  // parts per group in the group walk
+  // group tables of every candidate tau option (host), and their offsets
+  std::map<int, std::vector<std::vector<int2>>> gtab;
+  std::map<int, std::vector<int>> gofs;
+  int max_groups = 0;
+  for (int fi : fis) {
+    if (!grouped) break;
+    auto& g = gtab[fi];
+    auto& go = gofs[fi];
+    g.resize(npairs);
+    go.assign(npairs + 1, 0);
+    for (int k = 0; k < npairs; ++k) {
+      make_groups(qh.data() + 4 * yoff[k], m[k], kWave, kGroupTau[fi], g[k]);
+      go[k + 1] = go[k] + (int)g[k].size();
+    }
+    max_groups = std::max(max_groups, go[npairs]);
+  }
   std::vector<int> item_off(npairs + 1, 0);
   for (int k = 0; k < npairs; ++k) {
     if (grouped) {
-      // capacity for up to kCap wave items per group
-      const int nwi = (int)groups[k].size() * kCap;
+      // capacity for up to kCap wave items per group (the most groups of any candidate)
+      int ng = 0;
+      for (int fi : fis) ng = std::max(ng, (int)gtab[fi][k].size());
+      const int nwi = ng * kCap;
       pds[k].n_items = (nwi + kBlock / kWave - 1) / (kBlock / kWave);
       pds[k].jr = 1;
       pds[k].tile = kBlock;
@@ -1454,8 +1792,8 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
   FGA_TRY(B.get(&dpairs, sizeof(PairDev) * npairs));
   FGA_TRY(B.get(&ditems, sizeof(int2) * max_queue));
   if (grouped) {
-    FGA_TRY(B.get(&dwitems, sizeof(int4) * (size_t)goff[npairs] * kCap));
-    FGA_TRY(B.get(&gcost, sizeof(unsigned) * goff[npairs]));
+    FGA_TRY(B.get(&dwitems, sizeof(int4) * (size_t)max_groups * kCap));
+    FGA_TRY(B.get(&gcost, sizeof(unsigned) * max_groups));
   }
   for (int k = 0; k < npairs; ++k) {
     PairDev& pd = pds[k];
@@ -1469,78 +1807,195 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pd.n = (int)n[k];
     pd.m = (int)m[k];
     pd.n_nodes = nodes ? noff[k + 1] - noff[k] : 0;
-    pd.witems = dwitems ? dwitems + (size_t)goff[k] * kCap : nullptr;
+    pd.witems = nullptr;
     pd.gcost = nullptr;
-    pd.n_groups = goff[k + 1] - goff[k];
+    pd.n_groups = 0;
     pd.n_witems = 0;
   }
   FGA_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * doff[npairs], s));
   FGA_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned) * 2, s));
   std::vector<int2> items;
   if (grouped) {
-    // one iteration with one wave per group measures every group's cost; the
-    // rigid states are restored afterwards
     std::vector<RigidState> saved(npairs);
     FGA_HIP(hipMemcpyAsync(saved.data(), st, sizeof(RigidState) * npairs, hipMemcpyDeviceToHost, s));
-    std::vector<int4> wi((size_t)goff[npairs] * kCap);
-    std::vector<std::pair<double, int2>> blocks;
-    for (int k = 0; k < npairs; ++k) {
-      for (int g = 0; g < (int)groups[k].size(); ++g)
-        wi[(size_t)goff[k] * kCap + g] = make_int4(groups[k][g].x, groups[k][g].y, 1 << 8, goff[k] + g);
-      pds[k].n_witems = (int)groups[k].size();
-      pds[k].gcost = gcost;
-      const int nb = (pds[k].n_witems + kBlock / kWave - 1) / (kBlock / kWave);
-      pds[k].n_items = nb;
-      for (int b = 0; b < nb; ++b) items.push_back(make_int2(k, b));
-    }
-    FGA_HIP(hipMemcpyAsync(dwitems, wi.data(), sizeof(int4) * wi.size(), hipMemcpyHostToDevice, s));
-    FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
-    FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
-    FGA_HIP(hipMemsetAsync(gcost, 0, sizeof(unsigned) * goff[npairs], s));
-    int rb = 1;
-    for (int k = 0; k < npairs; ++k) rb = std::max(rb, reduce_blocks(pds[k].n_items));
-    FGA_TRY(launch_batch_iteration<T>(dpairs, npairs, rb, ditems, (int)items.size(), queue,
-                                      std::min((int)items.size(), cus * 8), c, s, true, true));
-    std::vector<unsigned> cost(goff[npairs]);
-    FGA_HIP(hipMemcpyAsync(cost.data(), gcost, sizeof(unsigned) * cost.size(), hipMemcpyDeviceToHost, s));
-    FGA_HIP(hipMemcpyAsync(st, saved.data(), sizeof(RigidState) * npairs, hipMemcpyHostToDevice, s));
     FGA_HIP(hipStreamSynchronize(s));
-    // wave items: heavy groups split over parts; blocks of four items of one
-    // pair, queued heaviest first
-    std::vector<double> cs(cost.begin(), cost.end());
-    double total = 0.0;
-    for (double v : cs) total += v;
-    std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
-    const double target = std::max(2.0 * cs[cs.size() / 2], total / 8192.0);
-    items.clear();
-    for (int k = 0; k < npairs; ++k) {
-      std::vector<std::pair<double, int4>> w;
-      for (int g = 0; g < (int)groups[k].size(); ++g) {
-        const unsigned cg = cost[goff[k] + g];
-        int nr = 1;
-        while (2 * nr <= kCap && cg > target * nr) nr *= 2;
-        for (int r = 0; r < nr; ++r)
-          w.push_back({(double)cg / nr, make_int4(groups[k][g].x, groups[k][g].y, r | nr << 8, goff[k] + g)});
+    auto restore = [&]() -> fga_status {
+      FGA_HIP(hipMemcpyAsync(st, saved.data(), sizeof(RigidState) * npairs, hipMemcpyHostToDevice, s));
+      FGA_HIP(hipStreamSynchronize(s));
+      return FGA_OK;
+    };
+    auto upload = [&]() -> fga_status {
+      FGA_HIP(hipMemcpyAsync(dpairs, pds.data(), sizeof(PairDev) * npairs, hipMemcpyHostToDevice, s));
+      FGA_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+      return FGA_OK;
+    };
+    auto launch = [&]() -> fga_status {
+      int rb = 1;
+      for (int k = 0; k < npairs; ++k) rb = std::max(rb, reduce_blocks(pds[k].n_items));
+      return launch_batch_iteration<T>(dpairs, npairs, rb, ditems, (int)items.size(), queue,
+                                       std::min((int)items.size(), cus * 8), c, s, true, true);
+    };
+    // one iteration with one wave per group measures every group's cost for
+    // the tau option fi; the rigid states are restored afterwards
+    std::map<int, std::vector<unsigned>> costs;  // key 16 * tree set + fi
+    int cur_set = 0;
+    auto use_set = [&](int ti) {
+      cur_set = ti;
+      for (int k = 0; k < npairs; ++k) {
+        pds[k].nodes = tsets[ti].nodes + tsets[ti].off[k];
+        pds[k].n_nodes = tsets[ti].off[k + 1] - tsets[ti].off[k];
       }
-      std::stable_sort(w.begin(), w.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+    };
+    auto measure = [&](int fi) -> fga_status {
+      const auto& g = gtab[fi];
+      const auto& go = gofs[fi];
+      std::vector<int4> wi((size_t)go[npairs]);
+      items.clear();
+      for (int k = 0; k < npairs; ++k) {
+        for (int q = 0; q < (int)g[k].size(); ++q)
+          wi[(size_t)go[k] + q] = make_int4(g[k][q].x, g[k][q].y, 1 << 8, go[k] + q);
+        pds[k].witems = dwitems + go[k];
+        pds[k].n_groups = (int)g[k].size();
+        pds[k].n_witems = (int)g[k].size();
+        pds[k].gcost = gcost;
+        const int nb = (pds[k].n_witems + kBlock / kWave - 1) / (kBlock / kWave);
+        pds[k].n_items = nb;
+        for (int b = 0; b < nb; ++b) items.push_back(make_int2(k, b));
+      }
+      FGA_HIP(hipMemcpyAsync(dwitems, wi.data(), sizeof(int4) * wi.size(), hipMemcpyHostToDevice, s));
+      FGA_TRY(upload());
+      FGA_HIP(hipMemsetAsync(gcost, 0, sizeof(unsigned) * go[npairs], s));
+      FGA_TRY(launch());
+      auto& cv = costs[16 * cur_set + fi];
+      cv.assign(go[npairs], 0u);
+      FGA_HIP(hipMemcpyAsync(cv.data(), gcost, sizeof(unsigned) * cv.size(), hipMemcpyDeviceToHost, s));
+      return restore();
+    };
+    // wave items for (fi, cap): heavy groups split over parts; blocks of four
+    // items of one pair, queued heaviest first
+    auto build = [&](int fi, int cap) -> fga_status {
+      const auto& g = gtab[fi];
+      const auto& go = gofs[fi];
+      const auto& cost = costs[16 * cur_set + fi];
+      std::vector<double> cs(cost.begin(), cost.end());
+      double total = 0.0;
+      for (double v : cs) total += v;
+      std::nth_element(cs.begin(), cs.begin() + cs.size() / 2, cs.end());
+      const double target = std::max(2.0 * cs[cs.size() / 2], total / 8192.0);
+      std::vector<int4> wi((size_t)go[npairs] * kCap);
+      std::vector<std::pair<double, int2>> blocks;
+      items.clear();
+      size_t base = 0;
+      for (int k = 0; k < npairs; ++k) {
+        std::vector<std::pair<double, int4>> w;
+        for (int q = 0; q < (int)g[k].size(); ++q) {
+          const unsigned cg = cost[go[k] + q];
+          int nr = 1;
+          while (2 * nr <= cap && cg > target * nr) nr *= 2;
+          for (int r = 0; r < nr; ++r)
+            w.push_back({(double)cg / nr, make_int4(g[k][q].x, g[k][q].y, r | nr << 8, go[k] + q)});
+        }
+        std::stable_sort(w.begin(), w.end(), [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+          return x.first > y.first;
+        });
+        for (size_t e = 0; e < w.size(); ++e) wi[base + e] = w[e].second;
+        pds[k].witems = dwitems + base;
+        base += w.size();
+        pds[k].n_groups = (int)g[k].size();
+        pds[k].n_witems = (int)w.size();
+        pds[k].gcost = nullptr;
+        const int nb = (pds[k].n_witems + kBlock / kWave - 1) / (kBlock / kWave);
+        pds[k].n_items = nb;
+        for (int b = 0; b < nb; ++b) {
+          double bc = 0.0;
+          for (int e = 4 * b; e < std::min((int)w.size(), 4 * b + 4); ++e) bc += w[e].first;
+          blocks.push_back({bc, make_int2(k, b)});
+        }
+      }
+      std::stable_sort(blocks.begin(), blocks.end(), [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
         return x.first > y.first;
       });
-      for (size_t e = 0; e < w.size(); ++e) wi[(size_t)goff[k] * kCap + e] = w[e].second;
-      pds[k].n_witems = (int)w.size();
-      pds[k].gcost = nullptr;
-      const int nb = (pds[k].n_witems + kBlock / kWave - 1) / (kBlock / kWave);
-      pds[k].n_items = nb;
-      for (int b = 0; b < nb; ++b) {
-        double bc = 0.0;
-        for (int e = 4 * b; e < std::min((int)w.size(), 4 * b + 4); ++e) bc += w[e].first;
-        blocks.push_back({bc, make_int2(k, b)});
-      }
+      for (auto& b : blocks) items.push_back(b.second);
+      FGA_HIP(hipMemcpyAsync(dwitems, wi.data(), sizeof(int4) * base, hipMemcpyHostToDevice, s));
+      return upload();
+    };
+    int best_fi = fis[0], best_cap = caps[0], best_set = 0;
+    if (btuned && leaves[0] != tsets[0].leaf) {  // cached leaf size differs from the one built
+      FGA_TRY(build_set(leaves[0]));
+      best_set = 1;
     }
-    std::stable_sort(blocks.begin(), blocks.end(), [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) {
-      return x.first > y.first;
-    });
-    for (auto& b : blocks) items.push_back(b.second);
-    FGA_HIP(hipMemcpyAsync(dwitems, wi.data(), sizeof(int4) * wi.size(), hipMemcpyHostToDevice, s));
+    use_set(best_set);
+    if (!btuned) {
+      // every (fi, cap) timed as the faster of two iterations on the batch itself
+      hipEvent_t e0, e1;
+      FGA_HIP(hipEventCreate(&e0));
+      FGA_HIP(hipEventCreate(&e1));
+      float best_ms = 1e30f;
+      fga_status ts = FGA_OK;
+      for (int fi : fis) {
+        if ((ts = measure(fi)) != FGA_OK) break;
+        for (int cap : caps) {
+          if ((ts = build(fi, cap)) != FGA_OK) break;
+          float ms = 1e30f;
+          for (int r = 0; r < 2 && ts == FGA_OK; ++r) {
+            float one = 0.f;
+            if (hipEventRecord(e0, s) != hipSuccess) ts = FGA_E_DEVICE;
+            if (ts == FGA_OK) ts = launch();
+            if (ts == FGA_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&one, e0, e1) != hipSuccess))
+              ts = FGA_E_DEVICE;
+            ms = std::min(ms, one);
+          }
+          if (ts == FGA_OK) ts = restore();
+          if (ts != FGA_OK) break;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_fi = fi;
+            best_cap = cap;
+          }
+        }
+        if (ts != FGA_OK) break;
+      }
+      // then the other leaf sizes with the best (fi, cap): trees of every pair
+      // built again, costs measured on them, and the same timing
+      for (size_t li = 1; li < leaves.size() && ts == FGA_OK; ++li) {
+        if ((ts = build_set(leaves[li])) != FGA_OK) break;
+        use_set((int)tsets.size() - 1);
+        if ((ts = measure(best_fi)) != FGA_OK || (ts = build(best_fi, best_cap)) != FGA_OK) break;
+        float ms = 1e30f;
+        for (int r = 0; r < 2 && ts == FGA_OK; ++r) {
+          float one = 0.f;
+          if (hipEventRecord(e0, s) != hipSuccess) ts = FGA_E_DEVICE;
+          if (ts == FGA_OK) ts = launch();
+          if (ts == FGA_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                               hipEventElapsedTime(&one, e0, e1) != hipSuccess))
+            ts = FGA_E_DEVICE;
+          ms = std::min(ms, one);
+        }
+        if (ts == FGA_OK) ts = restore();
+        if (ts == FGA_OK && ms < best_ms) {
+          best_ms = ms;
+          best_set = (int)tsets.size() - 1;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (ts != FGA_OK) {
+        set_error("tuning the batched group walk failed");
+        return ts;
+      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[bkey] = tsets[best_set].leaf << 16 | best_fi << 8 | best_cap;
+      tune_save_locked();
+    }
+    use_set(best_set);
+    nodes = tsets[best_set].nodes;
+    noff = tsets[best_set].off;
+    if (!costs.count(16 * best_set + best_fi)) FGA_TRY(measure(best_fi));
+    FGA_TRY(build(best_fi, best_cap));
+    B.tuned_leaf = tsets[best_set].leaf;
+    B.tuned_fi = best_fi;
+    B.tuned_cap = best_cap;
   } else {
     std::vector<int> order(npairs);
     for (int k = 0; k < npairs; ++k) order[k] = k;
@@ -1592,6 +2047,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
       reps[k].interactions = hs[k].interactions;
       reps[k].ms_total = ms;
       reps[k].traversal = grouped ? kWave : nodes ? 1 : 0;
+      reps[k].leaf_size = !nodes ? 0 : grouped ? B.tuned_leaf : std::max(1, p.leaf_size);
     }
     if ((hs[k].flags & 2) && result == FGA_OK) {
       set_error("pair %d: Barnes-Hut group walk: traversal stack overflow (forces incomplete)", k);
@@ -1626,6 +2082,10 @@ extern "C" fga_status fga_register_batch(int npairs, const void* const* X, const
     set_error("particle velocities are not supported in batched registration");
     return FGA_E_UNSUPPORTED;
   }
+  if (p->group_width == 128) {
+    set_error("the batched group walk holds 64 particles per wave (group_width 0, 1 or 64)");
+    return FGA_E_UNSUPPORTED;
+  }
   for (int k = 0; k < npairs; ++k) {
     FGA_TRY(check_device_ptr(X[k], "X[k]"));
     FGA_TRY(check_device_ptr(Y[k], "Y[k]"));
@@ -1634,4 +2094,47 @@ extern "C" fga_status fga_register_batch(int npairs, const void* const* X, const
   return p->precision == FGA_PREC_FP64
              ? batch_impl<double>(npairs, X, n, Y, m, dt, *p, R, t, reps, s)
              : batch_impl<float>(npairs, X, n, Y, m, dt, *p, R, t, reps, s);
+}
+
+extern "C" fga_status fga_register_sequence(int nframes, const void* const* frames,
+                                            const int64_t* sizes, fga_dtype dt, const fga_params* p,
+                                            double* R_rel, double* t_rel, double* R_abs,
+                                            double* t_abs, fga_report* reps, void* stream) {
+  if (nframes < 2) {
+    set_error("a sequence needs at least 2 frames (got %d)", nframes);
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_ptr(frames, "frames"));
+  FGA_TRY(check_ptr(sizes, "sizes"));
+  FGA_TRY(check_ptr(R_rel, "R_rel"));
+  FGA_TRY(check_ptr(t_rel, "t_rel"));
+  // pair k registers frame k + 1 (template) to frame k (reference); every
+  // frame but the last is a reference once, so its tree is built once
+  const int np = nframes - 1;
+  FGA_TRY(fga_register_batch(np, frames, sizes, frames + 1, sizes + 1, dt, p, R_rel, t_rel, reps,
+                             stream));
+  if (R_abs && t_abs) {
+    // T_0 = [I | 0]; T_{k+1} = T_k o T_rel(k): frame k+1's points in frame 0
+    for (int e = 0; e < 9; ++e) R_abs[e] = (e % 4 == 0) ? 1.0 : 0.0;
+    for (int a = 0; a < 3; ++a) t_abs[a] = 0.0;
+    for (int k = 0; k < np; ++k) {
+      const double* Rk = R_abs + 9 * k;
+      const double* tk = t_abs + 3 * k;
+      const double* Rr = R_rel + 9 * k;
+      const double* tr = t_rel + 3 * k;
+      double* Rn = R_abs + 9 * (k + 1);
+      double* tn = t_abs + 3 * (k + 1);
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+          double v = 0.0;
+          for (int l = 0; l < 3; ++l) v += Rk[3 * i + l] * Rr[3 * l + j];
+          Rn[3 * i + j] = v;
+        }
+        double v = tk[i];
+        for (int l = 0; l < 3; ++l) v += Rk[3 * i + l] * tr[l];
+        tn[i] = v;
+      }
+    }
+  }
+  return FGA_OK;
 }

@@ -83,7 +83,7 @@ struct RigidState {
   int m;          // template particles
   int flags;      // bit 0: degenerate Kabsch (rank(C) < 2) seen; bit 1: traversal stack overflow
   int max_iter;
-  int pad_;
+  int dims;       // 3, or 2 for planar point sets (z = const): the rigid step is then the 2 x 2 Kabsch
   float fR[9], fmu[3], fA[9], fb[3];  // FP32 copies read by the FP32 force kernels
 };
 
@@ -175,6 +175,8 @@ struct PairDev {
 struct CloudIn {
   const void* p;  // n x 3 row-major device array (dtype of the call)
   int64_t n;
+  const int64_t* lm = nullptr;  // host: indices of its landmark points (RBF masses)
+  int n_lm = 0;
 };
 struct PrepOut {
   void* X;          // packed reference vec4 (n_x)
@@ -184,10 +186,14 @@ struct PrepOut {
 struct NormInfo {   // host copy of the Appendix A normalisation
   double xbar[3], ybar[3], l, r, a, b;
 };
+// dims = 2: the clouds are planar point sets embedded at z = 0 (NIV on the
+// planar lattice with disc areas; 2 x 2 Kabsch steps)
 fga_status prep_pairs(int npairs, const CloudIn* X, const CloudIn* Y, fga_dtype dt,
-                      const fga_params& p, PrepOut* out, NormInfo* info, hipStream_t s);
-fga_status masses_only(const void* pts, fga_dtype dt, int64_t n, const fga_params& p, int norm,
-                       void* out, hipStream_t s);
+                      const fga_params& p, PrepOut* out, NormInfo* info, hipStream_t s,
+                      int dims = 3);
+fga_status masses_only(const void* pts, fga_dtype dt, int64_t n, const int64_t* lm, int n_lm,
+                       const fga_params& p, int norm, void* out, hipStream_t s);
+constexpr int kMaxLandmarkPairs = 64;  // landmark correspondences per registration
 
 // tree.hip: Morton codes, LDS radix sort, octree build
 struct TreeSeg {       // one reference cloud in a concatenated packed array
@@ -232,6 +238,17 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
                           hipStream_t s);
 template <typename T>
 fga_status pack_points(const void* X, const void* mX, int64_t n, void* out, hipStream_t s);
+// iter.hip: Plummer energy (fga_energy), direct and through the per-particle walk
+template <typename T>
+fga_status energy_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, const fga_params& p, double* E_host, hipStream_t s);
+template <typename T>
+fga_status energy_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
+                          const void* Xs, double theta, const fga_params& p, const void* mY,
+                          double* E_host, long long* interactions, hipStream_t s);
+// iter.hip: planar point sets (n x 2) to z = 0 embedded n x 3 and back
+fga_status embed_planar(const void* in, int64_t n, bool f64, void* out, hipStream_t s);
+fga_status take_planar(const void* in, int64_t n, bool f64, void* out, hipStream_t s);
 
 // iter.hip: one iteration as two launches (pose, forces, ODE and per-block
 // moments; then the ordered moment sum and the Kabsch step)

@@ -102,6 +102,18 @@ __device__ inline double rsqrt3_mass<double>(double m, double r2) {
   return m * r * (r * r);
 }
 
+// m / sqrt(r2): one term of the Plummer potential (the energy diagnostic).
+template <typename T>
+__device__ inline T rsqrt1_mass(T m, T r2);
+template <>
+__device__ inline float rsqrt1_mass<float>(float m, float r2) {
+  return m * __builtin_amdgcn_rsqf(r2);
+}
+template <>
+__device__ inline double rsqrt1_mass<double>(double m, double r2) {
+  return m * rsqrt_f64(r2);
+}
+
 
 // ------------------------------------------------------------- Barnes-Hut
 // Wavefront-cooperative traversal with per-lane decisions. Lanes are template
@@ -132,15 +144,20 @@ struct StackEntry {
   unsigned long long mask;
 };
 
-// One exact term of Eq. (GAForce) (per unit G and template mass).
-template <typename T>
+// One exact term of Eq. (GAForce) (per unit G and template mass); with POT
+// the Plummer potential term m / sqrt(r^2 + eps^2), added to ax alone.
+template <typename T, bool POT = false>
 __device__ inline void accum_point(const vec4_t<T>& x, T yx, T yy, T yz, T eps2, T& ax, T& ay,
                                    T& az) {
   const T ex = x.x - yx, ey = x.y - yy, ez = x.z - yz;
-  const T s = rsqrt3_mass<T>(x.w, ex * ex + ey * ey + ez * ez + eps2);
-  ax += ex * s;
-  ay += ey * s;
-  az += ez * s;
+  if constexpr (POT) {
+    ax += rsqrt1_mass<T>(x.w, ex * ex + ey * ey + ez * ez + eps2);
+  } else {
+    const T s = rsqrt3_mass<T>(x.w, ex * ex + ey * ey + ez * ez + eps2);
+    ax += ex * s;
+    ay += ey * s;
+    az += ez * s;
+  }
 }
 
 // Lanes per particle in the traversal. Each particle is held by S lanes
@@ -155,7 +172,9 @@ template <> struct SlotMask<2> { static constexpr unsigned long long v = 0x55555
 template <> struct SlotMask<4> { static constexpr unsigned long long v = 0x1111111111111111ull; };
 template <> struct SlotMask<8> { static constexpr unsigned long long v = 0x0101010101010101ull; };
 
-template <typename T, int S>
+// With POT the traversal makes the same decisions and sums the Plummer
+// potential instead (node term M / sqrt(r^2 + eps^2), into ax).
+template <typename T, int S, bool POT = false>
 __device__ inline void bh_accum(const BHWide* __restrict__ nodes,
                                 const vec4_t<T>* __restrict__ X, int j0, int j1, float theta2,
                                 T eps2, bool active, T yx, T yy, T yz, T& ax, T& ay, T& az,
@@ -195,11 +214,16 @@ __device__ inline void bh_accum(const BHWide* __restrict__ nodes,
             (sizeof(T) == 4 && leaf && nd.first == nd.last) || l2 < theta2 * (float)r2;
         {  // the node's term, kept only where this lane takes it and this range owns it
           const bool own = on && take && nd.first >= j0;
-          const T s = rsqrt3_mass<T>((T)nd.cm.w, r2 + eps2);
-          const T sk = own ? s : (T)0;
-          bx += dx * sk;
-          by += dy * sk;
-          bz += dz * sk;
+          if constexpr (POT) {
+            const T s = rsqrt1_mass<T>((T)nd.cm.w, r2 + eps2);
+            bx += own ? s : (T)0;
+          } else {
+            const T s = rsqrt3_mass<T>((T)nd.cm.w, r2 + eps2);
+            const T sk = own ? s : (T)0;
+            bx += dx * sk;
+            by += dy * sk;
+            bz += dz * sk;
+          }
           count += own ? 1u : 0u;
         }
         const bool exact = leaf || twig;
@@ -211,7 +235,7 @@ __device__ inline void bh_accum(const BHWide* __restrict__ nodes,
             const bool go = t < np;
             if (__ballot(go) == 0ull) break;
             if (go) {
-              accum_point<T>(X[p0 + t], yx, yy, yz, eps2, bx, by, bz);
+              accum_point<T, POT>(X[p0 + t], yx, yy, yz, eps2, bx, by, bz);
               ++count;
             }
           }

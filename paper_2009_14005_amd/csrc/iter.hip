@@ -553,6 +553,87 @@ __global__ __launch_bounds__(kBlock) void k_forces_bh(const T* Y, const int* yor
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(count, c);
 }
 
+// ------------------------------------------------------ Plummer energy
+// E = -G sum_i m_Y,i sum_j m_X,j / sqrt(|y_i - x_j|^2 + eps^2), the energy
+// whose negative gradient is Eq. (GAForce) (a convergence diagnostic).
+// Direct: per (template tile, reference range) the partial potentials, summed
+// per particle in FP64 in range order (tiles of 64 terms in the data's
+// precision); BH: the per-particle walk of Alg. 2 with the potential terms.
+// Both end in one FP64 partial per block and an ordered final sum.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy_direct(const T* Y, int m, const vec4_t<T>* X,
+                                                          int n, int jrn, T eps2, double* part) {
+  const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+  const int jr = blockIdx.y;
+  const bool valid = i < m;
+  const int ii = valid ? i : m - 1;
+  const T yx = Y[3 * ii], yy = Y[3 * ii + 1], yz = Y[3 * ii + 2];
+  int j0, j1;
+  jrange(n, jrn, jr, j0, j1);
+  double acc = 0.0;
+  for (int j = j0; j < j1; j += 64) {
+    const int je = min(j + 64, j1);
+    T t = 0;
+    for (int q = j; q < je; ++q) {
+      const vec4_t<T> x = X[q];
+      const T dx = x.x - yx, dy = x.y - yy, dz = x.z - yz;
+      t += rsqrt1_mass<T>(x.w, dx * dx + dy * dy + dz * dz + eps2);
+    }
+    acc += (double)t;
+  }
+  if (valid) part[(size_t)jr * m + i] = acc;
+}
+
+// One FP64 partial per block: sum over its particles of m_Y,i * potential_i.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy_rows(const double* part, int m, int jrn,
+                                                        const T* mY, double* rows) {
+  __shared__ double lds[kBlock / kWave];
+  const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+  double v[1] = {0.0};
+  if (i < m) {
+    for (int r = 0; r < jrn; ++r) v[0] += part[(size_t)r * m + i];
+    v[0] *= mY ? (double)mY[i] : 1.0;
+  }
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) rows[blockIdx.x] = v[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_energy_bh(const T* Y, const int* yorder, int m,
+                                                      const BHWide* nodes, const vec4_t<T>* Xs,
+                                                      float theta2, T eps2, const T* mY,
+                                                      double* rows, unsigned long long* count) {
+  __shared__ StackEntry stk[(kBlock / kWave) * kStack];
+  __shared__ double lds[kBlock / kWave];
+  const int k = blockIdx.x * kBlock + (int)threadIdx.x;
+  const bool valid = k < m;
+  const int i = valid ? yorder[k] : 0;
+  const T yx = Y[3 * i], yy = Y[3 * i + 1], yz = Y[3 * i + 2];
+  T pot = 0, unused_y = 0, unused_z = 0;
+  unsigned cnt = 0;
+  bh_accum<T, 1, true>(nodes, Xs, 0, 0x7fffffff, theta2, eps2, valid, yx, yy, yz, pot, unused_y,
+                       unused_z, cnt, stk + (threadIdx.x / kWave) * kStack);
+  double v[1] = {valid ? (double)pot * (mY ? (double)mY[i] : 1.0) : 0.0};
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) rows[blockIdx.x] = v[0];
+  unsigned long long c = cnt;
+  for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(count, c);
+}
+
+// E = -G sum of the block partials, in block order (one block).
+__global__ __launch_bounds__(kBlock) void k_energy_final(const double* rows, int nrows, double G,
+                                                         double* E) {
+  __shared__ double lds[kBlock / kWave];
+  double v[1] = {0.0};
+  // each thread sums a contiguous run of rows, then the block adds the runs
+  const int per = (nrows + kBlock - 1) / kBlock;
+  for (int r = (int)threadIdx.x * per; r < min(nrows, ((int)threadIdx.x + 1) * per); ++r) v[0] += rows[r];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) *E = -G * v[0];
+}
+
 // Group traversal for fga_forces: every wave takes 64 K consecutive template
 // particles of the Morton order yorder and writes F_i = G m_Y,i acc_i.
 template <int K, bool KAHAN>
@@ -711,6 +792,103 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
   return FGA_OK;
 }
 
+template <typename T>
+fga_status energy_direct(const void* Y, int64_t m, const void* X, int64_t n, const void* mX,
+                         const void* mY, const fga_params& p, double* E_host, hipStream_t s) {
+  const int jrn = direct_ranges(m, n);
+  const int nb = (int)((m + kBlock - 1) / kBlock);
+  const size_t x4 = ((sizeof(vec4_t<T>) * (size_t)n + 255) / 256) * 256;
+  const size_t pb = ((sizeof(double) * (size_t)m * jrn + 255) / 256) * 256;
+  char* buf = nullptr;
+  FGA_TRY(pool_get(&buf, x4 + pb + sizeof(double) * (nb + 1), s));
+  vec4_t<T>* X4 = (vec4_t<T>*)buf;
+  double* part = (double*)(buf + x4);
+  double* rows = (double*)(buf + x4 + pb);
+  k_pack4<T><<<(int)((n + 255) / 256), 256, 0, s>>>((const T*)X, (const T*)mX, n, X4);
+  k_energy_direct<T><<<dim3((unsigned)nb, (unsigned)jrn), kBlock, 0, s>>>((const T*)Y, (int)m, X4, (int)n, jrn,
+                                                                          (T)(p.eps * p.eps), part);
+  k_energy_rows<T><<<nb, kBlock, 0, s>>>(part, (int)m, jrn, (const T*)mY, rows);
+  k_energy_final<<<1, kBlock, 0, s>>>(rows, nb, p.G, rows + nb);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(E_host, rows + nb, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  pool_free(buf, s);
+  if (e != hipSuccess) {
+    set_error("energy kernels failed: %s", hipGetErrorString(e));
+    return FGA_E_DEVICE;
+  }
+  return FGA_OK;
+}
+
+template <typename T>
+fga_status energy_bh_tree(const void* Y, int64_t m, const int* yorder, const BHWide* nodes,
+                          const void* Xs, double theta, const fga_params& p, const void* mY,
+                          double* E_host, long long* interactions, hipStream_t s) {
+  const int nb = (int)((m + kBlock - 1) / kBlock);
+  char* buf = nullptr;
+  FGA_TRY(pool_get(&buf, sizeof(double) * (nb + 1) + sizeof(unsigned long long), s));
+  double* rows = (double*)buf;
+  unsigned long long* cnt = (unsigned long long*)(buf + sizeof(double) * (nb + 1));
+  hipError_t e = hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
+  k_energy_bh<T><<<nb, kBlock, 0, s>>>((const T*)Y, yorder, (int)m, nodes, (const vec4_t<T>*)Xs,
+                                       (float)(theta * theta), (T)(p.eps * p.eps), (const T*)mY,
+                                       rows, cnt);
+  k_energy_final<<<1, kBlock, 0, s>>>(rows, nb, p.G, rows + nb);
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(E_host, rows + nb, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  pool_free(buf, s);
+  if (e != hipSuccess) {
+    set_error("BH energy kernel failed: %s", hipGetErrorString(e));
+    return FGA_E_DEVICE;
+  }
+  if (interactions) *interactions = (long long)h;
+  return FGA_OK;
+}
+
+// Planar point sets (n x 2) embedded at z = 0 (n x 3), and back.
+template <typename T>
+__global__ void k_embed_planar(const T* in, int64_t n, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    out[3 * i] = in[2 * i];
+    out[3 * i + 1] = in[2 * i + 1];
+    out[3 * i + 2] = (T)0;
+  }
+}
+template <typename T>
+__global__ void k_take_planar(const T* in, int64_t n, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    out[2 * i] = in[3 * i];
+    out[2 * i + 1] = in[3 * i + 1];
+  }
+}
+fga_status embed_planar(const void* in, int64_t n, bool f64, void* out, hipStream_t s) {
+  if (f64) k_embed_planar<double><<<(int)((n + 255) / 256), 256, 0, s>>>((const double*)in, n, (double*)out);
+  else k_embed_planar<float><<<(int)((n + 255) / 256), 256, 0, s>>>((const float*)in, n, (float*)out);
+  FGA_HIP(hipGetLastError());
+  return FGA_OK;
+}
+fga_status take_planar(const void* in, int64_t n, bool f64, void* out, hipStream_t s) {
+  if (f64) k_take_planar<double><<<(int)((n + 255) / 256), 256, 0, s>>>((const double*)in, n, (double*)out);
+  else k_take_planar<float><<<(int)((n + 255) / 256), 256, 0, s>>>((const float*)in, n, (float*)out);
+  FGA_HIP(hipGetLastError());
+  return FGA_OK;
+}
+
+template fga_status energy_direct<float>(const void*, int64_t, const void*, int64_t, const void*,
+                                         const void*, const fga_params&, double*, hipStream_t);
+template fga_status energy_direct<double>(const void*, int64_t, const void*, int64_t, const void*,
+                                          const void*, const fga_params&, double*, hipStream_t);
+template fga_status energy_bh_tree<float>(const void*, int64_t, const int*, const BHWide*, const void*,
+                                          double, const fga_params&, const void*, double*, long long*,
+                                          hipStream_t);
+template fga_status energy_bh_tree<double>(const void*, int64_t, const int*, const BHWide*, const void*,
+                                           double, const fga_params&, const void*, double*, long long*,
+                                           hipStream_t);
 template fga_status forces_direct<float>(const void*, int64_t, const void*, int64_t, const void*,
                                          const void*, const fga_params&, void*, hipStream_t);
 template fga_status forces_direct<double>(const void*, int64_t, const void*, int64_t, const void*,

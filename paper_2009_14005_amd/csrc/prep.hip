@@ -1,7 +1,8 @@
 // Step a0 of the hot path, once per registration: the Appendix A
-// normalisation (Eqs. A.1-A.3) and the smooth-particle masses (Eq.
-// Normalized_IntrinsicVol, Eq. FinalSPM with B = 1), then packing of both
-// clouds into the vec4 layouts the force kernels read.
+// normalisation (Eqs. A.1-A.3) and the smooth-particle masses S = N o B
+// (Eq. Normalized_IntrinsicVol for N, Eq. RBF_function for B when landmark
+// correspondences are given, B = 1 otherwise; Eq. FinalSPM), then packing
+// of both clouds into the vec4 layouts the force kernels read.
 //
 // All reductions are two-stage and deterministic: one block per chunk of
 // kChunk points writes partial values, and one block per cloud (or pair)
@@ -30,6 +31,7 @@ struct Seg {                // one cloud
   int is_y;                 // 1 = template
   int64_t out_off;          // offset of its packed output (points)
   int hist_off;             // offset of its histogram (cells)
+  int lm_off, lm_cnt;       // its landmark anchors (RBF masses); none: B = 1
 };
 struct Chunk {
   int seg;
@@ -39,9 +41,9 @@ struct Chunk {
 struct SegStats {           // device, per cloud
   double mean[3];
   double lo[3], hi[3];      // box of the normalised coordinates
-  double niv_sum;
+  double niv_sum;           // sum of the unnormalised masses N o B
   unsigned nonfinite;
-  int pad_;
+  unsigned lm_singular;     // the RBF collocation system had no usable pivot
 };
 struct PairStats {          // device, per pair
   double l, r;              // Eq. (A.2)
@@ -50,6 +52,9 @@ struct PairStats {          // device, per pair
 
 struct PrepConsts {
   double a, b;
+  int dims;                 // 3, or 2 for planar clouds embedded at z = 0
+  double rbf_inv_s2;        // 1 / sigma^2 of the RBF kernel Phi(s) = exp(-s^2 / sigma^2)
+  double rbf_beta;          // B at a landmark anchor
   double v_ball;            // volume of one point's ball, Eq. (Normalized_IntrinsicVol)
   int rho;
   int mass_mode;
@@ -101,6 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_mean(const Seg* segs, const doub
       for (int k = 0; k < 4; ++k) s[k] += part[(sg.chunk0 + c) * kPart + k];
     for (int k = 0; k < 3; ++k) ss[blockIdx.x].mean[k] = s[k] / (double)sg.n;
     ss[blockIdx.x].nonfinite = (unsigned)s[3];
+    ss[blockIdx.x].lm_singular = 0u;  // set by the collocation solve, if the cloud has landmarks
   }
 }
 
@@ -153,6 +159,78 @@ __device__ inline void normalised(const Seg& sg, const SegStats& st, const PairS
   if (c.identity) return;
   const PairStats& pr = ps[sg.pair];
   for (int a = 0; a < 3; ++a) x[a] = norm1(x[a], st.mean[a], pr.l, pr.r, c.a, c.b);
+}
+
+// ------------------------------------------------------- RBF landmarks
+// Eq. (RBF_function): B(p) = 1 + sum_c lambda_c exp(-|p - a_c|^2 / sigma^2)
+// over the cloud's anchors a_c (x, y, z, lambda_c), B = 1 without anchors.
+__device__ inline double rbf_B(const double* x, const double4* lmk, const Seg& sg, double inv_s2) {
+  double b = 1.0;
+  for (int k = 0; k < sg.lm_cnt; ++k) {
+    const double4 a = lmk[sg.lm_off + k];
+    const double dx = x[0] - a.x, dy = x[1] - a.y, dz = x[2] - a.z;
+    b += a.w * exp(-(dx * dx + dy * dy + dz * dz) * inv_s2);
+  }
+  return b;
+}
+
+// The collocation system of one cloud (one block per cloud): anchors in the
+// frame the masses are computed in, Phi_cc' lambda = (beta - 1) 1, solved by
+// Gaussian elimination without pivoting (Phi is symmetric positive definite
+// for distinct anchors); one thread per row, the back substitution on one.
+constexpr int kMaxLandmarks = 64;
+template <typename Tin>
+__global__ __launch_bounds__(kMaxLandmarks) void k_rbf_solve(const Seg* segs, const SegStats* ss,
+                                                             const PairStats* ps, PrepConsts c,
+                                                             const int64_t* lm_idx, double4* lmk,
+                                                             SegStats* ss_out) {
+  __shared__ double A[kMaxLandmarks][kMaxLandmarks + 1];
+  __shared__ double rhs[kMaxLandmarks], anc[kMaxLandmarks][3];
+  __shared__ int bad;
+  const Seg sg = segs[blockIdx.x];
+  const int m = sg.lm_cnt, i = (int)threadIdx.x;
+  if (m == 0) return;
+  const SegStats st = ss[blockIdx.x];
+  if (i == 0) bad = 0;
+  if (i < m) {
+    double x[3];
+    normalised<Tin>(sg, st, ps, c, lm_idx[sg.lm_off + i], x);
+    for (int a = 0; a < 3; ++a) anc[i][a] = x[a];
+  }
+  __syncthreads();
+  if (i < m) {
+    for (int j = 0; j < m; ++j) {
+      const double dx = anc[i][0] - anc[j][0], dy = anc[i][1] - anc[j][1], dz = anc[i][2] - anc[j][2];
+      A[i][j] = exp(-(dx * dx + dy * dy + dz * dz) * c.rbf_inv_s2);
+    }
+    rhs[i] = c.rbf_beta - 1.0;
+  }
+  for (int k = 0; k < m; ++k) {
+    __syncthreads();
+    const double piv = A[k][k];
+    if (!(piv > 1e-12)) {  // coincident or nearly coincident anchors
+      if (i == 0) bad = 1;
+      break;
+    }
+    if (i > k && i < m) {
+      const double f = A[i][k] / piv;
+      for (int j = k; j < m; ++j) A[i][j] -= f * A[k][j];
+      rhs[i] -= f * rhs[k];
+    }
+  }
+  __syncthreads();
+  if (i == 0) {
+    if (!bad) {
+      for (int k = m - 1; k >= 0; --k) {
+        double v = rhs[k];
+        for (int j = k + 1; j < m; ++j) v -= A[k][j] * rhs[j];
+        rhs[k] = v / A[k][k];
+      }
+    }
+    ss_out[blockIdx.x].lm_singular = bad ? 1u : 0u;
+  }
+  __syncthreads();
+  if (i < m) lmk[sg.lm_off + i] = make_double4(anc[i][0], anc[i][1], anc[i][2], bad ? 0.0 : rhs[i]);
 }
 
 // ---------------------------------------------------------------- stage C
@@ -209,9 +287,9 @@ __device__ inline int niv_cell(const double* x, const SegStats& st, int rho) {
   return idx;
 }
 
-__device__ inline double niv_vcell(const SegStats& st, int rho) {
+__device__ inline double niv_vcell(const SegStats& st, int rho, int dims) {
   double v = 1.0;
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < dims; ++a) {
     double ext = st.hi[a] - st.lo[a];
     if (!(ext > 0.0)) ext = 1.0;
     v *= ext / (double)rho;
@@ -259,21 +337,29 @@ __global__ __launch_bounds__(kBlock) void k_hist(const Seg* segs, const Chunk* c
 }
 
 // ---------------------------------------------------------------- stage E
+// Unnormalised mass N o B of a point (N = 1 in uniform mode).
+__device__ inline double spm_value(const double* x, const Seg& sg, const SegStats& st,
+                                   const PrepConsts& c, const unsigned* hist, const double4* lmk) {
+  const double nv = c.mass_mode == FGA_MASS_UNIFORM
+                        ? 1.0
+                        : niv_value(hist[sg.hist_off + niv_cell(x, st, c.rho)], niv_vcell(st, c.rho, c.dims), c.v_ball);
+  return sg.lm_cnt ? nv * rbf_B(x, lmk, sg, c.rbf_inv_s2) : nv;
+}
+
 template <typename Tin>
 __global__ __launch_bounds__(kBlock) void k_nivsum(const Seg* segs, const Chunk* chunks,
                                                    const SegStats* ss, const PairStats* ps,
                                                    PrepConsts c, const unsigned* hist,
-                                                   double* part) {
+                                                   const double4* lmk, double* part) {
   __shared__ double lds[kBlock / kWave];
   const Chunk ch = chunks[blockIdx.x];
   const Seg sg = segs[ch.seg];
   const SegStats st = ss[ch.seg];
-  const double vc = niv_vcell(st, c.rho);
   double v[1] = {0.0};
   for (int64_t k = threadIdx.x; k < ch.count; k += kBlock) {
     double x[3];
     normalised<Tin>(sg, st, ps, c, ch.start + k, x);
-    v[0] += niv_value(hist[sg.hist_off + niv_cell(x, st, c.rho)], vc, c.v_ball);
+    v[0] += spm_value(x, sg, st, c, hist, lmk);
   }
   block_sum<1>(v, lds);
   if (threadIdx.x == 0) part[blockIdx.x * kPart] = v[0];
@@ -295,19 +381,19 @@ template <typename Tin, typename T>
 __global__ __launch_bounds__(kBlock) void k_pack(const Seg* segs, const Chunk* chunks,
                                                  const SegStats* ss, const PairStats* ps,
                                                  PrepConsts c, const unsigned* hist,
-                                                 vec4_t<T>* outX, vec4_t<T>* outQ) {
+                                                 const double4* lmk, vec4_t<T>* outX,
+                                                 vec4_t<T>* outQ) {
   const Chunk ch = chunks[blockIdx.x];
   const Seg sg = segs[ch.seg];
   const SegStats st = ss[ch.seg];
-  const double vc = niv_vcell(st, c.rho);
   for (int64_t k = threadIdx.x; k < ch.count; k += kBlock) {
     double x[3];
     normalised<Tin>(sg, st, ps, c, ch.start + k, x);
     double w;
-    if (c.mass_mode == FGA_MASS_UNIFORM) {
+    if (c.mass_mode == FGA_MASS_UNIFORM && sg.lm_cnt == 0) {
       w = sg.is_y ? 1.0 : 1.0 / (double)sg.n;
     } else {
-      const double nv = niv_value(hist[sg.hist_off + niv_cell(x, st, c.rho)], vc, c.v_ball);
+      const double nv = spm_value(x, sg, st, c, hist, lmk);
       w = sg.is_y ? nv / (st.niv_sum / (double)sg.n) : nv / st.niv_sum;
     }
     if (!sg.is_y) {
@@ -344,31 +430,30 @@ __global__ __launch_bounds__(kBlock) void k_s0(const Seg* segs, const Chunk* chu
 }
 
 __global__ void k_fin_state(const Seg* segs, const double* part, const PairStats* ps,
-                            RigidState* st, double tol, int max_iter, double rank_tol) {
+                            RigidState* st, double tol, int max_iter, double rank_tol, int dims) {
   if (threadIdx.x != 0) return;
   const int p = blockIdx.x;
   const Seg sg = segs[2 * p + 1];
   double S0[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = 0; k < sg.nchunk; ++k)
     for (int e = 0; e < 9; ++e) S0[e] += part[(sg.chunk0 + k) * kPart + e];
-  rigid_init(st[p], S0, ps[p].mu0, (int)sg.n, tol, max_iter, rank_tol);
+  rigid_init(st[p], S0, ps[p].mu0, (int)sg.n, tol, max_iter, rank_tol, dims);
 }
 
-// masses_only: write the normalised NIV values of one raw cloud.
+// masses_only: write the normalised masses N o B of one raw cloud.
 template <typename Tin>
 __global__ __launch_bounds__(kBlock) void k_write_masses(const Seg* segs, const Chunk* chunks,
                                                          const SegStats* ss, PrepConsts c,
-                                                         const unsigned* hist, int norm,
-                                                         Tin* out) {
+                                                         const unsigned* hist, const double4* lmk,
+                                                         int norm, Tin* out) {
   const Chunk ch = chunks[blockIdx.x];
   const Seg sg = segs[ch.seg];
   const SegStats st = ss[ch.seg];
-  const double vc = niv_vcell(st, c.rho);
   const double scale = norm == 0 ? st.niv_sum : st.niv_sum / (double)sg.n;
   for (int64_t k = threadIdx.x; k < ch.count; k += kBlock) {
     double x[3];
     load3<Tin>(sg.p, ch.start + k, x);
-    out[ch.start + k] = (Tin)(niv_value(hist[sg.hist_off + niv_cell(x, st, c.rho)], vc, c.v_ball) / scale);
+    out[ch.start + k] = (Tin)(spm_value(x, sg, st, c, hist, lmk) / scale);
   }
 }
 
@@ -376,11 +461,16 @@ __global__ __launch_bounds__(kBlock) void k_write_masses(const Seg* segs, const 
 struct Plan {
   std::vector<Seg> segs;
   std::vector<Chunk> chunks;
+  std::vector<int64_t> lm;  // landmark point indices of every cloud, in cloud order
   int hist_cells = 0;
 };
 
-void plan_add(Plan& pl, const void* p, int64_t n, int pair, int is_y, int64_t out_off, int rho) {
+void plan_add(Plan& pl, const void* p, int64_t n, int pair, int is_y, int64_t out_off, int rho,
+              const int64_t* lm = nullptr, int n_lm = 0) {
   Seg s;
+  s.lm_off = (int)pl.lm.size();
+  s.lm_cnt = lm ? n_lm : 0;
+  for (int k = 0; k < s.lm_cnt; ++k) pl.lm.push_back(lm[k]);
   s.p = p;
   s.n = n;
   s.chunk0 = (int)pl.chunks.size();
@@ -409,12 +499,16 @@ struct DevBufs {
   }
 };
 
-PrepConsts make_consts(const fga_params& p, int identity) {
+PrepConsts make_consts(const fga_params& p, int identity, int dims = 3) {
   PrepConsts c;
   c.a = p.a;
   c.b = p.b;
+  c.dims = dims;
+  c.rbf_inv_s2 = 1.0 / (p.rbf_sigma * p.rbf_sigma);
+  c.rbf_beta = p.rbf_weight;
   const double rb = (p.b - p.a) / (2.0 * (double)p.max_depth * (double)p.rho);
-  c.v_ball = 4.0 / 3.0 * M_PI * (rb * rb * rb);
+  // one point's ball (Eq. Normalized_IntrinsicVol): a disc in D = 2
+  c.v_ball = dims == 2 ? M_PI * (rb * rb) : 4.0 / 3.0 * M_PI * (rb * rb * rb);
   c.rho = p.rho;
   c.mass_mode = p.mass_mode;
   c.identity = identity;
@@ -426,12 +520,12 @@ PrepConsts make_consts(const fga_params& p, int identity) {
 
 template <typename Tin, typename T>
 fga_status prep_impl(int npairs, const CloudIn* X, const CloudIn* Y, const fga_params& p,
-                     PrepOut* out, NormInfo* info, hipStream_t s) {
+                     PrepOut* out, NormInfo* info, hipStream_t s, int dims) {
   Plan pl;
   int64_t xoff = 0, yoff = 0;
   for (int k = 0; k < npairs; ++k) {
-    plan_add(pl, X[k].p, X[k].n, k, 0, xoff, p.rho);
-    plan_add(pl, Y[k].p, Y[k].n, k, 1, yoff, p.rho);
+    plan_add(pl, X[k].p, X[k].n, k, 0, xoff, p.rho, X[k].lm, X[k].n_lm);
+    plan_add(pl, Y[k].p, Y[k].n, k, 1, yoff, p.rho, Y[k].lm, Y[k].n_lm);
     xoff += X[k].n;
     yoff += Y[k].n;
   }
@@ -442,7 +536,9 @@ fga_status prep_impl(int npairs, const CloudIn* X, const CloudIn* Y, const fga_p
   size_t o_ss = o_part + sizeof(double) * kPart * nch;
   size_t o_ps = o_ss + sizeof(SegStats) * nseg;
   size_t o_hist = o_ps + sizeof(PairStats) * npairs;
-  size_t total = o_hist + sizeof(unsigned) * pl.hist_cells;
+  size_t o_lmi = (o_hist + sizeof(unsigned) * pl.hist_cells + 255) & ~(size_t)255;
+  size_t o_lmk = o_lmi + sizeof(int64_t) * pl.lm.size();
+  size_t total = o_lmk + sizeof(double4) * pl.lm.size();
   DevBufs buf;
   buf.s = s;
   FGA_TRY(pool_get(&buf.mem, total, s));
@@ -453,28 +549,34 @@ fga_status prep_impl(int npairs, const CloudIn* X, const CloudIn* Y, const fga_p
   SegStats* ss = (SegStats*)(base + o_ss);
   PairStats* ps = (PairStats*)(base + o_ps);
   unsigned* hist = (unsigned*)(base + o_hist);
+  int64_t* lmi = (int64_t*)(base + o_lmi);
+  double4* lmk = (double4*)(base + o_lmk);
+  const bool any_lm = !pl.lm.empty();
+  if (any_lm)
+    FGA_HIP(hipMemcpyAsync(lmi, pl.lm.data(), sizeof(int64_t) * pl.lm.size(), hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(dseg, pl.segs.data(), sizeof(Seg) * nseg, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(dch, pl.chunks.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemsetAsync(hist, 0, sizeof(unsigned) * pl.hist_cells, s));
-  const PrepConsts c = make_consts(p, 0);
+  const PrepConsts c = make_consts(p, 0, dims);
   k_sum<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, part);
   k_fin_mean<<<nseg, 64, 0, s>>>(dseg, part, ss);
   k_minmax<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, part);
   k_fin_lr<<<npairs, 64, 0, s>>>(dseg, part, ps, c);
   k_box<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, part);
   k_fin_box<<<nseg, 64, 0, s>>>(dseg, part, ss);
-  if (p.mass_mode == FGA_MASS_NIV) {
-    k_hist<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, hist);
-    k_nivsum<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, hist, part);
+  if (any_lm) k_rbf_solve<Tin><<<nseg, kMaxLandmarks, 0, s>>>(dseg, ss, ps, c, lmi, lmk, ss);
+  if (p.mass_mode == FGA_MASS_NIV) k_hist<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, hist);
+  if (p.mass_mode == FGA_MASS_NIV || any_lm) {
+    k_nivsum<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, hist, lmk, part);
     k_fin_niv<<<nseg, 64, 0, s>>>(dseg, part, ss);
   }
-  k_pack<Tin, T><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, hist, (vec4_t<T>*)out->X,
+  k_pack<Tin, T><<<nch, kBlock, 0, s>>>(dseg, dch, ss, ps, c, hist, lmk, (vec4_t<T>*)out->X,
                                         (vec4_t<T>*)out->Q);
   k_s0<T><<<nch, kBlock, 0, s>>>(dseg, dch, (const vec4_t<T>*)out->Q, part);
   // FP32 template coordinates carry ~1e-7 relative rounding, so a collinear
   // template shows singular-value ratios of that order
   const double rank_tol = sizeof(T) == 8 ? 1e-12 : 1e-6;
-  k_fin_state<<<npairs, 64, 0, s>>>(dseg, part, ps, out->st, p.tol, p.max_iter, rank_tol);
+  k_fin_state<<<npairs, 64, 0, s>>>(dseg, part, ps, out->st, p.tol, p.max_iter, rank_tol, dims);
   FGA_HIP(hipGetLastError());
   // host copies for validation and de-normalisation (one sync per prep)
   std::vector<SegStats> hss(nseg);
@@ -489,6 +591,11 @@ fga_status prep_impl(int npairs, const CloudIn* X, const CloudIn* Y, const fga_p
       set_error("pair %d: %u non-finite reference and %u non-finite template values", k,
                 sx.nonfinite, sy.nonfinite);
       return FGA_E_NONFINITE;
+    }
+    if (sx.lm_singular || sy.lm_singular) {
+      set_error("pair %d: landmark points (nearly) coincide within the RBF width: the "
+                "collocation system is singular", k);
+      return FGA_E_DEGENERATE;
     }
     if (!(hps[k].r > hps[k].l)) {
       set_error("pair %d: both clouds have zero extent (r == l in Eq. A.2)", k);
@@ -507,16 +614,18 @@ fga_status prep_impl(int npairs, const CloudIn* X, const CloudIn* Y, const fga_p
 }
 
 template <typename Tin>
-fga_status masses_impl(const void* pts, int64_t n, const fga_params& p, int norm, void* out,
-                       hipStream_t s) {
+fga_status masses_impl(const void* pts, int64_t n, const int64_t* lm, int n_lm,
+                       const fga_params& p, int norm, void* out, hipStream_t s) {
   Plan pl;
-  plan_add(pl, pts, n, 0, 0, 0, p.rho);
+  plan_add(pl, pts, n, 0, 0, 0, p.rho, lm, n_lm);
   const int nseg = 1, nch = (int)pl.chunks.size();
   size_t o_seg = 0, o_ch = sizeof(Seg), o_part = o_ch + sizeof(Chunk) * nch;
   o_part = (o_part + 255) & ~(size_t)255;
   size_t o_ss = o_part + sizeof(double) * kPart * nch;
   size_t o_hist = o_ss + sizeof(SegStats);
-  size_t total = o_hist + sizeof(unsigned) * pl.hist_cells;
+  size_t o_lmi = (o_hist + sizeof(unsigned) * pl.hist_cells + 255) & ~(size_t)255;
+  size_t o_lmk = o_lmi + sizeof(int64_t) * pl.lm.size();
+  size_t total = o_lmk + sizeof(double4) * pl.lm.size();
   DevBufs buf;
   buf.s = s;
   FGA_TRY(pool_get(&buf.mem, total, s));
@@ -526,6 +635,10 @@ fga_status masses_impl(const void* pts, int64_t n, const fga_params& p, int norm
   double* part = (double*)(base + o_part);
   SegStats* ss = (SegStats*)(base + o_ss);
   unsigned* hist = (unsigned*)(base + o_hist);
+  int64_t* lmi = (int64_t*)(base + o_lmi);
+  double4* lmk = (double4*)(base + o_lmk);
+  if (!pl.lm.empty())
+    FGA_HIP(hipMemcpyAsync(lmi, pl.lm.data(), sizeof(int64_t) * pl.lm.size(), hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(dseg, pl.segs.data(), sizeof(Seg), hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(dch, pl.chunks.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemsetAsync(hist, 0, sizeof(unsigned) * pl.hist_cells, s));
@@ -535,10 +648,11 @@ fga_status masses_impl(const void* pts, int64_t n, const fga_params& p, int norm
   k_fin_mean<<<nseg, 64, 0, s>>>(dseg, part, ss);
   k_box<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, nullptr, c, part);
   k_fin_box<<<nseg, 64, 0, s>>>(dseg, part, ss);
-  k_hist<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, nullptr, c, hist);
-  k_nivsum<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, nullptr, c, hist, part);
+  if (!pl.lm.empty()) k_rbf_solve<Tin><<<nseg, kMaxLandmarks, 0, s>>>(dseg, ss, nullptr, c, lmi, lmk, ss);
+  if (p.mass_mode == FGA_MASS_NIV) k_hist<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, nullptr, c, hist);
+  k_nivsum<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, nullptr, c, hist, lmk, part);
   k_fin_niv<<<nseg, 64, 0, s>>>(dseg, part, ss);
-  k_write_masses<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, c, hist, norm, (Tin*)out);
+  k_write_masses<Tin><<<nch, kBlock, 0, s>>>(dseg, dch, ss, c, hist, lmk, norm, (Tin*)out);
   FGA_HIP(hipGetLastError());
   SegStats hss;
   FGA_HIP(hipMemcpyAsync(&hss, ss, sizeof(SegStats), hipMemcpyDeviceToHost, s));
@@ -547,25 +661,29 @@ fga_status masses_impl(const void* pts, int64_t n, const fga_params& p, int norm
     set_error("%u non-finite coordinates", hss.nonfinite);
     return FGA_E_NONFINITE;
   }
+  if (hss.lm_singular) {
+    set_error("landmark points (nearly) coincide within the RBF width: the collocation system is singular");
+    return FGA_E_DEGENERATE;
+  }
   return FGA_OK;
 }
 
 }  // namespace
 
 fga_status prep_pairs(int npairs, const CloudIn* X, const CloudIn* Y, fga_dtype dt,
-                      const fga_params& p, PrepOut* out, NormInfo* info, hipStream_t s) {
+                      const fga_params& p, PrepOut* out, NormInfo* info, hipStream_t s, int dims) {
   const bool f64 = p.precision == FGA_PREC_FP64;
   if (dt == FGA_F32)
-    return f64 ? prep_impl<float, double>(npairs, X, Y, p, out, info, s)
-               : prep_impl<float, float>(npairs, X, Y, p, out, info, s);
-  return f64 ? prep_impl<double, double>(npairs, X, Y, p, out, info, s)
-             : prep_impl<double, float>(npairs, X, Y, p, out, info, s);
+    return f64 ? prep_impl<float, double>(npairs, X, Y, p, out, info, s, dims)
+               : prep_impl<float, float>(npairs, X, Y, p, out, info, s, dims);
+  return f64 ? prep_impl<double, double>(npairs, X, Y, p, out, info, s, dims)
+             : prep_impl<double, float>(npairs, X, Y, p, out, info, s, dims);
 }
 
-fga_status masses_only(const void* pts, fga_dtype dt, int64_t n, const fga_params& p, int norm,
-                       void* out, hipStream_t s) {
-  return dt == FGA_F32 ? masses_impl<float>(pts, n, p, norm, out, s)
-                       : masses_impl<double>(pts, n, p, norm, out, s);
+fga_status masses_only(const void* pts, fga_dtype dt, int64_t n, const int64_t* lm, int n_lm,
+                       const fga_params& p, int norm, void* out, hipStream_t s) {
+  return dt == FGA_F32 ? masses_impl<float>(pts, n, lm, n_lm, p, norm, out, s)
+                       : masses_impl<double>(pts, n, lm, n_lm, p, norm, out, s);
 }
 
 }  // namespace fga

@@ -139,6 +139,22 @@ FGA_HD int kabsch3(const double* C, double* R, double rank_tol = 1e-13, double* 
   return 0;
 }
 
+// Eq. (R_Kabsch) in D = 2 for a planar C (its third row and column zero):
+// the rotation about z that maximises tr(R^T C), angle atan2(C10 - C01, C00 + C11).
+// Returns 1 (R = I) when both terms vanish (no rotation is determined).
+FGA_HD int kabsch2(const double* C, double* R, double rank_tol) {
+  const double sn = C[3] - C[1], cs = C[0] + C[4];
+  const double h = sqrt(sn * sn + cs * cs);
+  const double scale = fabs(C[0]) + fabs(C[1]) + fabs(C[3]) + fabs(C[4]);
+  for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  if (!(h > rank_tol * scale)) return 1;
+  R[0] = cs / h;
+  R[1] = -sn / h;
+  R[3] = sn / h;
+  R[4] = cs / h;
+  return 0;
+}
+
 // One Alg. 2 rigid step from the reduced displacement moments.
 //   mom[0..2]  = sum_i d_i
 //   mom[3..11] = P = sum_i d_i q_i^T (row-major, P[a][b] = sum d_a q_b)
@@ -154,7 +170,7 @@ FGA_HD void rigid_update(RigidState& s, const double* mom, double dt) {
   m3_mul(s.R, s.S0, RS0);
   for (int k = 0; k < 9; ++k) RS0[k] += mom[3 + k];
   m3_mul_bt(RS0, s.R, C);
-  if (kabsch3(C, Rs, s.rank_tol, s.Vw)) s.flags |= 1;
+  if (s.dims == 2 ? kabsch2(C, Rs, s.rank_tol) : kabsch3(C, Rs, s.rank_tol, s.Vw)) s.flags |= 1;
   double muD[3], ts[3], Rn[9], tn[3];
   for (int a = 0; a < 3; ++a) muD[a] = s.mu[a] + dbar[a];
   for (int a = 0; a < 3; ++a)
@@ -202,7 +218,7 @@ FGA_HD void rigid_update(RigidState& s, const double* mom, double dt) {
 
 // Initial state: T = [I | 0] (Alg. 2 initialisation), zero velocity.
 FGA_HD void rigid_init(RigidState& s, const double* S0, const double* mu0, int m, double tol,
-                       int max_iter, double rank_tol) {
+                       int max_iter, double rank_tol, int dims = 3) {
   for (int k = 0; k < 9; ++k) {
     s.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
     s.A[k] = 0.0;
@@ -228,7 +244,7 @@ FGA_HD void rigid_init(RigidState& s, const double* S0, const double* mu0, int m
   s.m = m;
   s.flags = 0;
   s.max_iter = max_iter;
-  s.pad_ = 0;
+  s.dims = dims;
 }
 
 }  // namespace fga

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "random_rotation", "mixture", "mixture_pair", "lidar_pair", "mesh_pair",
     "precision_pair", "batch_pairs", "batch_pair", "config_seed",
-    "BATCH_PAIRS", "uniform_grid_pair",
+    "BATCH_PAIRS", "uniform_grid_pair", "misaligned_pair", "lidar_sequence",
 ]
 
 BATCH_PAIRS = 256
@@ -70,14 +70,32 @@ def _pose_template(rng, ref_pts, max_deg, t_half, noise):
 
 def mixture_pair(seed: int = config_seed(0), n_comp: int = 8, per_comp: int = 128,
                  m: int = 900, max_deg: float = 30.0, t_half: float = 0.1,
-                 noise: float = 0.005):
+                 noise: float = 0.005, return_index: bool = False, min_deg: float = 0.0):
     """Reference: ``n_comp`` x ``per_comp`` mixture points. Template: an
-    ``m``-point subset without replacement, rotated, translated and noised."""
+    ``m``-point subset without replacement, rotated (angle U[min_deg,
+    max_deg]), translated and noised. With ``return_index`` the subset's
+    reference indices are returned too (template point i is a noisy copy of
+    reference point index[i]: the true correspondences)."""
     rng = np.random.default_rng(seed)
     X, _, _ = mixture(rng, n_comp, per_comp)
     idx = rng.choice(X.shape[0], size=m, replace=False)
-    Y, R_gt, t_gt = _pose_template(rng, X[idx], max_deg, t_half, noise)
-    return X, Y, R_gt, t_gt
+    if min_deg > 0.0:
+        Ry = _rotation_between(rng, min_deg, max_deg)
+        ty = rng.uniform(-t_half, t_half, size=3)
+        Y = X[idx] @ Ry.T + ty + noise * rng.normal(size=(m, 3))
+        R_gt, t_gt = Ry.T, -Ry.T @ ty
+    else:
+        Y, R_gt, t_gt = _pose_template(rng, X[idx], max_deg, t_half, noise)
+    return (X, Y, R_gt, t_gt, idx) if return_index else (X, Y, R_gt, t_gt)
+
+
+def _rotation_between(rng, min_deg, max_deg):
+    """Rotation about a uniform axis by an angle uniform in [min_deg, max_deg]."""
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    ang = np.deg2rad(rng.uniform(min_deg, max_deg))
+    K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * (K @ K)
 
 
 def uniform_grid_pair(seed: int, n_side: int = 8, max_deg: float = 30.0,
@@ -89,6 +107,25 @@ def uniform_grid_pair(seed: int, n_side: int = 8, max_deg: float = 30.0,
     X = X + rng.uniform(-0.2, 0.2, size=X.shape) / n_side
     Y, R_gt, t_gt = _pose_template(rng, X, max_deg, t_half, 0.0)
     return X, Y, R_gt, t_gt
+
+
+def misaligned_pair(seed: int, per_comp: int = 236, max_deg: float = 135.0):
+    """Full overlap under large misalignment (the robustness experiment's
+    third case): a noise-free 8-component mixture (1,888 points) and the same
+    points in shuffled order, rotated by Euler angles about x, y and z each
+    uniform in [0, max_deg] and translated U[-0.1, 0.1]^3. Returns X, Y,
+    R_gt, t_gt and the correspondences: Y[i] is the image of X[index[i]]."""
+    rng = np.random.default_rng([14010, seed])
+    X, _, _ = mixture(rng, 8, per_comp)
+    idx = rng.permutation(X.shape[0])
+    a = np.deg2rad(rng.uniform(0.0, max_deg, size=3))
+    Rx = np.array([[1, 0, 0], [0, np.cos(a[0]), -np.sin(a[0])], [0, np.sin(a[0]), np.cos(a[0])]])
+    Ry = np.array([[np.cos(a[1]), 0, np.sin(a[1])], [0, 1, 0], [-np.sin(a[1]), 0, np.cos(a[1])]])
+    Rz = np.array([[np.cos(a[2]), -np.sin(a[2]), 0], [np.sin(a[2]), np.cos(a[2]), 0], [0, 0, 1]])
+    Rt = Rz @ Ry @ Rx
+    tt = rng.uniform(-0.1, 0.1, size=3)
+    Y = X[idx] @ Rt.T + tt
+    return X, Y, Rt.T, -Rt.T @ tt, idx
 
 
 def precision_pair(seed: int = config_seed(3), per_comp: int = 16384):
@@ -217,6 +254,29 @@ def lidar_pair(seed: int = config_seed(1), beams: int = 64, azimuths: int = 1024
     X = _scan(rng, np.eye(3), np.zeros(3), boxes, cyls, beams, azimuths, height, range_noise)
     Y = _scan(rng, R2, t2, boxes, cyls, beams, azimuths, height, range_noise)
     return X, Y, R2, t2
+
+
+def lidar_sequence(frames: int = 32, seed: int = config_seed(5), step: float = 1.0,
+                   beams: int = 64, azimuths: int = 1024, height: float = 1.73,
+                   range_noise: float = 0.02):
+    """A drive through one seeded scene (the LiDAR pair's scene recipe): the
+    sensor advances ``step`` metres per frame along its heading, which turns by
+    U[-3, 3] degrees per frame, and takes one ring scan per frame. Returns the
+    scans (each in its own sensor-base frame) and the world poses (R_k, t_k)
+    of every frame; frame k+1 registered to frame k has the ground truth
+    R_k^T R_{k+1}, R_k^T (t_{k+1} - t_k)."""
+    rng = np.random.default_rng(seed)
+    boxes, cyls = _scene(rng)
+    yaw = rng.uniform(-np.pi, np.pi)
+    pos = np.zeros(3)
+    scans, poses = [], []
+    for k in range(frames):
+        R = np.array([[np.cos(yaw), -np.sin(yaw), 0.0], [np.sin(yaw), np.cos(yaw), 0.0], [0, 0, 1.0]])
+        scans.append(_scan(rng, R, pos.copy(), boxes, cyls, beams, azimuths, height, range_noise))
+        poses.append((R, pos.copy()))
+        yaw += np.deg2rad(rng.uniform(-3.0, 3.0))
+        pos = pos + step * np.array([np.cos(yaw), np.sin(yaw), 0.0])
+    return scans, poses
 
 
 # ---------------------------------------------------------------- weighted mesh

@@ -8,7 +8,7 @@ record stores a SHA-256 of those FP32 inputs so that a reader can tell when
 the generators have changed since the record was written.
 
 Usage:  python tests/golden/make_oracle_runs.py [section ...]
-Sections: lidar, mesh, precision, batch (default: all). Existing records of
+Sections: lidar, mesh, precision, batch, odometry (default: all). Existing records of
 other sections are kept. The whole run takes about an hour on 8 cores.
 """
 import hashlib
@@ -106,7 +106,18 @@ def main(sections):
                     print(key, pidx + 1, flush=True)
             db[key] = recs
             save(db)
+    if "odometry" in sections:
+        # the first 8 frame pairs of the 32-frame drive: frame k+1 registered to frame k
+        scans, _ = synth.lidar_sequence(9)
+        recs = []
+        for k in range(8):
+            rec = run(scans[k], scans[k + 1], theta=0.5, max_iter=100)
+            rec["input_sha256"] = input_hash(scans[k], scans[k + 1])
+            recs.append(rec)
+            print("odometry", k, rec["seconds"], flush=True)
+        db["odometry_lidar_pairs_bh0.5"] = recs
+        save(db)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch"])
+    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch", "odometry"])

@@ -154,3 +154,49 @@ def test_noalloc_direct_rejects_oversized_scratch_on_the_host():
     assert st == 1 and b"scratch" in L.fga_last_error()
     st = L.fga_forces_direct_noalloc(fake, 0, fake, 10, fake, None, fga.F32, ctypes.byref(p), fake, None)
     assert st == 1
+
+
+@pytest.mark.parametrize("idx,count,over,code", [
+    ([0, 1], 65, {}, 1),            # more than 64 landmarks
+    ([-1], 1, {}, 1),               # index below range
+    ([10], 1, {}, 1),               # index n (out of range)
+    ([0], 1, {"rbf_sigma": 0.0}, 1),
+    ([0], 1, {"rbf_weight": float("nan")}, 1),
+])
+def test_landmark_argument_validation(idx, count, over, code):
+    """Landmark checks run on the host before any device call (fake pointers)."""
+    L = fga.lib()
+    p = fga.default_params(**over)
+    fake = ctypes.c_void_p(0x1000)
+    arr = (ctypes.c_int64 * max(len(idx), count))(*idx)
+    st = L.fga_masses_landmarks(fake, fga.F32, 10, arr, count, ctypes.byref(p), 0, fake, None)
+    assert st == code, L.fga_last_error()
+    R = (ctypes.c_double * 9)()
+    t = (ctypes.c_double * 3)()
+    st = L.fga_register_landmarks(fake, 10, fake, 10, fga.F32, arr, arr, count, ctypes.byref(p),
+                                  R, t, None, None)
+    assert st == code, L.fga_last_error()
+
+
+def test_energy_planar_sequence_argument_validation():
+    """Host-side checks of the energy, planar and sequence entry points
+    (fake, never-dereferenced pointers)."""
+    L = fga.lib()
+    p = fga.default_params()
+    fake = ctypes.c_void_p(0x1000)
+    E = ctypes.c_double(0)
+    assert L.fga_energy(fake, 10, fake, 10, fake, None, fga.F32, -1.0, ctypes.byref(p),
+                        ctypes.byref(E), None, None) == 1
+    assert L.fga_energy(fake, 10, fake, 10, None, None, fga.F32, 0.0, ctypes.byref(p),
+                        ctypes.byref(E), None, None) == 1
+    assert L.fga_forces_2d(fake, 0, fake, 10, fake, None, fga.F32, 0.5, ctypes.byref(p), fake,
+                           None, None) == 1
+    R = (ctypes.c_double * 4)()
+    t = (ctypes.c_double * 2)()
+    assert L.fga_register_2d(fake, 10, None, 10, fga.F32, ctypes.byref(p), R, t, None, None) == 1
+    frames = (ctypes.c_void_p * 1)(0x1000)
+    sizes = (ctypes.c_int64 * 1)(10)
+    R9 = (ctypes.c_double * 9)()
+    t3 = (ctypes.c_double * 3)()
+    assert L.fga_register_sequence(1, frames, sizes, fga.F32, ctypes.byref(p), R9, t3, None, None,
+                                   None, None) == 1
