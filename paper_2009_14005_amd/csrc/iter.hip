@@ -284,8 +284,8 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
   }
   unsigned cnt = 0, entries = 0;
   const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
-      pd.nodes, pd.n_nodes, (const float4*)pd.X, pd.n, r, nr, R, c.ftheta2, c.feps2, valid, y,
-      acc, cnt, entries, g[wave]);
+      pd.nodes, pd.n_nodes, (const float4*)pd.X, pd.n, r, nr, R, pd.subboxes, c.ftheta2, c.feps2,
+      valid, y, acc, cnt, entries, g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
   if (pd.gcost && lane == 0 && gi >= 0) atomicAdd(&pd.gcost[gi], entries);
   bool owner[K];
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
                                                          const float4* Xs, int n_points,
                                                          float theta2, float eps2, const float* mY,
                                                          double G, float* F,
-                                                         unsigned long long* count) {
+                                                         unsigned long long* count, int nb) {
   __shared__ GroupLds g[kBlock / kWave];
   const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
   int idx[K];
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, 1, theta2, eps2, valid,
+  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, 1, nb, theta2, eps2, valid,
                                     y, acc, cnt, entries, g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -763,14 +763,15 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
       const float* Yf = (const float*)Y;
       const float4* X4 = (const float4*)Xs;
       const bool kahan = p.precision == FGA_PREC_FP32_KAHAN;
+      const int nb = group_boxes_of(p);
       if (K == 1 && kahan)
-        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
+        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
       else if (K == 1)
-        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
+        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
       else if (kahan)
-        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
+        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
       else
-        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt);
+        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
     }
   }
   if (K != 1 && K != 2) {

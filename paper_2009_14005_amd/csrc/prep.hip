@@ -97,13 +97,29 @@ __global__ __launch_bounds__(kBlock) void k_sum(const Seg* segs, const Chunk* ch
     for (int k = 0; k < 4; ++k) part[blockIdx.x * kPart + k] = v[k];
 }
 
-__global__ __launch_bounds__(kBlock) void k_fin_mean(const Seg* segs, const double* part,
-                                                     SegStats* ss) {
+// One wave combines a cloud's chunk partials: lane j takes chunks j, j + 64,
+// ..., then a butterfly over the lanes (a fixed order: deterministic).
+__device__ inline double wave_sum_d(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ inline double wave_min_d(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ inline double wave_max_d(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__global__ __launch_bounds__(kWave) void k_fin_mean(const Seg* segs, const double* part,
+                                                    SegStats* ss) {
   const Seg sg = segs[blockIdx.x];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = (int)threadIdx.x; c < sg.nchunk; c += kWave)
+    for (int k = 0; k < 4; ++k) s[k] += part[(sg.chunk0 + c) * kPart + k];
+  for (int k = 0; k < 4; ++k) s[k] = wave_sum_d(s[k]);
   if (threadIdx.x == 0) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = 0; c < sg.nchunk; ++c)
-      for (int k = 0; k < 4; ++k) s[k] += part[(sg.chunk0 + c) * kPart + k];
     for (int k = 0; k < 3; ++k) ss[blockIdx.x].mean[k] = s[k] / (double)sg.n;
     ss[blockIdx.x].nonfinite = (unsigned)s[3];
     ss[blockIdx.x].lm_singular = 0u;  // set by the collocation solve, if the cloud has landmarks
@@ -136,15 +152,18 @@ __global__ __launch_bounds__(kBlock) void k_minmax(const Seg* segs, const Chunk*
 }
 
 // Eq. (A.2): l and r over both clouds of a pair (segments 2p and 2p + 1).
-__global__ void k_fin_lr(const Seg* segs, const double* part, PairStats* ps, PrepConsts c) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kWave) void k_fin_lr(const Seg* segs, const double* part,
+                                                  PairStats* ps, PrepConsts c) {
   const int p = blockIdx.x;
   double l = INFINITY, r = -INFINITY;
   for (int s = 2 * p; s < 2 * p + 2; ++s)
-    for (int k = 0; k < segs[s].nchunk; ++k) {
+    for (int k = (int)threadIdx.x; k < segs[s].nchunk; k += kWave) {
       l = fmin(l, part[(segs[s].chunk0 + k) * kPart + 0]);
       r = fmax(r, part[(segs[s].chunk0 + k) * kPart + 1]);
     }
+  l = wave_min_d(l);
+  r = wave_max_d(r);
+  if (threadIdx.x != 0) return;
   ps[p].l = l;
   ps[p].r = r;
   // mean of the normalised template: Eq. (A.3) applied to a zero centred coordinate
@@ -259,17 +278,20 @@ __global__ __launch_bounds__(kBlock) void k_box(const Seg* segs, const Chunk* ch
     }
 }
 
-__global__ void k_fin_box(const Seg* segs, const double* part, SegStats* ss) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kWave) void k_fin_box(const Seg* segs, const double* part, SegStats* ss) {
   const Seg sg = segs[blockIdx.x];
   for (int a = 0; a < 3; ++a) {
     double mn = INFINITY, mx = -INFINITY;
-    for (int k = 0; k < sg.nchunk; ++k) {
+    for (int k = (int)threadIdx.x; k < sg.nchunk; k += kWave) {
       mn = fmin(mn, part[(sg.chunk0 + k) * kPart + a]);
       mx = fmax(mx, part[(sg.chunk0 + k) * kPart + 3 + a]);
     }
-    ss[blockIdx.x].lo[a] = mn;
-    ss[blockIdx.x].hi[a] = mx;
+    mn = wave_min_d(mn);
+    mx = wave_max_d(mx);
+    if (threadIdx.x == 0) {
+      ss[blockIdx.x].lo[a] = mn;
+      ss[blockIdx.x].hi[a] = mx;
+    }
   }
 }
 
@@ -365,12 +387,12 @@ __global__ __launch_bounds__(kBlock) void k_nivsum(const Seg* segs, const Chunk*
   if (threadIdx.x == 0) part[blockIdx.x * kPart] = v[0];
 }
 
-__global__ void k_fin_niv(const Seg* segs, const double* part, SegStats* ss) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kWave) void k_fin_niv(const Seg* segs, const double* part, SegStats* ss) {
   const Seg sg = segs[blockIdx.x];
   double s = 0.0;
-  for (int k = 0; k < sg.nchunk; ++k) s += part[(sg.chunk0 + k) * kPart];
-  ss[blockIdx.x].niv_sum = s;
+  for (int k = (int)threadIdx.x; k < sg.nchunk; k += kWave) s += part[(sg.chunk0 + k) * kPart];
+  s = wave_sum_d(s);
+  if (threadIdx.x == 0) ss[blockIdx.x].niv_sum = s;
 }
 
 // ---------------------------------------------------------------- stage F
@@ -429,14 +451,17 @@ __global__ __launch_bounds__(kBlock) void k_s0(const Seg* segs, const Chunk* chu
     for (int k = 0; k < 9; ++k) part[blockIdx.x * kPart + k] = v[k];
 }
 
-__global__ void k_fin_state(const Seg* segs, const double* part, const PairStats* ps,
-                            RigidState* st, double tol, int max_iter, double rank_tol, int dims) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kWave) void k_fin_state(const Seg* segs, const double* part,
+                                                     const PairStats* ps, RigidState* st,
+                                                     double tol, int max_iter, double rank_tol,
+                                                     int dims) {
   const int p = blockIdx.x;
   const Seg sg = segs[2 * p + 1];
   double S0[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < sg.nchunk; ++k)
+  for (int k = (int)threadIdx.x; k < sg.nchunk; k += kWave)
     for (int e = 0; e < 9; ++e) S0[e] += part[(sg.chunk0 + k) * kPart + e];
+  for (int e = 0; e < 9; ++e) S0[e] = wave_sum_d(S0[e]);
+  if (threadIdx.x != 0) return;
   rigid_init(st[p], S0, ps[p].mu0, (int)sg.n, tol, max_iter, rank_tol, dims);
 }
 

@@ -84,15 +84,22 @@ __global__ __launch_bounds__(kBlock) void k_box_part(const vec4_t<T>* X, const S
     }
 }
 
-__global__ void k_box_fin(const double* part, const int* seg_tile0, int nseg, SegBox* box) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
+// One wave per segment: lane j takes tiles j, j + 64, ... of the segment.
+__global__ __launch_bounds__(kWave) void k_box_fin(const double* part, const int* seg_tile0,
+                                                   int nseg, SegBox* box) {
+  const int s = blockIdx.x;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int t = seg_tile0[s]; t < seg_tile0[s + 1]; ++t)
+  for (int t = seg_tile0[s] + (int)threadIdx.x; t < seg_tile0[s + 1]; t += kWave)
     for (int a = 0; a < 3; ++a) {
       lo[a] = fmin(lo[a], part[6 * t + a]);
       hi[a] = fmax(hi[a], part[6 * t + 3 + a]);
     }
+  for (int o = kWave / 2; o > 0; o >>= 1)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fmin(lo[a], __shfl_xor(lo[a], o, kWave));
+      hi[a] = fmax(hi[a], __shfl_xor(hi[a], o, kWave));
+    }
+  if (threadIdx.x != 0) return;
   double d2 = 0.0;
   for (int a = 0; a < 3; ++a) {
     box[s].lo[a] = lo[a];
@@ -173,6 +180,49 @@ __global__ __launch_bounds__(1024) void k_scan_u32_1block(unsigned* v, int n) {
     const unsigned x = v[i];
     v[i] = run;
     run += x;
+  }
+}
+
+// Exclusive scan of n unsigned values in place over many blocks: each block
+// scans a tile of kHScanTile values (kHScanItems contiguous ones per thread) and
+// writes its total; one block scans the totals (k_scan_u32_1block); a third
+// launch adds each tile's offset. Three short launches instead of one block
+// walking the whole histogram (the radix sort's histograms have 256 entries
+// per tile of keys: 65,536 for a million points).
+constexpr int kHScanItems = 16;
+constexpr int kHScanTile = kBlock * kHScanItems;
+__global__ __launch_bounds__(kBlock) void k_scan_tile(unsigned* v, int n, unsigned* tot) {
+  __shared__ unsigned lds[kBlock / kWave];
+  const int base = blockIdx.x * kHScanTile + (int)threadIdx.x * kHScanItems;
+  unsigned x[kHScanItems];
+  unsigned s = 0;
+#pragma unroll
+  for (int k = 0; k < kHScanItems; ++k) {
+    x[k] = base + k < n ? v[base + k] : 0u;
+    s += x[k];
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  unsigned inc = s;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  unsigned run = inc - s;
+  for (int ww = 0; ww < w; ++ww) run += lds[ww];
+  if (threadIdx.x == kBlock - 1) tot[blockIdx.x] = run + s;
+#pragma unroll
+  for (int k = 0; k < kHScanItems; ++k) {
+    if (base + k < n) v[base + k] = run;
+    run += x[k];
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_scan_add(unsigned* v, int n, const unsigned* tot) {
+  const unsigned add = tot[blockIdx.x];
+  for (int k = 0; k < kHScanItems; ++k) {
+    const int i = blockIdx.x * kHScanTile + k * kBlock + (int)threadIdx.x;
+    if (i < n) v[i] += add;
   }
 }
 
@@ -469,32 +519,98 @@ __device__ inline void prune_mark(const u64* codes, const SegRange& s, int64_t a
   }
 }
 
+// Tree statistics (deepest level, leaves, internal nodes, overflow flag) of
+// one block, written to the block's own slot of part; k_stats_fin folds the
+// slots. Same-address atomics from every wave of a million-node build
+// serialise chip-wide at roughly 10 ns each, which cost over half a
+// millisecond per launch. Every thread of the block calls it.
+__device__ inline void block_stats(uint4* part, bool leaf, bool internal, int depth, bool over) {
+  __shared__ unsigned lds[4][kBlock / kWave];
+  const unsigned long long ml = __ballot(leaf), mi = __ballot(internal), mo = __ballot(over);
+  int d = depth;
+  for (int o = kWave / 2; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, kWave));
+  const int w = (int)threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    lds[0][w] = (unsigned)d;
+    lds[1][w] = (unsigned)__popcll(ml);
+    lds[2][w] = (unsigned)__popcll(mi);
+    lds[3][w] = mo ? 1u : 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    for (int k = 0; k < kBlock / kWave; ++k) {
+      r.x = max(r.x, lds[0][k]);
+      r.y += lds[1][k];
+      r.z += lds[2][k];
+      r.w |= lds[3][k];
+    }
+    part[blockIdx.x] = r;
+  }
+}
+
+// One block: stats[0] = max(stats[0], deepest), stats[1] += leaves,
+// stats[2] += internal nodes, stats[3] |= overflow, over the nb slots.
+__global__ __launch_bounds__(kBlock) void k_stats_fin(const uint4* part, int nb, unsigned* stats) {
+  __shared__ uint4 lds[kBlock / kWave];
+  uint4 r = make_uint4(0u, 0u, 0u, 0u);
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    const uint4 v = part[k];
+    r.x = max(r.x, v.x);
+    r.y += v.y;
+    r.z += v.z;
+    r.w |= v.w;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    r.x = max(r.x, (unsigned)__shfl_xor((int)r.x, o, kWave));
+    r.y += (unsigned)__shfl_xor((int)r.y, o, kWave);
+    r.z += (unsigned)__shfl_xor((int)r.z, o, kWave);
+    r.w |= (unsigned)__shfl_xor((int)r.w, o, kWave);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[threadIdx.x / kWave] = r;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < kBlock / kWave; ++k) {
+    r.x = max(r.x, lds[k].x);
+    r.y += lds[k].y;
+    r.z += lds[k].z;
+    r.w |= lds[k].w;
+  }
+  stats[0] = max(stats[0], r.x);
+  stats[1] += r.y;
+  stats[2] += r.z;
+  stats[3] |= r.w;
+}
+
 // Copies the kept nodes to their compacted preorder positions; skip pointers
 // and segment offsets map through the exclusive scan NI of the keep flags.
 __global__ __launch_bounds__(kBlock) void k_compact(const BHNode* in, const unsigned* keep,
                                                     const unsigned* NI, const int* node_off,
                                                     int nseg, unsigned total, BHNode* out,
-                                                    unsigned* stats) {
+                                                    uint4* part) {
   const unsigned i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= total || !keep[i]) return;
-  int lo = 0, hi = nseg - 1;  // segment of node i
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if ((unsigned)node_off[mid] <= i) lo = mid;
-    else hi = mid - 1;
+  bool is_leaf = false, is_int = false;
+  if (i < total && keep[i]) {
+    int lo = 0, hi = nseg - 1;  // segment of node i
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((unsigned)node_off[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const unsigned base = (unsigned)node_off[lo];
+    BHNode nd = in[i];
+    const unsigned skip_g = base + (unsigned)nd.skip;
+    const unsigned ni = NI[i];
+    nd.skip = (int)(NI[skip_g] - NI[base]);
+    if ((unsigned)nd.skip == ni - NI[base] + 1) {
+      is_leaf = true;
+      nd.l2 = fabsf(nd.l2);  // a leaf is walked point by point anyway: no twig flag
+    } else {
+      is_int = true;
+    }
+    out[ni] = nd;
   }
-  const unsigned base = (unsigned)node_off[lo];
-  BHNode nd = in[i];
-  const unsigned skip_g = base + (unsigned)nd.skip;
-  const unsigned ni = NI[i];
-  nd.skip = (int)(NI[skip_g] - NI[base]);
-  if ((unsigned)nd.skip == ni - NI[base] + 1) {
-    atomicAdd(&stats[1], 1u);
-    nd.l2 = fabsf(nd.l2);  // a leaf is walked point by point anyway: no twig flag
-  } else {
-    atomicAdd(&stats[2], 1u);
-  }
-  out[ni] = nd;
+  block_stats(part, is_leaf, is_int, 0, false);
 }
 
 // ------------------------------------------------------------ node emission
@@ -505,70 +621,74 @@ __global__ __launch_bounds__(kBlock) void k_emit(const vec4_t<T>* Xs, const u64*
                                                  const unsigned char* leaf0, const int* own_d,
                                                  const int* own_a, const int* own_b,
                                                  const unsigned* P, const D4* W, BHNode* nodes,
-                                                 unsigned cap, unsigned* stats, int L,
+                                                 unsigned cap, uint4* part, int L,
                                                  unsigned* keep) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
-  const int sg = find_seg(sr, nseg, k);
-  const double lroot = box[sg].lroot;
-  // node fields are local to the segment: point indices from its first sorted
-  // point, node indices from its root
-  const int s0 = (int)sr[sg].s0;
-  const int nbase = (int)P[s0];
-  const int d = own_d[k];
-  if (d >= 0) {  // branching cell owned by separator k
-    const int a = own_a[k], b = own_b[k];
-    const unsigned idx = P[a] + (unsigned)__popc(mask[a] & ((1u << d) - 1u));
-    const D4 s = W[b + 1] + D4{-W[a].m, -W[a].x, -W[a].y, -W[a].z};
-    BHNode nd;
-    nd.cm = make_float4((float)(s.x / s.m), (float)(s.y / s.m), (float)(s.z / s.m), (float)s.m);
-    nd.skip = (int)P[b + 1] - nbase;
-    nd.first = a - s0;
-    nd.last = b - s0;
-    const double l = ldexp(lroot, -d);
-    nd.l2 = (float)(l * l);
-    // twig: every point of the cell is its own child (all separators inside
-    // branch at depth d); flagged by the sign bit of l2. At most 8 points.
-    if (b - a < 8) {
-      bool twig = true;
-      for (int q = a; q < b && twig; ++q) twig = lcp_digits(codes[q], codes[q + 1]) == d;
-      if (twig) nd.l2 = -nd.l2;
-    }
-    if (idx >= cap) {  // more nodes than the array holds: reported, never written
-      atomicOr(&stats[3], 1u);
-    } else {
-      if (L > 1) prune_mark(codes, sr[sg], a, b, L, lroot, &nd, keep + idx);
-      nodes[idx] = nd;
-    }
-    atomicMax(&stats[0], (unsigned)d);
-    atomicAdd(&stats[2], 1u);
-  }
-  if (leaf0[k]) {  // leaf: run of identical codes starting at k
-    int64_t e = k;
-    while (e + 1 < sr[sg].s1 && !leaf0[e + 1]) ++e;
-    const unsigned idx = P[k] + (unsigned)__popc(mask[k]);
-    BHNode nd;
-    if (e == k) {  // singleton: the point itself
-      const vec4_t<T> p = Xs[k];
-      nd.cm = make_float4((float)p.x, (float)p.y, (float)p.z, (float)p.w);
-    } else {
-      const D4 s = W[e + 1] + D4{-W[k].m, -W[k].x, -W[k].y, -W[k].z};
+  bool is_int = false, is_leaf = false, over = false;
+  int dmax = 0;
+  if (k < n) {
+    const int sg = find_seg(sr, nseg, k);
+    const double lroot = box[sg].lroot;
+    // node fields are local to the segment: point indices from its first sorted
+    // point, node indices from its root
+    const int s0 = (int)sr[sg].s0;
+    const int nbase = (int)P[s0];
+    const int d = own_d[k];
+    if (d >= 0) {  // branching cell owned by separator k
+      const int a = own_a[k], b = own_b[k];
+      const unsigned idx = P[a] + (unsigned)__popc(mask[a] & ((1u << d) - 1u));
+      const D4 s = W[b + 1] + D4{-W[a].m, -W[a].x, -W[a].y, -W[a].z};
+      BHNode nd;
       nd.cm = make_float4((float)(s.x / s.m), (float)(s.y / s.m), (float)(s.z / s.m), (float)s.m);
-      atomicMax(&stats[0], (unsigned)kQBits);
+      nd.skip = (int)P[b + 1] - nbase;
+      nd.first = a - s0;
+      nd.last = b - s0;
+      const double l = ldexp(lroot, -d);
+      nd.l2 = (float)(l * l);
+      // twig: every point of the cell is its own child (all separators inside
+      // branch at depth d); flagged by the sign bit of l2. At most 8 points.
+      if (b - a < 8) {
+        bool twig = true;
+        for (int q = a; q < b && twig; ++q) twig = lcp_digits(codes[q], codes[q + 1]) == d;
+        if (twig) nd.l2 = -nd.l2;
+      }
+      if (idx >= cap) {  // more nodes than the array holds: reported, never written
+        over = true;
+      } else {
+        if (L > 1) prune_mark(codes, sr[sg], a, b, L, lroot, &nd, keep + idx);
+        nodes[idx] = nd;
+      }
+      dmax = max(dmax, d);
+      is_int = true;
     }
-    nd.skip = (int)idx + 1 - nbase;
-    nd.first = (int)k - s0;
-    nd.last = (int)e - s0;
-    const double l = ldexp(lroot, -kQBits);  // a leaf of several points is a depth-20 cell
-    nd.l2 = (float)(l * l);
-    if (idx >= cap) {
-      atomicOr(&stats[3], 1u);
-    } else {
-      if (L > 1) prune_mark(codes, sr[sg], k, e, L, lroot, &nd, keep + idx);
-      nodes[idx] = nd;
+    if (leaf0[k]) {  // leaf: run of identical codes starting at k
+      int64_t e = k;
+      while (e + 1 < sr[sg].s1 && !leaf0[e + 1]) ++e;
+      const unsigned idx = P[k] + (unsigned)__popc(mask[k]);
+      BHNode nd;
+      if (e == k) {  // singleton: the point itself
+        const vec4_t<T> p = Xs[k];
+        nd.cm = make_float4((float)p.x, (float)p.y, (float)p.z, (float)p.w);
+      } else {
+        const D4 s = W[e + 1] + D4{-W[k].m, -W[k].x, -W[k].y, -W[k].z};
+        nd.cm = make_float4((float)(s.x / s.m), (float)(s.y / s.m), (float)(s.z / s.m), (float)s.m);
+        dmax = kQBits;
+      }
+      nd.skip = (int)idx + 1 - nbase;
+      nd.first = (int)k - s0;
+      nd.last = (int)e - s0;
+      const double l = ldexp(lroot, -kQBits);  // a leaf of several points is a depth-20 cell
+      nd.l2 = (float)(l * l);
+      if (idx >= cap) {
+        over = true;
+      } else {
+        if (L > 1) prune_mark(codes, sr[sg], k, e, L, lroot, &nd, keep + idx);
+        nodes[idx] = nd;
+      }
+      is_leaf = true;
     }
-    atomicAdd(&stats[1], 1u);
   }
+  block_stats(part, is_leaf, is_int, dmax, over);
 }
 
 __global__ void k_seg_nodes(const SegRange* sr, int nseg, const unsigned* P, int* node_off) {
@@ -644,14 +764,19 @@ fga_status morton_sort(int nseg, const TreeSeg* segs, const vec4_t<T>* X, int64_
   FGA_TRY(sc.get(&v0, sizeof(unsigned) * ntot));
   FGA_TRY(sc.get(&v1, sizeof(unsigned) * ntot));
   FGA_TRY(sc.get(&hist, sizeof(unsigned) * hist_entries));
+  const int scan_blocks = (hist_entries + kHScanTile - 1) / kHScanTile;
+  unsigned* scan_tot;
+  FGA_TRY(sc.get(&scan_tot, sizeof(unsigned) * scan_blocks));
   FGA_HIP(hipMemcpyAsync(dtiles, tiles.data(), sizeof(SortTile) * ntiles, hipMemcpyHostToDevice, s));
   FGA_HIP(hipMemcpyAsync(dseg0, seg_tile0.data(), sizeof(int) * (nseg + 1), hipMemcpyHostToDevice, s));
   k_box_part<T><<<ntiles, kBlock, 0, s>>>(X, dtiles, boxpart);
-  k_box_fin<<<(nseg + 63) / 64, 64, 0, s>>>(boxpart, dseg0, nseg, box_dev);
+  k_box_fin<<<nseg, kWave, 0, s>>>(boxpart, dseg0, nseg, box_dev);
   k_morton<T><<<ntiles, kBlock, 0, s>>>(X, dtiles, box_dev, k0, v0);
   for (int shift = 0; shift < 3 * kQBits; shift += 8) {
     k_rs_hist<<<ntiles, kBlock, 0, s>>>(k0, dtiles, shift, hist);
-    k_scan_u32_1block<<<1, 1024, 0, s>>>(hist, hist_entries);
+    k_scan_tile<<<scan_blocks, kBlock, 0, s>>>(hist, hist_entries, scan_tot);
+    k_scan_u32_1block<<<1, 1024, 0, s>>>(scan_tot, scan_blocks);
+    k_scan_add<<<scan_blocks, kBlock, 0, s>>>(hist, hist_entries, scan_tot);
     k_rs_scatter<<<ntiles, kBlock, 0, s>>>(k0, v0, dtiles, shift, hist, k1, v1);
     std::swap(k0, k1);
     std::swap(v0, v1);
@@ -697,6 +822,7 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   for (int g = 0; g < nseg; ++g) hr[g] = {segs[g].off, segs[g].off + segs[g].n};
   SegRange* sr;
   unsigned *mask, *cnt, *P, *stats;
+  uint4* bpart;
   unsigned char* leaf0;
   int *own_d, *own_a, *own_b, *node_off;
   D4 *W, *bsumD;
@@ -707,6 +833,7 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
   FGA_TRY(sc.get(&cnt, sizeof(unsigned) * ntot));
   FGA_TRY(sc.get(&P, sizeof(unsigned) * (ntot + 1)));
   FGA_TRY(sc.get(&stats, sizeof(unsigned) * 4));
+  FGA_TRY(sc.get(&bpart, sizeof(uint4) * (size_t)((2 * ntot + kBlock - 1) / kBlock)));
   FGA_TRY(sc.get(&leaf0, ntot));
   FGA_TRY(sc.get(&own_d, sizeof(int) * ntot));
   FGA_TRY(sc.get(&own_a, sizeof(int) * ntot));
@@ -742,7 +869,8 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
     FGA_HIP(hipMemsetAsync(keep, 0, sizeof(unsigned) * (total + 1), s));
   }
   k_emit<T><<<nb, kBlock, 0, s>>>(X, codes, sr, box, nseg, ntot, mask, leaf0, own_d, own_a, own_b, P, W,
-                                  nodes, total ? total : 1, stats, L, keep);
+                                  nodes, total ? total : 1, bpart, L, keep);
+  k_stats_fin<<<1, kBlock, 0, s>>>(bpart, nb, stats);
   k_seg_nodes<<<(nseg + 63) / 64, 64, 0, s>>>(sr, nseg, P, node_off);
   if (L > 1) {  // drop the cells below the leaf size and compact the preorder
     unsigned *NI, *bsumK;
@@ -760,8 +888,9 @@ fga_status build_trees(int nseg, const TreeSeg* segs, void* Xpacked, int64_t nto
       return FGA_E_NOMEM;
     }
     FGA_HIP(hipMemsetAsync(stats + 1, 0, sizeof(unsigned) * 2, s));
-    k_compact<<<(int)((total + kBlock - 1) / kBlock), kBlock, 0, s>>>(nodes, keep, NI, node_off, nseg,
-                                                                      total, packed, stats);
+    const int nbC = (int)((total + kBlock - 1) / kBlock);
+    k_compact<<<nbC, kBlock, 0, s>>>(nodes, keep, NI, node_off, nseg, total, packed, bpart);
+    k_stats_fin<<<1, kBlock, 0, s>>>(bpart, nbC, stats);
     k_remap_off<<<(nseg + 64) / 64, 64, 0, s>>>(NI, nseg, node_off);
     FGA_HIP(hipStreamSynchronize(s));
     pool_free(nodes, s);
