@@ -43,6 +43,7 @@ PEAK_FP32_NONPACKED = 78.6e12      # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
 KERNEL_NAMES = {0: "k_iteration<float, direct, FP32_KAHAN>",
                 1: "k_iteration<float, BH per-particle walk, FP32_KAHAN>",
+                32: "k_iteration_group<FP32_KAHAN, 1> (group walk, groups of 32 held twice per wave)",
                 64: "k_iteration_group<FP32_KAHAN, 1> (group walk, 64 particles per wave)",
                 128: "k_iteration_group<FP32_KAHAN, 2> (group walk, 128 particles per wave)"}
 

@@ -107,8 +107,13 @@ typedef struct {
                              the Alg. 2 accept/open decisions itself; 64 or 128 = the
                              particles of a wave (consecutive in Morton order) share one walk,
                              a node being accepted only if the MAC holds for the group's whole
-                             bounding box (at least as accurate as per-particle); 0 = chosen
-                             by the autotuner among these. FP64 uses 1. */
+                             bounding box (at least as accurate as per-particle); 32 = groups
+                             of at most 32 such particles, each held twice over the wave's
+                             lanes (the two copies split the interaction list); 0 = chosen
+                             by the autotuner among 1, 64 and 128. FP64 uses 1. The choice changes
+                             which nodes are accepted, so with 0 the result of identical
+                             inputs can differ (within the MAC's accuracy) between processes
+                             whose timings made different choices; FGA_TUNE_CACHE pins them. */
   double rbf_sigma;       /* width sigma of the RBF kernel exp(-s^2 / sigma^2) of the landmark
                              masses (Eq. RBF_function), in the normalised frame; 0.03 */
   double rbf_weight;      /* value of the RBF weight B at a landmark point; away from every
@@ -128,7 +133,8 @@ typedef struct {
   long long interactions; /* force interactions evaluated (accepted nodes + leaf points) */
   double ms_total;        /* wall time of the call in milliseconds */
   int traversal;          /* force kernel in use: 0 = direct sum (theta = 0), 1 = per-particle
-                             Barnes-Hut walk, 64 or 128 = group walk of that many particles */
+                             Barnes-Hut walk, 32, 64 or 128 = group walk of groups of at most
+                             that many particles */
   int leaf_size;          /* leaf size of the Barnes-Hut tree in use (0 for the direct sum) */
 } fga_report;
 

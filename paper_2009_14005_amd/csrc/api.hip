@@ -107,9 +107,9 @@ fga_status check_params(const fga_params* p) {
     set_error("leaf_size must be in [0, 64] (got %d)", p->leaf_size);
     return FGA_E_INVALID_ARG;
   }
-  if (p->group_width != 0 && p->group_width != 1 && p->group_width != 64 &&
-      p->group_width != 128) {
-    set_error("group_width must be 0, 1, 64 or 128 (got %d)", p->group_width);
+  if (p->group_width != 0 && p->group_width != 1 && p->group_width != 32 &&
+      p->group_width != 64 && p->group_width != 128) {
+    set_error("group_width must be 0, 1, 32, 64 or 128 (got %d)", p->group_width);
     return FGA_E_INVALID_ARG;
   }
   if (p->group_boxes != 0 && p->group_boxes != 1 && p->group_boxes != 2 && p->group_boxes != 4) {
@@ -326,6 +326,7 @@ struct fga_state {
   // group walk whose costs are measured by the first iteration of fga_step
   // (registrations): the K, tau option, part cap and tree of the pending split
   int pend_K = 0, pend_fi = 0, pend_cap = 0, pend_li = 0;
+  int run = 0;  // particles per group of the group walk in use (32, 64 or 128)
   int4* ident_items = nullptr;          // one wave item per group, Morton order
 };
 
@@ -363,7 +364,12 @@ static void state_free(fga_state* S) {
 // runs of G. Sparse stretches of the order (where consecutive particles are
 // far apart) then form small groups with small boxes instead of one box that
 // opens everything between them.
+// Tau options fi = 0..3 bound runs of 64 K particles; fi = 4..7 take the
+// same bounds on runs of at most 32 (K = 1), which the kernel holds twice
+// over the wave's lanes: smaller boxes accept more nodes, and a launch has
+// twice as many waves.
 static const double kGroupTau[4] = {0.0, 1.0, 2.0, 4.0};
+static int group_run(int K, int fi) { return fi >= 4 ? kWave / 2 : kWave * K; }
 // leaf sizes the autotuner chooses from (leaf_size 0)
 static const int kLeafOpts[] = {1, 2, 4, 8, 16};
 constexpr int kNumLeafOpts = 5;
@@ -467,11 +473,11 @@ static fga_status measure_groups(fga_state* S, int K, int li, fga_state::Groups&
 // Device groups of a state for (K, tau option) on tree li, built on first use
 // (the group tables do not depend on the tree; their costs do).
 static fga_status ensure_groups(fga_state* S, int K, int fi, int li, fga_state::Groups** out) {
-  const int key = 16 * li + K * 4 + fi;
+  const int key = 64 * li + K * 8 + fi;
   auto it = S->groups.find(key);
   if (it == S->groups.end()) {
     for (auto& kv : S->groups)
-      if (kv.first % 16 == key % 16) {  // the same tables for another tree
+      if (kv.first % 64 == key % 64) {  // the same tables for another tree
         fga_state::Groups gt;
         gt.host = kv.second.host;
         gt.n = kv.second.n;
@@ -487,7 +493,7 @@ static fga_status ensure_groups(fga_state* S, int K, int fi, int li, fga_state::
       FGA_HIP(hipEventSynchronize(S->qready));
     }
     fga_state::Groups gt;
-    make_groups(S->qhost.data(), S->m, kWave * K, kGroupTau[fi], gt.host);
+    make_groups(S->qhost.data(), S->m, group_run(K, fi), kGroupTau[fi & 3], gt.host);
     gt.n = (int)gt.host.size();
     it = S->groups.emplace(key, std::move(gt)).first;
   }
@@ -663,6 +669,19 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands,
 // restored. The stop rule is off while tuning.
 constexpr int kTuneAdvance = 16;
 constexpr int kTuneFinal = 8;
+
+// FGA_TUNE_LOG=1: the autotuner prints every timing round to stderr.
+static void tune_log(const char* what, const std::vector<std::pair<float, int>>& times) {
+  const char* v = getenv("FGA_TUNE_LOG");
+  if (!v || v[0] != '1') return;
+  std::fprintf(stderr, "[fga tune] %s:", what);
+  for (const auto& t : times) {
+    const int mode = (t.second >> 8) & 255;
+    std::fprintf(stderr, " L%d/%s%d/c%d=%.3fms", t.second >> 16, mode >= 16 ? "g" : "p",
+                 mode >= 16 ? mode - 16 : mode, t.second & 255, t.first);
+  }
+  std::fprintf(stderr, "\n");
+}
 constexpr int kTuneLeafLead = 3;  // splits of the first tree retimed on every other tree
 static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* best) {
   RigidState init;
@@ -673,6 +692,7 @@ static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* bes
   FGA_HIP(hipMemcpyAsync(S->st, &open, sizeof open, hipMemcpyHostToDevice, S->s));
   std::vector<std::pair<float, int>> times;
   fga_status st = tune_ranges(S, cands, &times);
+  if (st == FGA_OK) tune_log("initial pose", times);
   if (st == FGA_OK && S->trees.size() > 1) {
     // leaf sizes: the leading splits of the first tree (Alg. 1's singleton
     // leaves) timed again on every other tree
@@ -682,6 +702,7 @@ static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* bes
         more.push_back((int)li << 16 | (times[k].second & 0xffff));
     std::vector<std::pair<float, int>> t2;
     st = tune_ranges(S, more, &t2);
+    if (st == FGA_OK) tune_log("leaf sizes", t2);
     times.insert(times.end(), t2.begin(), t2.end());
     std::stable_sort(times.begin(), times.end(),
                      [](const std::pair<float, int>& x, const std::pair<float, int>& y) {
@@ -698,6 +719,7 @@ static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* bes
       std::vector<int> lead;
       for (size_t k = 0; k < times.size() && k < (size_t)kTuneFinal; ++k) lead.push_back(times[k].second);
       if (st == FGA_OK) st = tune_ranges(S, lead, &times);
+      if (st == FGA_OK) tune_log("after the advance", times);
       if (st == FGA_OK) *best = times[0].second;
     }
   }
@@ -1240,11 +1262,16 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     for (int fi = 0; fi < 4; ++fi) {
       if (gw == 0 || gw == 64) modes.push_back(16 + 1 + 4 * fi);
       if (gw == 0 || gw == 128) modes.push_back(16 + 2 + 4 * fi);
+      // runs of 32 on request only: on the LiDAR and mesh workloads every
+      // one of them timed slower than the runs of 64 (the walks double)
+      if (gw == 32) modes.push_back(16 + 1 + 4 * (fi + 4));
     }
   }
   std::vector<int> cands;
   for (int md : modes) {
-    const int64_t tp = md >= 16 ? (int64_t)kBlock * ((md - 16) & 3) : kBlock / md;
+    const int64_t tp = md < 16 ? kBlock / md
+                       : ((md - 16) >> 2) >= 4 ? kBlock / 2  // runs of 32 particles
+                                               : (int64_t)kBlock * ((md - 16) & 3);
     const int64_t tl = (m + tp - 1) / tp;
     if (p->velocity == FGA_VEL_PARTICLE) {
       cands.push_back(md << 8 | 1);
@@ -1348,6 +1375,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     pd.n_nodes = S->n_nodes;
   }
   if (fga_status gs = apply_split(S, pd, best, true, defer); gs != FGA_OK) return fail(gs);
+  S->run = pd.group ? group_run(pd.group, ((best >> 8) & 255) >= 16 ? (((best >> 8) & 255) - 16) >> 2 : 0) : 0;
   if (S->V) {  // trial iterations wrote per-particle velocities; the state starts at rest
     const size_t vb = (S->f64 ? 8 : 4) * 3 * (size_t)m;
     if (hipMemsetAsync(S->V, 0, vb, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
@@ -1501,7 +1529,7 @@ fga_status fga_state_get(const fga_state* S, double R[9], double t[3], fga_repor
     rep->last_dT2 = h.dT2;
     rep->interactions = h.interactions;
     rep->ms_total = 0.0;
-    rep->traversal = !S->nodes ? 0 : S->pd.group ? kWave * S->pd.group : 1;
+    rep->traversal = !S->nodes ? 0 : S->pd.group ? S->run : 1;
     rep->leaf_size = S->leaf_used;
   }
   if (h.flags & 2) {
@@ -2090,8 +2118,8 @@ extern "C" fga_status fga_register_batch(int npairs, const void* const* X, const
     set_error("particle velocities are not supported in batched registration");
     return FGA_E_UNSUPPORTED;
   }
-  if (p->group_width == 128) {
-    set_error("the batched group walk holds 64 particles per wave (group_width 0, 1 or 64)");
+  if (p->group_width == 128 || p->group_width == 32) {
+    set_error("the batched group walk holds groups of 64 particles (group_width 0, 1 or 64)");
     return FGA_E_UNSUPPORTED;
   }
   for (int k = 0; k < npairs; ++k) {

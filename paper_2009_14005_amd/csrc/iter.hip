@@ -148,22 +148,46 @@ __device__ void finish_item(const PairDev& pd, const IterConsts& c, int item, in
           PREC == FGA_PREC_FP32_ALL && k < kMom ? (double)(float)mom[k] : mom[k];
 }
 
-// Ordered sum of partial-moment rows [r0, r1) (one row per thread, then the
-// fixed-order block sum); the result is valid in thread 0.
+// Threads of a reduction block: kRow waves, so that a stride of the block
+// over the flat array of rows keeps every thread on one column of the row and
+// every load of the block is contiguous.
+constexpr int kReduceThreads = kRow * kWave;
+
+// Ordered sum of partial-moment rows [r0, r1). Thread t adds column t mod kRow
+// of the flat elements t, t + kReduceThreads, ... (rows t / kRow + 64 j),
+// then thread k < kRow adds the kWave per-thread sums of column k in thread
+// order: a fixed order, so the result is deterministic. FP32_ALL adds the
+// moments in FP32. The result is valid in every thread.
 template <int PREC>
 __device__ inline void sum_rows(const double* base, int r0, int r1, double (&tot)[kRow],
-                                double* lds) {
-#pragma unroll
-  for (int k = 0; k < kRow; ++k) tot[k] = 0.0;
-  for (int e = r0 + (int)threadIdx.x; e < r1; e += kBlock) {
-    const double* pp = base + (size_t)e * kRow;
-#pragma unroll
-    for (int k = 0; k < kRow; ++k) {
-      if (PREC == FGA_PREC_FP32_ALL && k < kMom) tot[k] = (double)((float)tot[k] + (float)pp[k]);
-      else tot[k] += pp[k];
-    }
+                                double* lds /* kReduceThreads + kRow */) {
+  const int t = (int)threadIdx.x;
+  const bool f32 = PREC == FGA_PREC_FP32_ALL && t % kRow < kMom;
+  const double* p = base + (size_t)r0 * kRow;
+  const int ne = (r1 - r0) * kRow;
+  double s = 0.0;
+  float sf = 0.f;
+#pragma unroll 8
+  for (int e = t; e < ne; e += kReduceThreads) {
+    const double v = p[e];
+    if (f32) sf += (float)v;
+    else s += v;
   }
-  block_sum<kRow>(tot, lds);
+  lds[t] = f32 ? (double)sf : s;
+  __syncthreads();
+  if (t < kRow) {
+    double a = 0.0;
+    float af = 0.f;
+    for (int i = 0; i < kWave; ++i) {
+      const double v = lds[t + kRow * i];
+      if (f32) af += (float)v;
+      else a += v;
+    }
+    lds[kReduceThreads + t] = f32 ? (double)af : a;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRow; ++k) tot[k] = lds[kReduceThreads + k];
 }
 
 // a6/a7 completion of one pair's iteration, block b of the reduction launch:
@@ -361,8 +385,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGroupWa
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_reduce_step(PairDev pd, IterConsts c) {
-  __shared__ double lds[kRow * (kBlock / kWave)];
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_step(PairDev pd, IterConsts c) {
+  __shared__ double lds[kReduceThreads + kRow];
   if (pd.st->converged) return;  // uniform: the state was written by an earlier launch
   reduce_step<PREC>(pd, c, (int)blockIdx.x, lds);
 }
@@ -370,9 +394,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce_step(PairDev pd, IterConsts c
 // Reduction launch of the batched iteration: blockIdx.y is the pair. Block
 // (0, 0) also rewinds the work queue for the next iteration.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_batch_reduce_step(const PairDev* pairs, unsigned* queue,
-                                                              IterConsts c) {
-  __shared__ double lds[kRow * (kBlock / kWave)];
+__global__ __launch_bounds__(kReduceThreads) void k_batch_reduce_step(const PairDev* pairs,
+                                                                      unsigned* queue,
+                                                                      IterConsts c) {
+  __shared__ double lds[kReduceThreads + kRow];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) queue[0] = 0u;
   const PairDev pd = pairs[blockIdx.y];
   if ((int)blockIdx.x >= reduce_blocks(pd.n_items) || pd.st->converged) return;
@@ -381,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_reduce_step(const PairDev* pai
 
 template <int PREC>
 inline void reduce_launch(const PairDev& pd, const IterConsts& c, hipStream_t s) {
-  k_reduce_step<PREC><<<reduce_blocks(pd.n_items), kBlock, 0, s>>>(pd, c);
+  k_reduce_step<PREC><<<reduce_blocks(pd.n_items), kReduceThreads, 0, s>>>(pd, c);
 }
 
 }  // namespace
@@ -457,9 +482,9 @@ fga_status launch_batch_iteration(const PairDev* pairs_dev, int npairs, int redu
     }
   }
   const dim3 rgrid((unsigned)std::max(1, reduce_blocks), (unsigned)npairs);
-  if (sizeof(T) == 8) k_batch_reduce_step<FGA_PREC_FP64><<<rgrid, kBlock, 0, s>>>(pairs_dev, queue, c);
-  else if (c.prec == FGA_PREC_FP32_ALL) k_batch_reduce_step<FGA_PREC_FP32_ALL><<<rgrid, kBlock, 0, s>>>(pairs_dev, queue, c);
-  else k_batch_reduce_step<FGA_PREC_FP32_KAHAN><<<rgrid, kBlock, 0, s>>>(pairs_dev, queue, c);
+  if (sizeof(T) == 8) k_batch_reduce_step<FGA_PREC_FP64><<<rgrid, kReduceThreads, 0, s>>>(pairs_dev, queue, c);
+  else if (c.prec == FGA_PREC_FP32_ALL) k_batch_reduce_step<FGA_PREC_FP32_ALL><<<rgrid, kReduceThreads, 0, s>>>(pairs_dev, queue, c);
+  else k_batch_reduce_step<FGA_PREC_FP32_KAHAN><<<rgrid, kReduceThreads, 0, s>>>(pairs_dev, queue, c);
   FGA_HIP(hipGetLastError());
   return FGA_OK;
 }
@@ -634,23 +659,26 @@ __global__ __launch_bounds__(kBlock) void k_energy_final(const double* rows, int
   if (threadIdx.x == 0) *E = -G * v[0];
 }
 
-// Group traversal for fga_forces: every wave takes 64 K consecutive template
-// particles of the Morton order yorder and writes F_i = G m_Y,i acc_i.
+// Group traversal for fga_forces: every wave takes 64 K / R consecutive
+// template particles of the Morton order yorder (R = 2: a group of 32 held
+// twice over the lanes, K = 1) and writes F_i = G m_Y,i acc_i.
 template <int K, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const int* yorder, int m,
                                                          const BHWide* nodes, int n_nodes,
                                                          const float4* Xs, int n_points,
                                                          float theta2, float eps2, const float* mY,
                                                          double G, float* F,
-                                                         unsigned long long* count, int nb) {
+                                                         unsigned long long* count, int nb,
+                                                         int R) {
   __shared__ GroupLds g[kBlock / kWave];
   const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
+  const int per_wave = kWave * K / R, pl = lane & (kWave / R - 1);
   int idx[K];
   bool valid[K];
   float y[K][3], acc[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int pos = blockIdx.x * (kBlock * K) + wave * (kWave * K) + K * lane + k;
+    const int pos = blockIdx.x * (kBlock / kWave) * per_wave + wave * per_wave + K * pl + k;
     valid[k] = pos < m;
     idx[k] = valid[k] ? yorder[pos] : 0;
 #pragma unroll
@@ -660,11 +688,11 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, 1, nb, theta2, eps2, valid,
+  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, R, nb, theta2, eps2, valid,
                                     y, acc, cnt, entries, g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
-    if (valid[k]) {
+    if (valid[k] && lane < kWave / R) {
       const double w = G * (mY ? (double)mY[idx[k]] : 1.0);
 #pragma unroll
       for (int a = 0; a < 3; ++a) F[3 * idx[k] + a] = ok ? (float)(w * (double)acc[k][a]) : __builtin_nanf("");
@@ -754,10 +782,12 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
   unsigned long long* cnt = nullptr;
   FGA_TRY(pool_get(&cnt, sizeof(unsigned long long), s));
   (void)hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
-  const int K = sizeof(T) == 4 ? p.group_width / kWave : 0;  // 64 -> 1, 128 -> 2
+  // 32 -> K = 1 held twice (R = 2), 64 -> K = 1, 128 -> K = 2
+  const int K = sizeof(T) == 4 ? (p.group_width == 32 ? 1 : p.group_width / kWave) : 0;
+  const int R = p.group_width == 32 ? 2 : 1;
   if constexpr (sizeof(T) == 4) {
     if (K == 1 || K == 2) {
-      const int tp = kBlock * K;
+      const int tp = kBlock * K / R;
       const dim3 grid((unsigned)((m + tp - 1) / tp));
       const float t2 = (float)(theta * theta), e2 = (float)(p.eps * p.eps);
       const float* Yf = (const float*)Y;
@@ -765,13 +795,13 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
       const bool kahan = p.precision == FGA_PREC_FP32_KAHAN;
       const int nb = group_boxes_of(p);
       if (K == 1 && kahan)
-        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
+        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
       else if (K == 1)
-        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
+        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
       else if (kahan)
-        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
+        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
       else
-        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb);
+        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
     }
   }
   if (K != 1 && K != 2) {

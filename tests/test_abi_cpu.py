@@ -58,7 +58,7 @@ def call_forces(**over):
     (dict(p=fga.default_params(rho=0)), 1), (dict(p=fga.default_params(a=5.0, b=-5.0)), 1),
     (dict(p=fga.default_params(max_depth=12)), 6), (dict(p=fga.default_params(precision=9)), 1),
     (dict(p=fga.default_params(leaf_size=65)), 1), (dict(p=fga.default_params(leaf_size=-1)), 1),
-    (dict(p=fga.default_params(group_width=32)), 1), (dict(p=fga.default_params(group_width=-1)), 1),
+    (dict(p=fga.default_params(group_width=48)), 1), (dict(p=fga.default_params(group_width=-1)), 1),
     (dict(p=fga.default_params(tile=256)), 1), (dict(p=fga.default_params(tile=-1)), 1),
     (dict(dt=0, p=fga.default_params(precision=2)), 1),
 ])

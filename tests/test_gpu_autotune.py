@@ -123,7 +123,7 @@ def test_autotuned_results_agree_across_processes():
 
 
 @pytest.mark.parametrize("nb", [2, 4])
-@pytest.mark.parametrize("gw", [64, 128])
+@pytest.mark.parametrize("gw", [32, 64, 128])
 def test_group_run_boxes_refine_alg2(nb, gw):
     """The MAC against the boxes of runs of lanes accepts only nodes that pass
     Alg. 2's test for every particle: no further from the direct sum than the

@@ -88,7 +88,7 @@ def test_mesh_bh_and_direct_sampled():
         assert np.median(eb) <= 1e-5, (theta, np.median(eb))
 
 
-@pytest.mark.parametrize("gw", [64, 128])
+@pytest.mark.parametrize("gw", [32, 64, 128])
 def test_lidar_group_forces_sampled(gw):
     X, Y, _, _ = synth.lidar_pair()
     Xn, Yn, mX = prepared(X, Y)

@@ -173,7 +173,7 @@ def test_bh_forces_match_oracle_tree(theta):
         assert cnt == len(X) * len(Y)
 
 
-@pytest.mark.parametrize("gw", [64, 128])
+@pytest.mark.parametrize("gw", [32, 64, 128])
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.8])
 def test_group_forces_against_oracle_tree(theta, gw):
     """Group walk: a node is accepted only when the MAC holds for the group's
@@ -201,7 +201,7 @@ def test_group_forces_against_oracle_tree(theta, gw):
     assert cnt >= cref, (cnt, cref)
 
 
-@pytest.mark.parametrize("gw", [64, 128])
+@pytest.mark.parametrize("gw", [32, 64, 128])
 def test_group_forces_tiny_theta_is_direct(gw):
     X, m = _tree_case(9, 5000)
     rng = np.random.default_rng(10)
@@ -213,7 +213,7 @@ def test_group_forces_tiny_theta_is_direct(gw):
     assert cnt == len(X) * len(Y)
 
 
-@pytest.mark.parametrize("gw", [64, 128])
+@pytest.mark.parametrize("gw", [32, 64, 128])
 def test_group_forces_ragged_and_duplicates(gw):
     # duplicates make depth-20 leaves; 1, 63, 65 and 130 template points
     # leave partial waves and partial particle slots
@@ -280,7 +280,7 @@ def test_register_config0_bh():
     assert rep.interactions > 0
 
 
-@pytest.mark.parametrize("gw", [1, 64, 128])
+@pytest.mark.parametrize("gw", [1, 32, 64, 128])
 def test_register_config0_bh_traversals(gw):
     X, Y, _, _ = synth.mixture_pair()
     ref = oracle_run(X, Y, 0.5, 200)
@@ -318,7 +318,7 @@ def test_register_group_walk_tiny_reference(per):
 def test_register_group_precisions(prec):
     X, Y, _, _ = synth.mixture_pair(15, per_comp=512, m=3000)
     ref = oracle_run(X, Y, 0.5, 60)
-    for gw in (64, 128):
+    for gw in (32, 64, 128):
         R, t, rep = fga_run(X, Y, theta=0.5, max_iter=60, group_width=gw, precision=prec)
         check_transform(R, t, ref, X)
 
