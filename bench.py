@@ -92,10 +92,14 @@ def golden():
         return {}
 
 
-def vs_oracle(rec, R, t, X, at=None):
-    """Pose error against a stored FP64 oracle registration (None if absent)."""
+def vs_oracle(rec, R, t, X, at=None, iters=None):
+    """Pose error against a stored FP64 oracle registration (None if absent).
+    With `iters`, the record's pose after that many iterations (its final
+    pose or a stored checkpoint), else None."""
     if not rec:
         return None
+    if iters is not None and rec.get("iters") != iters:
+        at = iters
     if at is not None:
         rec = rec.get("at", {}).get(str(at))
         if rec is None:
@@ -258,7 +262,7 @@ def main():
         "interactions_evaluated_per_registration": evaluated,
         "interactions_evaluated_per_s": evaluated * args.steps / elapsed,
         "ms_per_iteration": {"force_launch": f_ms, "reduction_launch": r_ms},
-        "error_vs_oracle": vs_oracle(gold.get("mesh_1048576_bh0.5"), R, t, X),
+        "error_vs_oracle": vs_oracle(gold.get("mesh_1048576_bh0.5"), R, t, X, iters=args.iters),
         "oracle_alg2_interactions_per_registration": (gold.get("mesh_1048576_bh0.5") or {}).get("interactions"),
         "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, R),
                                      "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag_of(X))},
@@ -345,7 +349,7 @@ def bench_sweep(reg, fga, torch, synth, gold, args):
                   "speedup_vs_direct": res["direct"]["force_launch_ms"] / f_ms})
         r["alg2_interactions_per_particle"] = a2 / args.iters / len(Y)
         r["alg2_interactions_per_s_force_launch"] = a2 / args.iters / (f_ms * 1e-3)
-        r["error_vs_oracle"] = vs_oracle(gold.get(f"mesh_1048576_bh{th}"), sub.R, sub.t, X)
+        r["error_vs_oracle"] = vs_oracle(gold.get(f"mesh_1048576_bh{th}"), sub.R, sub.t, X, iters=args.iters)
         res[f"theta_{th}"] = r
         log(f"  theta {th}: force launch {f_ms * 1e3:.0f} us, error vs oracle direct median "
             f"{r['force_rel_err_vs_oracle_direct']['group_walk']['median']:.1e}")
@@ -388,7 +392,7 @@ def bench_lidar(fga, torch, synth, gold, args):
             "alg2_interactions_per_s": alg2 * 10 / el, "alg2_interactions_per_registration": alg2,
             "interactions_evaluated_per_registration": evaluated,
             "oracle_alg2_interactions_per_registration": (gold.get("lidar_65536_bh0.5") or {}).get("interactions"),
-            "error_vs_oracle": vs_oracle(gold.get("lidar_65536_bh0.5"), reg.R, reg.t, X),
+            "error_vs_oracle": vs_oracle(gold.get("lidar_65536_bh0.5"), reg.R, reg.t, X, iters=args.iters),
             "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, reg.R),
                                          "dt_over_diag": float(np.linalg.norm(reg.t - t_gt) / diag_of(X))},
             "leaf_size": reg.rep.leaf_size,
@@ -566,7 +570,7 @@ def bench_odometry(fga, torch, synth, gold, args, nframes=32):
     path = sum(float(np.linalg.norm(poses[k + 1][1] - poses[k][1])) for k in range(nframes - 1))
     end_err = float(np.linalg.norm(ta[-1] - R0.T @ (poses[-1][1] - p0)))
     recs = gold.get("odometry_lidar_pairs_bh0.5") or []
-    vo = [vs_oracle(recs[k], Rr[k], tr[k], scans[k]) for k in range(min(len(recs), nframes - 1))]
+    vo = [vs_oracle(recs[k], Rr[k], tr[k], scans[k], iters=args.iters) for k in range(min(len(recs), nframes - 1))]
     rel = np.array(rel)
     log(f"  {el * 1e3:.1f} ms for {nframes - 1} pairs ({(nframes - 1) / el:.1f} frames/s), drift {end_err / path:.4f}")
     return {"frames": nframes, "ms_total": el * 1e3, "frames_per_s": (nframes - 1) / el,

@@ -314,8 +314,6 @@ struct fga_state {
   IterConsts c;
   NormInfo norm;
   int tree_stats[3] = {0, 0, 0};
-  std::vector<float> qhost;             // Morton-sorted template (x, y, z, c), group walk only
-  hipEvent_t qready = nullptr;          // recorded after the copy into qhost
   struct Groups {
     std::vector<int2> host;             // (first, count) of every group, Morton order
     int n = 0;
@@ -354,16 +352,13 @@ static void state_free(fga_state* S) {
   for (auto& kv : S->groups)
     for (auto& it : kv.second.items) pool_free(it.second.first, s);
   pool_free(S->ident_items, s);
-  if (S->qready) (void)hipEventDestroy(S->qready);
   delete S;
 }
 
-// Groups of the template for the group walk, over its Morton order: runs of
-// at most G consecutive particles; with f > 0 a run also ends before its
-// bounding-box diagonal would exceed f times the median diagonal of the fixed
-// runs of G. Sparse stretches of the order (where consecutive particles are
-// far apart) then form small groups with small boxes instead of one box that
-// opens everything between them.
+// Groups of the template for the group walk, over its Morton order (built on
+// the device by device_groups): aligned blocks of G consecutive particles,
+// each cut into runs; with f > 0 a run also ends before its bounding-box
+// diagonal would exceed f times the median diagonal of the blocks.
 // Tau options fi = 0..3 bound runs of 64 K particles; fi = 4..7 take the
 // same bounds on runs of at most 32 (K = 1), which the kernel holds twice
 // over the wave's lanes: smaller boxes accept more nodes, and a launch has
@@ -373,49 +368,6 @@ static int group_run(int K, int fi) { return fi >= 4 ? kWave / 2 : kWave * K; }
 // leaf sizes the autotuner chooses from (leaf_size 0)
 static const int kLeafOpts[] = {1, 2, 4, 8, 16};
 constexpr int kNumLeafOpts = 5;
-
-static void make_groups(const float* q4, int64_t m, int G, double f, std::vector<int2>& out) {
-  out.clear();
-  out.reserve((size_t)(m / G + 1));
-  float tau2 = std::numeric_limits<float>::infinity();
-  if (f > 0) {
-    std::vector<float> d;
-    d.reserve((size_t)(m / G + 1));
-    for (int64_t i = 0; i < m; i += G) {
-      const int64_t e = std::min<int64_t>(m, i + G);
-      float lx = q4[4 * i], ly = q4[4 * i + 1], lz = q4[4 * i + 2];
-      float hx = lx, hy = ly, hz = lz;
-      for (int64_t k = i + 1; k < e; ++k) {
-        const float* v = q4 + 4 * k;
-        lx = std::min(lx, v[0]); hx = std::max(hx, v[0]);
-        ly = std::min(ly, v[1]); hy = std::max(hy, v[1]);
-        lz = std::min(lz, v[2]); hz = std::max(hz, v[2]);
-      }
-      d.push_back((hx - lx) * (hx - lx) + (hy - ly) * (hy - ly) + (hz - lz) * (hz - lz));
-    }
-    std::nth_element(d.begin(), d.begin() + d.size() / 2, d.end());
-    const float med = d[d.size() / 2];
-    if (med > 0) tau2 = (float)(f * f) * med;
-  }
-  int64_t i = 0;
-  while (i < m) {
-    float lx = q4[4 * i], ly = q4[4 * i + 1], lz = q4[4 * i + 2];
-    float hx = lx, hy = ly, hz = lz;
-    int64_t j = i + 1;
-    const int64_t e = std::min<int64_t>(m, i + G);
-    for (; j < e; ++j) {
-      const float* v = q4 + 4 * j;
-      const float nlx = std::min(lx, v[0]), nhx = std::max(hx, v[0]);
-      const float nly = std::min(ly, v[1]), nhy = std::max(hy, v[1]);
-      const float nlz = std::min(lz, v[2]), nhz = std::max(hz, v[2]);
-      const float dd = (nhx - nlx) * (nhx - nlx) + (nhy - nly) * (nhy - nly) + (nhz - nlz) * (nhz - nlz);
-      if (dd > tau2) break;
-      lx = nlx; hx = nhx; ly = nly; hy = nhy; lz = nlz; hz = nhz;
-    }
-    out.push_back(make_int2((int)i, (int)(j - i)));
-    i = j;
-  }
-}
 
 static fga_status upload_items(fga_state* S, const std::vector<int4>& v, int4** out) {
   FGA_TRY(pool_get(out, sizeof(int4) * std::max<size_t>(1, v.size()), S->s));
@@ -485,15 +437,12 @@ static fga_status ensure_groups(fga_state* S, int K, int fi, int li, fga_state::
         *out = &it->second;
         return FGA_OK;
       }
-    if (S->qhost.empty()) {
-      S->qhost.resize((size_t)S->m * 4);
-      FGA_HIP(hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * S->m, hipMemcpyDeviceToHost, S->s));
-      FGA_HIP(hipStreamSynchronize(S->s));
-    } else if (S->qready) {
-      FGA_HIP(hipEventSynchronize(S->qready));
-    }
     fga_state::Groups gt;
-    make_groups(S->qhost.data(), S->m, group_run(K, fi), kGroupTau[fi & 3], gt.host);
+    std::vector<std::vector<int2>> tabs;
+    const int64_t zero = 0, mm = S->m;
+    FGA_TRY(device_groups((const float4*)S->Q, 1, &zero, &mm, group_run(K, fi), kGroupTau[fi & 3], tabs,
+                          S->s));
+    gt.host = std::move(tabs[0]);
     gt.n = (int)gt.host.size();
     it = S->groups.emplace(key, std::move(gt)).first;
   }
@@ -665,8 +614,8 @@ static fga_status tune_ranges(fga_state* S, const std::vector<int>& cands,
 // can rank the splits differently from the poses where most iterations are
 // spent), so every candidate is timed at the initial pose, the state is then
 // advanced by kTuneAdvance iterations with the fastest split, the leading
-// kTuneFinal candidates are timed again there, and the initial state is
-// restored. The stop rule is off while tuning.
+// candidates of up to kTuneFinal walks are timed again there, and the
+// initial state is restored. The stop rule is off while tuning.
 constexpr int kTuneAdvance = 16;
 constexpr int kTuneFinal = 8;
 
@@ -716,8 +665,20 @@ static fga_status autotune(fga_state* S, const std::vector<int>& cands, int* bes
       st = apply_split(S, adv, *best);
       for (int k = 0; k < kTuneAdvance && st == FGA_OK; ++k)
         st = S->f64 ? launch_iteration<double>(adv, S->c, S->s) : launch_iteration<float>(adv, S->c, S->s);
+      // retimed: the fastest split of each of the kTuneFinal fastest walks
+      // (traversal, tau option and tree; the part caps of one walk time
+      // alike), and the three fastest splits overall. The initial pose can
+      // rank the walks differently from the poses most iterations see.
       std::vector<int> lead;
-      for (size_t k = 0; k < times.size() && k < (size_t)kTuneFinal; ++k) lead.push_back(times[k].second);
+      for (size_t k = 0; k < times.size() && lead.size() < (size_t)kTuneFinal; ++k) {
+        const int walk = times[k].second & ~0xff;
+        bool seen = false;
+        for (int c : lead) seen = seen || (c & ~0xff) == walk;
+        if (!seen) lead.push_back(times[k].second);
+      }
+      for (size_t k = 0; k < times.size() && k < 3; ++k)
+        if (std::find(lead.begin(), lead.end(), times[k].second) == lead.end())
+          lead.push_back(times[k].second);
       if (st == FGA_OK) st = tune_ranges(S, lead, &times);
       if (st == FGA_OK) tune_log("after the advance", times);
       if (st == FGA_OK) *best = times[0].second;
@@ -1215,15 +1176,6 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   st = S->f64 ? sort_points_morton<double>(1, &sy, S->Q, m, nullptr, s)
               : sort_points_morton<float>(1, &sy, S->Q, m, nullptr, s);
   if (st != FGA_OK) return fail(st);
-  if (p->theta > 0 && !S->f64 && p->group_width != 1) {
-    // the host builds the group tables from the sorted template: copy it now,
-    // so that the copy and the table building overlap the tree build below
-    S->qhost.resize((size_t)m * 4);
-    if (hipMemcpyAsync(S->qhost.data(), S->Q, sizeof(float) * 4 * m, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipEventCreateWithFlags(&S->qready, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(S->qready, s) != hipSuccess)
-      return fail(FGA_E_DEVICE);
-  }
   const bool bh = p->theta > 0;
   // leaf sizes: the given one, or (leaf_size 0, FP32) every option for the
   // autotuner; FP64 keeps Alg. 1's singleton leaves
@@ -1293,8 +1245,9 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   // a cached tuning result needs only its own split; otherwise every
   // candidate is timed
   const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width) +
-                          (bh ? "_L" + std::to_string(leaf_auto ? 0 : S->tree_leaf[0]) +
-                                    "_B" + std::to_string(group_boxes_of(*p))
+                          (bh ? "_t" + std::to_string(std::lround(p->theta * 1000)) + "_L" +
+                                    std::to_string(leaf_auto ? 0 : S->tree_leaf[0]) + "_B" +
+                                    std::to_string(group_boxes_of(*p))
                               : "");
   int best = cands[0];
   bool tuned = cands.size() == 1;
@@ -1302,7 +1255,10 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tune.find(key);
-    if (it != g_tune.end() && std::find(cands.begin(), cands.end(), it->second) != cands.end()) {
+    // the cached split names its tree (leaf size) in the bits above 16; the
+    // candidates are listed for the first tree
+    if (it != g_tune.end() && (it->second >> 16) < (int)std::max<size_t>(1, S->trees.size()) &&
+        std::find(cands.begin(), cands.end(), it->second & 0xffff) != cands.end()) {
       best = it->second;
       tuned = true;
     }
@@ -1689,15 +1645,7 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     xs[k] = {xoff[k], n[k]};
   }
   FGA_TRY(sort_points_morton<T>(npairs, ys.data(), Qp, NY, nullptr, s));
-  // the host builds the group tables from the sorted templates: copy them
-  // before the trees are built, so that the table building overlaps the build
   const bool grouped = sizeof(T) == 4 && p.theta > 0 && p.group_width != 1;
-  std::vector<float> qh;
-  if (grouped) {
-    qh.resize((size_t)NY * 4);
-    FGA_HIP(hipMemcpyAsync(qh.data(), Qp, sizeof(float) * 4 * NY, hipMemcpyDeviceToHost, s));
-    FGA_HIP(hipEventRecord(B.ev, s));
-  }
   // the trees of all pairs for one leaf size (one set of launches)
   struct TreeSet {
     int leaf;
@@ -1765,9 +1713,9 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
         btuned = false;
       }
     }
-    FGA_HIP(hipEventSynchronize(B.ev));
   }
-  // group tables of every candidate tau option (host), and their offsets
+  // group tables of every candidate tau option (built on the device), and
+  // their offsets
   std::map<int, std::vector<std::vector<int2>>> gtab;
   std::map<int, std::vector<int>> gofs;
   int max_groups = 0;
@@ -1775,12 +1723,9 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     if (!grouped) break;
     auto& g = gtab[fi];
     auto& go = gofs[fi];
-    g.resize(npairs);
     go.assign(npairs + 1, 0);
-    for (int k = 0; k < npairs; ++k) {
-      make_groups(qh.data() + 4 * yoff[k], m[k], kWave, kGroupTau[fi], g[k]);
-      go[k + 1] = go[k] + (int)g[k].size();
-    }
+    FGA_TRY(device_groups((const float4*)Qp, npairs, yoff.data(), m, kWave, kGroupTau[fi], g, s));
+    for (int k = 0; k < npairs; ++k) go[k + 1] = go[k] + (int)g[k].size();
     max_groups = std::max(max_groups, go[npairs]);
   }
   std::vector<int> item_off(npairs + 1, 0);

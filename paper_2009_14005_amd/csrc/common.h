@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "fga.h"
 
@@ -224,6 +225,14 @@ fga_status relayout_wide(const BHNode* pre, int total, int nseg, const int* node
 template <typename T>
 fga_status sort_points_morton(int nseg, const TreeSeg* segs, void* Q, int64_t ntot, int* perm,
                               hipStream_t s);
+
+// groups.hip: group tables of the group walk over Morton-ordered templates
+// Q (nseg segments at off[k], m[k] particles): aligned blocks of G particles
+// cut into runs whose bounding-box diagonal stays within f times the median
+// block diagonal of the segment (f = 0: one run per block). out[k] receives
+// segment k's runs as (first particle, count), first relative to off[k].
+fga_status device_groups(const float4* Q, int nseg, const int64_t* off, const int64_t* m, int G,
+                         double f, std::vector<std::vector<int2>>& out, hipStream_t s);
 
 // iter.hip: force-only evaluation (fga_forces)
 int direct_ranges(int64_t m, int64_t n);

@@ -122,6 +122,29 @@ def test_autotuned_results_agree_across_processes():
     assert np.linalg.norm(np.array(a["t"]) - np.array(b["t"])) / diag < 1e-4
 
 
+def test_cached_choice_with_a_leaf_tree_is_reused(tmp_path):
+    """A cached split that names a tree other than the first (leaf size > 1)
+    is taken from the cache: no timing round runs (FGA_TUNE_LOG stays silent)
+    and the registration uses that tree and walk."""
+    cache = tmp_path / "tune.cache"
+    env = dict(os.environ, FGA_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", CHILD.format(root=ROOT)], capture_output=True, text=True,
+                       timeout=240, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in cache.read_text().splitlines() if l.startswith('"bh_f32_p1_g0_')]
+    assert len(lines) == 1, cache.read_text()
+    key = lines[0].split('"')[1]
+    # leaf index 1 (leaf size 2), group walk K = 1 with the first tau option, one part per group
+    cache.write_text(f'"{key}": {(1 << 16) | (17 << 8) | 1},\n')
+    env["FGA_TUNE_LOG"] = "1"
+    r = subprocess.run([sys.executable, "-c", CHILD.format(root=ROOT)], capture_output=True, text=True,
+                       timeout=240, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "[fga tune]" not in r.stderr, r.stderr[-2000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert (out["leaf"], out["trav"]) == (2, 64)
+
+
 @pytest.mark.parametrize("nb", [2, 4])
 @pytest.mark.parametrize("gw", [32, 64, 128])
 def test_group_run_boxes_refine_alg2(nb, gw):
