@@ -60,9 +60,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra workloads")
-    ap.add_argument("--extras", default="sweep,lidar,boxes,direct,precision,batched,odometry,mixture,landmarks",
+    ap.add_argument("--extras", default="sweep,lidar,direct,precision,batched,odometry,mixture,landmarks",
                     help="comma list of extra workloads: sweep (mesh theta 0.3/0.8 and direct), "
-                         "lidar, boxes (group-walk MAC against 1, 2, 4 run boxes), direct, precision, "
+                         "lidar, direct, precision, "
                          "batched, odometry, mixture, landmarks")
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--leaf", type=int, default=0,
@@ -276,8 +276,6 @@ def main():
         out["mesh_theta_sweep"] = bench_sweep(reg, **ctx)
     if "lidar" in extras:
         out["lidar"] = bench_lidar(**ctx)
-    if "boxes" in extras:
-        out["group_boxes"] = bench_group_boxes(reg, **ctx)
     if "direct" in extras:
         out["direct"] = bench_direct(**ctx)
     if "precision" in extras:
@@ -353,27 +351,6 @@ def bench_sweep(reg, fga, torch, synth, gold, args):
         res[f"theta_{th}"] = r
         log(f"  theta {th}: force launch {f_ms * 1e3:.0f} us, error vs oracle direct median "
             f"{r['force_rel_err_vs_oracle_direct']['group_walk']['median']:.1e}")
-    return res
-
-
-def bench_group_boxes(reg, fga, torch, synth, gold, args):
-    """The group walk's MAC against the group box (1) or the boxes of 2 or 4
-    runs of its lanes: force-launch time and terms evaluated per particle over
-    a registration of the mesh pair and of the LiDAR pair (theta 0.5)."""
-    log("group walk: MAC against 1 / 2 / 4 run boxes")
-    res = {}
-    X, Y, _, _ = synth.lidar_pair()
-    lid = Registration(fga, torch, X, Y, fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0))
-    for name, r in (("mesh_1048576", reg), ("lidar_65536", lid)):
-        for nb in (1, 2, 4):
-            r.p = type(r.p).from_buffer_copy(r.p)
-            r.p.group_boxes = nb
-            f_ms, _, ev, _ = r.profile(args.iters)
-            res[f"{name}_boxes{nb}"] = {"force_launch_us": f_ms * 1e3,
-                                        "interactions_evaluated_per_particle": ev / len(r.Y)}
-            log(f"  {name}, {nb} boxes: {f_ms * 1e3:.1f} us, {ev / len(r.Y):.0f} terms per particle")
-    reg.p = type(reg.p).from_buffer_copy(reg.p)
-    reg.p.group_boxes = 0
     return res
 
 

@@ -118,12 +118,7 @@ typedef struct {
                              masses (Eq. RBF_function), in the normalised frame; 0.03 */
   double rbf_weight;      /* value of the RBF weight B at a landmark point; away from every
                              landmark B returns to the landmark-free value 1; 100 */
-  int group_boxes;        /* group walk: the MAC is tested against the bounding boxes of 1, 2 or 4
-                             runs of the wave's lanes (each run's particles, consecutive in
-                             Morton order) and a node accepted only if it is far enough from
-                             all of them: smaller boxes accept more nodes while every accepted
-                             node still passes Alg. 2's test for every particle; 0 = default */
-  int reserved[3];
+  int reserved[4];        /* zero */
 } fga_params;
 
 typedef struct {

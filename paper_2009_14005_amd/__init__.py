@@ -51,8 +51,8 @@ class Params(ctypes.Structure):
         ("velocity", ctypes.c_int), ("mass_mode", ctypes.c_int), ("precision", ctypes.c_int),
         ("leaf_size", ctypes.c_int), ("tile", ctypes.c_int), ("check_every", ctypes.c_int),
         ("group_width", ctypes.c_int), ("rbf_sigma", ctypes.c_double),
-        ("rbf_weight", ctypes.c_double), ("group_boxes", ctypes.c_int),
-        ("reserved", ctypes.c_int * 3),
+        ("rbf_weight", ctypes.c_double),
+        ("reserved", ctypes.c_int * 4),
     ]
 
     def replace(self, **kw) -> "Params":

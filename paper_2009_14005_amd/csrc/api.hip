@@ -112,10 +112,6 @@ fga_status check_params(const fga_params* p) {
     set_error("group_width must be 0, 1, 32, 64 or 128 (got %d)", p->group_width);
     return FGA_E_INVALID_ARG;
   }
-  if (p->group_boxes != 0 && p->group_boxes != 1 && p->group_boxes != 2 && p->group_boxes != 4) {
-    set_error("group_boxes must be 0, 1, 2 or 4 (got %d)", p->group_boxes);
-    return FGA_E_INVALID_ARG;
-  }
   if (p->tile < 0 || p->tile > 255 || p->check_every < 0) {
     set_error("tile must be in [0, 255] and check_every >= 0");
     return FGA_E_INVALID_ARG;
@@ -1246,8 +1242,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   // candidate is timed
   const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width) +
                           (bh ? "_t" + std::to_string(std::lround(p->theta * 1000)) + "_L" +
-                                    std::to_string(leaf_auto ? 0 : S->tree_leaf[0]) + "_B" +
-                                    std::to_string(group_boxes_of(*p))
+                                    std::to_string(leaf_auto ? 0 : S->tree_leaf[0])
                               : "");
   int best = cands[0];
   bool tuned = cands.size() == 1;
@@ -1300,7 +1295,6 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   pd.n = (int)n;
   pd.m = (int)m;
   pd.n_nodes = S->n_nodes;
-  pd.subboxes = group_boxes_of(*p);
   S->c = make_iter_consts(*p);
   // manual stepping has no iteration cap; fga_register applies max_iter itself
   const int big = 0x7fffffff;
@@ -1696,8 +1690,8 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
         return q;
       };
       char buf[96];
-      snprintf(buf, sizeof buf, "batch_p%d_k%d_m%d_n%d_t%d_L%d_B%d", p.precision, lg(npairs), lg(NY),
-               lg(NX), (int)std::lround(p.theta * 1000), p.leaf_size, group_boxes_of(p));
+      snprintf(buf, sizeof buf, "batch_p%d_k%d_m%d_n%d_t%d_L%d", p.precision, lg(npairs), lg(NY),
+               lg(NX), (int)std::lround(p.theta * 1000), p.leaf_size);
       bkey = buf;
       std::lock_guard<std::mutex> lk(g_tune_mu);
       tune_load_locked();
@@ -1791,7 +1785,6 @@ fga_status batch_impl(int npairs, const void* const* X, const int64_t* n, const 
     pd.gcost = nullptr;
     pd.n_groups = 0;
     pd.n_witems = 0;
-    pd.subboxes = group_boxes_of(p);
   }
   FGA_HIP(hipMemsetAsync(done, 0, sizeof(unsigned) * doff[npairs], s));
   FGA_HIP(hipMemsetAsync(queue, 0, sizeof(unsigned) * 2, s));

@@ -169,14 +169,8 @@ struct PairDev {
   unsigned* gcost;      // optional: list entries evaluated per group are added here
   int n_groups;
   int n_witems;
-  int subboxes;         // group walk: MAC against 1, 2 or 4 boxes of the group's lanes
 };
 
-// Run boxes of the group walk's MAC (fga_params.group_boxes; 0 = the default).
-constexpr int kDefaultGroupBoxes = 1;
-inline int group_boxes_of(const fga_params& p) {
-  return p.group_boxes > 0 ? p.group_boxes : kDefaultGroupBoxes;
-}
 
 // ------------------------------------------------------------ declarations
 // prep.hip: normalisation, masses and packing (Appendix A; Eq. NIV)

@@ -433,57 +433,6 @@ __device__ inline float box_dist2(const float (&lo)[3], const float (&hi)[3], co
   return d2;
 }
 
-// The group's particles as nb <= 4 boxes, one per run of 64 / nb lanes (each
-// lane's valid particles; an empty run gives an empty box, infinitely far).
-// Every particle lies in one of them, so a node whose distance to each box
-// passes the MAC passes it for every particle.
-constexpr int kMaxSubBoxes = 4;
-template <int K>
-__device__ inline void group_subboxes(const bool (&valid)[K], const float (&y)[K][3], int nb,
-                                      float (&slo)[kMaxSubBoxes][3], float (&shi)[kMaxSubBoxes][3]) {
-  float mn[3], mx[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    mn[a] = __builtin_huge_valf();
-    mx[a] = -__builtin_huge_valf();
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (valid[k]) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        mn[a] = fminf(mn[a], y[k][a]);
-        mx[a] = fmaxf(mx[a], y[k][a]);
-      }
-    }
-  const int width = kWave / nb;
-  for (int o = width / 2; o > 0; o >>= 1)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = fminf(mn[a], __shfl_xor(mn[a], o, kWave));
-      mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], o, kWave));
-    }
-#pragma unroll
-  for (int s = 0; s < kMaxSubBoxes; ++s)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int src = s < nb ? s * width : 0;
-      slo[s][a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mn[a]), src));
-      shi[s][a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mx[a]), src));
-    }
-}
-
-// Squared distance used by the group MAC: to the group box, or with nb > 1
-// the smallest distance to the run boxes (never smaller than the former).
-__device__ inline float group_dist2(const float (&lo)[3], const float (&hi)[3], int nb,
-                                    const float (&slo)[kMaxSubBoxes][3],
-                                    const float (&shi)[kMaxSubBoxes][3], const float (&c)[3]) {
-  if (nb <= 1) return box_dist2(lo, hi, c);
-  float d2 = box_dist2(slo[0], shi[0], c);
-  for (int s = 1; s < nb; ++s) d2 = fminf(d2, box_dist2(slo[s], shi[s], c));
-  return d2;
-}
-
 // Work split of one group's walk over nr waves (part r): nodes of more than
 // kSplitPts points are walked by every part, and their accepted terms and leaf
 // points belong to part 0; a node of at most kSplitPts points whose parent is
@@ -500,9 +449,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
                                   const float4* __restrict__ X, int n_points, int r, int nr,
                                   float theta2, float eps2, bool sel,
                                   int nvalid, int rep, int R, const float (&lo)[3],
-                                  const float (&hi)[3], int nb,
-                                  const float (&slo)[kMaxSubBoxes][3],
-                                  const float (&shi)[kMaxSubBoxes][3],
+                                  const float (&hi)[3],
                                   const float (&y)[K][3], float (&acc)[K][3],
                                   float (&cmp)[K][3], unsigned& count, unsigned& entries,
                                   GroupLds& g) {
@@ -518,7 +465,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
     // instead: the same nodes are visited and accepted, two steps sooner.
     auto walked_open = [&](const BHWide& b) {
       const float c3[3] = {b.cm.x, b.cm.y, b.cm.z};
-      const float d2 = group_dist2(lo, hi, nb, slo, shi, c3);
+      const float d2 = box_dist2(lo, hi, c3);
       return b.child != -1 && !(__float_as_uint(b.l2) >> 31) && b.last - b.first + 1 > kSplitPts &&
              !(fabsf(b.l2) < theta2 * d2);
     };
@@ -592,7 +539,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
     const bool leaf = nd.child == -1;
     const bool twig = __float_as_uint(nd.l2) >> 31;
     const float c3[3] = {nd.cm.x, nd.cm.y, nd.cm.z};
-    const float d2 = group_dist2(lo, hi, nb, slo, shi, c3);
+    const float d2 = box_dist2(lo, hi, c3);
     const bool accept = on && ((leaf && nd.first == nd.last) || fabsf(nd.l2) < theta2 * d2);
     const bool own = accept && mine;
     const bool pts = on && !accept && (leaf || twig) && mine;
@@ -668,7 +615,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
 template <int K, bool KAHAN>
 __device__ inline bool bh_group(const BHWide* __restrict__ nodes, int n_nodes,
                                 const float4* __restrict__ X, int n_points, int r, int nr, int R,
-                                int nb, float theta2, float eps2,
+                                float theta2, float eps2,
                                 const bool (&valid)[K], const float (&y)[K][3],
                                 float (&acc)[K][3], unsigned& count, unsigned& entries,
                                 GroupLds& g) {
@@ -678,8 +625,6 @@ __device__ inline bool bh_group(const BHWide* __restrict__ nodes, int n_nodes,
   if (__ballot(nvalid > 0) == 0ull) return true;
   float lo[3], hi[3];
   group_box<K>(valid, y, true, lo, hi);
-  float slo[kMaxSubBoxes][3], shi[kMaxSubBoxes][3];
-  if (nb > 1) group_subboxes<K>(valid, y, nb, slo, shi);
   float cmp[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -687,8 +632,7 @@ __device__ inline bool bh_group(const BHWide* __restrict__ nodes, int n_nodes,
     for (int a = 0; a < 3; ++a) cmp[k][a] = 0.f;
   const int rep = (int)(threadIdx.x & (kWave - 1)) / (kWave / R);
   const bool ok = group_walk<K, KAHAN>(nodes, n_nodes, X, n_points, r, nr, theta2, eps2, true,
-                                       nvalid, rep, R, lo, hi, nb, slo, shi, y, acc, cmp, count,
-                                       entries, g);
+                                       nvalid, rep, R, lo, hi, y, acc, cmp, count, entries, g);
   if (R > 1) {  // add the replicas' partial sums
 #pragma unroll
     for (int k = 0; k < K; ++k)

@@ -308,7 +308,7 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
   }
   unsigned cnt = 0, entries = 0;
   const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
-      pd.nodes, pd.n_nodes, (const float4*)pd.X, pd.n, r, nr, R, pd.subboxes, c.ftheta2, c.feps2,
+      pd.nodes, pd.n_nodes, (const float4*)pd.X, pd.n, r, nr, R, c.ftheta2, c.feps2,
       valid, y, acc, cnt, entries, g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
   if (pd.gcost && lane == 0 && gi >= 0) atomicAdd(&pd.gcost[gi], entries);
@@ -668,8 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
                                                          const float4* Xs, int n_points,
                                                          float theta2, float eps2, const float* mY,
                                                          double G, float* F,
-                                                         unsigned long long* count, int nb,
-                                                         int R) {
+                                                         unsigned long long* count, int R) {
   __shared__ GroupLds g[kBlock / kWave];
   const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
   const int per_wave = kWave * K / R, pl = lane & (kWave / R - 1);
@@ -688,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_forces_group(const float* Y, const i
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, R, nb, theta2, eps2, valid,
+  const bool ok = bh_group<K, KAHAN>(nodes, n_nodes, Xs, n_points, 0, 1, R, theta2, eps2, valid,
                                     y, acc, cnt, entries, g[wave]);
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -793,15 +792,14 @@ fga_status forces_bh_tree(const void* Y, int64_t m, const int* yorder, const BHW
       const float* Yf = (const float*)Y;
       const float4* X4 = (const float4*)Xs;
       const bool kahan = p.precision == FGA_PREC_FP32_KAHAN;
-      const int nb = group_boxes_of(p);
       if (K == 1 && kahan)
-        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
+        k_forces_group<1, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, R);
       else if (K == 1)
-        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
+        k_forces_group<1, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, R);
       else if (kahan)
-        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
+        k_forces_group<2, true><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, R);
       else
-        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, nb, R);
+        k_forces_group<2, false><<<grid, kBlock, 0, s>>>(Yf, yorder, (int)m, nodes, n_nodes, X4, (int)n, t2, e2, (const float*)mY, p.G, (float*)F, cnt, R);
     }
   }
   if (K != 1 && K != 2) {

@@ -42,9 +42,9 @@ int main() {
   expect(fga_register(fake, 10, fake, 10, FGA_F32, &q, R, t, nullptr, nullptr), FGA_E_INVALID_ARG,
          "fraction damping eta > 1");
   q = p;
-  q.group_boxes = 3;
+  q.group_width = 48;
   expect(fga_register(fake, 10, fake, 10, FGA_F32, &q, R, t, nullptr, nullptr), FGA_E_INVALID_ARG,
-         "group_boxes 3");
+         "group_width 48");
   const void* frames[1] = {fake};
   const int64_t sizes[1] = {10};
   expect(fga_register_sequence(1, frames, sizes, FGA_F32, &p, R, t, nullptr, nullptr, nullptr, nullptr),

@@ -202,10 +202,3 @@ def test_energy_planar_sequence_argument_validation():
                                    None, None) == 1
 
 
-def test_group_boxes_validation():
-    L = fga.lib()
-    fake = ctypes.c_void_p(0x1000)
-    for nb, code in ((3, 1), (8, 1), (-1, 1)):
-        p = fga.default_params(group_boxes=nb)
-        F = L.fga_forces(fake, 10, fake, 10, fake, None, fga.F32, 0.5, ctypes.byref(p), fake, None, None)
-        assert F == code

@@ -145,34 +145,3 @@ def test_cached_choice_with_a_leaf_tree_is_reused(tmp_path):
     assert (out["leaf"], out["trav"]) == (2, 64)
 
 
-@pytest.mark.parametrize("nb", [2, 4])
-@pytest.mark.parametrize("gw", [32, 64, 128])
-def test_group_run_boxes_refine_alg2(nb, gw):
-    """The MAC against the boxes of runs of lanes accepts only nodes that pass
-    Alg. 2's test for every particle: no further from the direct sum than the
-    oracle's Alg. 1 tree, and within the Barnes-Hut gate of it."""
-    X, Y, _, _ = synth.mixture_pair(93, per_comp=800, m=3000)
-    X, Y = f32(X), f32(Y)
-    mX = f32(np.full(len(X), 1.0 / len(X)))
-    d = oracle.direct_forces(Y, X, mX)
-    nd = np.linalg.norm(d, axis=1)
-    ref = oracle.BHTree(X, mX).forces(Y, None, 66.7, 0.2, 0.5)
-    e_alg1 = np.median(np.linalg.norm(ref - d, axis=1) / nd)
-    F, c = fga.forces(dev(Y), dev(X), dev(mX), None, 0.5, fga.default_params(group_width=gw, group_boxes=nb))
-    F = F.cpu().numpy().astype(np.float64)
-    _, c1 = fga.forces(dev(Y), dev(X), dev(mX), None, 0.5, fga.default_params(group_width=gw, group_boxes=1))
-    assert np.median(np.linalg.norm(F - d, axis=1) / nd) <= 1.05 * e_alg1 + 1e-6
-    assert np.median(np.linalg.norm(F - ref, axis=1) / np.linalg.norm(ref, axis=1)) < 1e-2
-    assert c <= c1  # the smaller boxes never open more
-
-
-@pytest.mark.parametrize("nb", [2, 4])
-def test_group_run_boxes_registration_matches_oracle(nb):
-    X, Y, _, _ = synth.mixture_pair(94, per_comp=1024, m=7000)
-    X, Y = f32(X), f32(Y)
-    o = oracle.register(X, Y, oracle.Params(theta=0.5, max_iter=60))
-    R, t, rep = fga.register(dev(X), dev(Y), fga.default_params(theta=0.5, tol=0.0, max_iter=60,
-                                                                group_width=64, group_boxes=nb))
-    diag = np.linalg.norm(X.max(0) - X.min(0))
-    assert rep.traversal == 64
-    assert phi_deg(o["R"], R) < 0.05 and np.linalg.norm(t - o["t"]) / diag < 1e-4
