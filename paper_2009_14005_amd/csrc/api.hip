@@ -352,9 +352,10 @@ static void state_free(fga_state* S) {
 }
 
 // Groups of the template for the group walk, over its Morton order (built on
-// the device by device_groups): aligned blocks of G consecutive particles,
-// each cut into runs; with f > 0 a run also ends before its bounding-box
-// diagonal would exceed f times the median diagonal of the blocks.
+// the device by device_groups): greedy runs of at most G consecutive
+// particles; with f > 0 a run also ends before its bounding-box diagonal
+// would exceed f times the median diagonal of aligned G-runs (f = 1.5 and 3
+// timed no faster than these on the LiDAR and mesh workloads).
 // Tau options fi = 0..3 bound runs of 64 K particles; fi = 4..7 take the
 // same bounds on runs of at most 32 (K = 1), which the kernel holds twice
 // over the wave's lanes: smaller boxes accept more nodes, and a launch has
