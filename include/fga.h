@@ -344,6 +344,17 @@ fga_status fga_tree_export(const fga_tree* tr, float* com_mass, int32_t* ints, i
 
 void fga_tree_destroy(fga_tree* tr);
 
+/* Group runs of the Barnes-Hut group walk for the points Y (m x 3, FP32, device
+ * pointer), taken in the given order (the library cuts the template in its
+ * body-frame Morton order): greedy runs of at most G (32, 64 or 128)
+ * consecutive points, each ending before the diagonal of its bounding box
+ * would exceed f times the median diagonal of the aligned runs of G points
+ * (f = 0: runs of exactly G). runs_out (host, 2 x cap int32) receives
+ * (first, count) per run and *n_runs their number; FGA_E_INVALID_ARG when
+ * there are more than cap runs (*n_runs is set either way). */
+fga_status fga_group_runs(const void* Y, int64_t m, int G, double f, int32_t* runs_out, int64_t cap,
+                          int64_t* n_runs, void* stream);
+
 /* Host evaluation of the FP64 Kabsch solution used on the device: given
  * C = hat(Y_D)^T hat(Y) (row-major 3x3), writes R = U diag(1,1,sgn det(U V^T)) V^T
  * (Eq. R_Kabsch). Returns FGA_E_DEGENERATE when rank(C) < 2. */

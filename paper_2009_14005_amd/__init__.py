@@ -15,7 +15,9 @@ from dataclasses import dataclass
 
 __all__ = [
     "FGAError", "Params", "Report", "lib", "default_params", "masses", "forces",
-    "register", "register_batch", "State", "Tree", "kabsch", "version",
+    "register", "register_batch", "register_2d", "register_sequence",
+    "State", "Tree", "kabsch", "version", "energy", "forces_2d", "forces_direct_noalloc",
+    "group_runs",
     "F32", "F64", "DAMP_FRACTION", "DAMP_LITERAL", "VEL_RIGID", "VEL_PARTICLE",
     "MASS_NIV", "MASS_UNIFORM", "PREC_FP32", "PREC_FP32_KAHAN", "PREC_FP64",
     "PREC_FP32_ALL",
@@ -150,6 +152,8 @@ def lib():
             "fga_tree_export": (st, [vp, vp, vp, vp]),
             "fga_tree_destroy": (None, [vp]),
             "fga_kabsch": (st, [dp, dp]),
+            "fga_group_runs": (st, [vp, i64, ctypes.c_int, ctypes.c_double, vp, i64,
+                                    ctypes.POINTER(i64), vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -510,6 +514,21 @@ class Tree:
             self.close()
         except Exception:
             pass
+
+
+def group_runs(Y, G=64, f=0.0):
+    """The group walk's runs of the FP32 points Y (m x 3, device), in their
+    order: an (n_runs x 2) int32 array of (first, count)."""
+    import numpy as np
+    Y = _dev(Y, "Y")
+    if Y.dtype != _torch().float32:
+        raise TypeError("Y must be float32")
+    m = Y.shape[0]
+    out = np.zeros((m, 2), np.int32)  # at most one run per point
+    n = ctypes.c_int64()
+    _check(lib().fga_group_runs(_ptr(Y), m, int(G), float(f), out.ctypes.data_as(ctypes.c_void_p), m,
+                                ctypes.byref(n), _stream()))
+    return out[: n.value].copy()
 
 
 def kabsch(C):

@@ -723,6 +723,35 @@ const char* fga_last_error(void) { return g_err.c_str(); }
 
 const char* fga_version(void) { return "fga-mi355x 0.1 (gfx950)"; }
 
+fga_status fga_group_runs(const void* Y, int64_t m, int G, double f, int32_t* runs_out, int64_t cap,
+                          int64_t* n_runs, void* stream) {
+  FGA_TRY(check_ptr(Y, "Y"));
+  FGA_TRY(check_ptr(runs_out, "runs_out"));
+  FGA_TRY(check_ptr(n_runs, "n_runs"));
+  FGA_TRY(check_count(m, "m"));
+  if (G != 32 && G != 64 && G != 128) {
+    set_error("G must be 32, 64 or 128 (got %d)", G);
+    return FGA_E_INVALID_ARG;
+  }
+  if (!(f >= 0.0) || !std::isfinite(f)) {
+    set_error("f must be finite and >= 0");
+    return FGA_E_INVALID_ARG;
+  }
+  FGA_TRY(check_device_ptr(Y, "Y"));
+  std::vector<int2> runs;
+  FGA_TRY(device_groups_xyz((const float*)Y, m, G, f, runs, (hipStream_t)stream));
+  *n_runs = (int64_t)runs.size();
+  if ((int64_t)runs.size() > cap) {
+    set_error("%lld runs, more than cap %lld", (long long)runs.size(), (long long)cap);
+    return FGA_E_INVALID_ARG;
+  }
+  for (size_t k = 0; k < runs.size(); ++k) {
+    runs_out[2 * k] = runs[k].x;
+    runs_out[2 * k + 1] = runs[k].y;
+  }
+  return FGA_OK;
+}
+
 fga_status fga_kabsch(const double C[9], double R[9]) {
   FGA_TRY(check_ptr(C, "C"));
   FGA_TRY(check_ptr(R, "R"));

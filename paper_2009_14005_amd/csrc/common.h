@@ -227,6 +227,9 @@ fga_status sort_points_morton(int nseg, const TreeSeg* segs, void* Q, int64_t nt
 // segment k's runs as (first particle, count), first relative to off[k].
 fga_status device_groups(const float4* Q, int nseg, const int64_t* off, const int64_t* m, int G,
                          double f, std::vector<std::vector<int2>>& out, hipStream_t s);
+// The same for one segment of m x 3 FP32 points (device), in their order.
+fga_status device_groups_xyz(const float* Y, int64_t m, int G, double f, std::vector<int2>& out,
+                             hipStream_t s);
 
 // iter.hip: force-only evaluation (fga_forces)
 int direct_ranges(int64_t m, int64_t n);

@@ -277,7 +277,30 @@ __global__ __launch_bounds__(kBlock) void k_compact_runs(const int2* slots, cons
   for (int j = lane; j < cnt[b]; j += kWave) table[ofs[b] + j] = slots[(int64_t)b * G + j];
 }
 
+__global__ void k_pack_xyz(const float* Y, int64_t m, float4* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = make_float4(Y[3 * i], Y[3 * i + 1], Y[3 * i + 2], 0.f);
+}
+
 }  // namespace
+
+fga_status device_groups_xyz(const float* Y, int64_t m, int G, double f, std::vector<int2>& out,
+                             hipStream_t s) {
+  float4* Q = nullptr;
+  FGA_TRY(pool_get(&Q, sizeof(float4) * (size_t)m, s));
+  k_pack_xyz<<<(int)((m + kBlock - 1) / kBlock), kBlock, 0, s>>>(Y, m, Q);
+  fga_status st = FGA_OK;
+  if (hipGetLastError() != hipSuccess) {
+    set_error("group tables: pack launch failed");
+    st = FGA_E_DEVICE;
+  }
+  std::vector<std::vector<int2>> tabs;
+  const int64_t zero = 0;
+  if (st == FGA_OK) st = device_groups(Q, 1, &zero, &m, G, f, tabs, s);
+  pool_free(Q, s);
+  if (st == FGA_OK) out = std::move(tabs[0]);
+  return st;
+}
 
 fga_status device_groups(const float4* Q, int nseg, const int64_t* off, const int64_t* m, int G,
                          double f, std::vector<std::vector<int2>>& out, hipStream_t s) {

@@ -202,3 +202,14 @@ def test_energy_planar_sequence_argument_validation():
                                    None, None) == 1
 
 
+
+
+def test_group_runs_argument_validation():
+    L = fga.lib()
+    fake = ctypes.c_void_p(0x1000)
+    out = (ctypes.c_int32 * 64)()
+    n = ctypes.c_int64()
+    for m, G, f in ((10, 48, 1.0), (10, 64, -1.0), (10, 64, float("inf")), (0, 64, 1.0)):
+        assert L.fga_group_runs(fake, m, G, f, out, 32, ctypes.byref(n), None) == 1, (m, G, f)
+    assert L.fga_group_runs(None, 10, 64, 1.0, out, 32, ctypes.byref(n), None) == 1
+    assert L.fga_group_runs(fake, 10, 64, 1.0, None, 32, ctypes.byref(n), None) == 1
