@@ -41,6 +41,7 @@ FLOP_PER_INTERACTION = 20          # conventional n-body count (3 sub, 3+3 fma, 
 PEAK_FP32_VECTOR = 157.3e12        # MI355X published FP32 vector peak (packed), FLOP/s
 PEAK_FP32_NONPACKED = 78.6e12      # 256 CU x 64 lanes x 2 flop x 2.4 GHz
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+GOLDEN_FORCES = os.path.join(ROOT, "tests", "golden", "oracle_forces.npz")
 KERNEL_NAMES = {0: "k_iteration<float, direct, FP32_KAHAN>",
                 1: "k_iteration<float, BH per-particle walk, FP32_KAHAN>",
                 32: "k_iteration_group<FP32_KAHAN, 1> (group walk, groups of 32 held twice per wave)",
@@ -88,6 +89,16 @@ def diag_of(X):
 def golden():
     try:
         return json.load(open(GOLDEN))
+    except (OSError, ValueError):
+        return {}
+
+
+def golden_forces():
+    """Stored FP64 oracle direct-sum forces on sampled template points of the
+    mesh and precision pairs (sample indices included)."""
+    try:
+        with np.load(GOLDEN_FORCES, allow_pickle=False) as z:
+            return {k: z[k] for k in z.files}
     except (OSError, ValueError):
         return {}
 
@@ -155,6 +166,22 @@ class Registration:
         el = time.perf_counter() - t0
         self.R, self.t, self.rep = R, t, rep
         return el, evaluated / steps
+
+    def tree_build_ms(self, reps=5):
+        """Wall time of one Alg. 1 tree build over the reference cloud (device
+        copy, Morton sort, octree, node relayout) at the registration's leaf
+        size, averaged over `reps` builds."""
+        fga, torch = self.fga, self.torch
+        p = type(self.p).from_buffer_copy(self.p)
+        p.leaf_size = self.rep.leaf_size
+        m = torch.ones(self.Xd.shape[0], dtype=self.Xd.dtype, device="cuda:0")
+        fga.Tree(self.Xd, m, p).close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fga.Tree(self.Xd, m, p).close()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
 
     def alg2_count(self):
         """Interactions of Alg. 2's per-particle decisions over one whole
@@ -235,6 +262,7 @@ def main():
     alg2 = reg.alg2 = reg.alg2_count()
     value = alg2 * args.steps / elapsed
     f_ms, r_ms, ev_it, trav = reg.profile(args.iters)
+    tree_ms = reg.tree_build_ms()
     log(f"timed {args.steps} registrations: {ms_step:.2f} ms/step; Alg. 2 interactions "
         f"{alg2:.4e} per registration -> {value:.3e}/s; force launch {f_ms * 1e3:.1f} us, "
         f"reduction launch {r_ms * 1e3:.1f} us")
@@ -262,6 +290,7 @@ def main():
         "interactions_evaluated_per_registration": evaluated,
         "interactions_evaluated_per_s": evaluated * args.steps / elapsed,
         "ms_per_iteration": {"force_launch": f_ms, "reduction_launch": r_ms},
+        "tree_build_ms": tree_ms,
         "error_vs_oracle": vs_oracle(gold.get("mesh_1048576_bh0.5"), R, t, X, iters=args.iters),
         "oracle_alg2_interactions_per_registration": (gold.get("mesh_1048576_bh0.5") or {}).get("interactions"),
         "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, R),
@@ -298,26 +327,21 @@ def bench_sweep(reg, fga, torch, synth, gold, args):
     """The same mesh pair at theta 0.3 and 0.8 (whole registrations, poses
     against the oracle's) and with the direct sum (one iteration); forces of
     every variant on 4,096 sampled template points against the FP64 oracle's
-    direct sum (uniform masses, the mesh's own coordinates)."""
-    import oracle
-    oracle.build(force=False)
+    direct sum (uniform masses, the mesh's own coordinates), stored with
+    their sample indices."""
     X, Y = reg.X, reg.Y
     res = {}
-    idx = np.random.default_rng(2).choice(len(Y), 4096, replace=False)
-    X64 = np.ascontiguousarray(X, dtype=np.float32).astype(np.float64)
-    Ys64 = np.ascontiguousarray(Y[idx], dtype=np.float32).astype(np.float64)
-    mX = np.full(len(X), 1.0 / len(X))
-    omp_threads(all_threads())
-    t0 = time.perf_counter()
-    Fo = oracle.direct_forces(Ys64, X64, mX)
-    res["oracle_direct_sample_s"] = time.perf_counter() - t0
-    no = np.linalg.norm(Fo, axis=1)
-    Ys = torch.as_tensor(Ys64, dtype=torch.float32, device="cuda:0")
+    gf = golden_forces()
+    Fo, idx = gf.get("mesh_F"), gf.get("mesh_idx")
+    Ys = torch.as_tensor(np.ascontiguousarray(Y[idx] if idx is not None else Y[:4096], dtype=np.float32),
+                         device="cuda:0")
     mXd = torch.full((len(X),), 1.0 / len(X), dtype=torch.float32, device="cuda:0")
 
     def ferr(theta, **kw):
+        if Fo is None:
+            return None
         F, _ = fga.forces(Ys, reg.Xd, mXd, None, theta, fga.default_params(**kw))
-        e = np.linalg.norm(F.cpu().numpy().astype(np.float64) - Fo, axis=1) / no
+        e = np.linalg.norm(F.cpu().numpy().astype(np.float64) - Fo, axis=1) / np.linalg.norm(Fo, axis=1)
         return {"median": float(np.median(e)), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
 
     # direct sum: one registration iteration, timed with events
@@ -349,8 +373,7 @@ def bench_sweep(reg, fga, torch, synth, gold, args):
         r["alg2_interactions_per_s_force_launch"] = a2 / args.iters / (f_ms * 1e-3)
         r["error_vs_oracle"] = vs_oracle(gold.get(f"mesh_1048576_bh{th}"), sub.R, sub.t, X, iters=args.iters)
         res[f"theta_{th}"] = r
-        log(f"  theta {th}: force launch {f_ms * 1e3:.0f} us, error vs oracle direct median "
-            f"{r['force_rel_err_vs_oracle_direct']['group_walk']['median']:.1e}")
+        log(f"  theta {th}: force launch {f_ms * 1e3:.0f} us")
     return res
 
 
@@ -364,6 +387,7 @@ def bench_lidar(fga, torch, synth, gold, args):
     el, evaluated = reg.timed(10, 2)
     alg2 = reg.alg2_count()
     f_ms, r_ms, ev_it, trav = reg.profile(args.iters)
+    tree_ms = reg.tree_build_ms()
     log(f"  {el / 10 * 1e3:.2f} ms per registration; force launch {f_ms * 1e3:.1f} us")
     return {"ms_per_registration": el / 10 * 1e3, "registrations_per_s": 10 / el,
             "alg2_interactions_per_s": alg2 * 10 / el, "alg2_interactions_per_registration": alg2,
@@ -372,7 +396,7 @@ def bench_lidar(fga, torch, synth, gold, args):
             "error_vs_oracle": vs_oracle(gold.get("lidar_65536_bh0.5"), reg.R, reg.t, X, iters=args.iters),
             "accuracy_vs_ground_truth": {"phi_deg": phi_deg(R_gt, reg.R),
                                          "dt_over_diag": float(np.linalg.norm(reg.t - t_gt) / diag_of(X))},
-            "leaf_size": reg.rep.leaf_size,
+            "leaf_size": reg.rep.leaf_size, "tree_build_ms": tree_ms,
             "roofline": roofline(KERNEL_NAMES.get(trav, "?") + " force launch", alg2 / args.iters, f_ms,
                                  measured_traffic("bh_group_iteration_lidar65536_traffic.json"), ev_it),
             "reduction_launch_us": r_ms * 1e3}
@@ -405,18 +429,15 @@ def precision_study(fga, torch, synth, gold, args):
     """131,072 x 131,072 direct sums in the three precision modes: relative
     force error on 512 sampled template points against the FP64 oracle (max,
     median), and the pose after 10 and 100 registration iterations against the
-    oracle's registration of the same FP32-rounded pair."""
-    import oracle
-    oracle.build(force=False)
+    oracle's registration of the same FP32-rounded pair (both stored)."""
     log("precision study: 131,072 x 131,072")
     X, Y, _, _ = synth.precision_pair()
     X32 = np.ascontiguousarray(X, dtype=np.float32).astype(np.float64)
     Y32 = np.ascontiguousarray(Y, dtype=np.float32).astype(np.float64)
     n = len(X32)
     mX = np.full(n, 1.0 / n)
-    idx = np.random.default_rng(1).choice(len(Y32), 512, replace=False)
-    omp_threads(all_threads())
-    ref = oracle.direct_forces(Y32[idx], X32, mX)
+    gf = golden_forces()
+    ref, idx = gf.get("precision_F"), gf.get("precision_idx")
     rec = gold.get("precision_131072_direct")
     modes = (("pure_fp32", fga.PREC_FP32_ALL), ("fp32_tiles_fp64_reductions", fga.PREC_FP32),
              ("fp32_kahan_tiles_fp64_reductions", fga.PREC_FP32_KAHAN))
@@ -426,8 +447,11 @@ def precision_study(fga, torch, synth, gold, args):
     res = {}
     for name, prec in modes:
         F, _ = fga.forces(Yd, Xd, mXd, None, 0.0, fga.default_params(precision=prec))
-        Fs = F.cpu().numpy().astype(np.float64)[idx]
-        e = np.linalg.norm(Fs - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        if ref is not None:
+            Fs = F.cpu().numpy().astype(np.float64)[idx]
+            e = np.linalg.norm(Fs - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        else:
+            e = np.full(1, np.nan)
         st = fga.State(Xd, Yd, fga.default_params(theta=0.0, tol=0.0, precision=prec))
         st.step(10)
         R10, t10, _ = st.get()
@@ -509,6 +533,7 @@ def bench_batched(fga, torch, synth, gold, args):
                     "pairs": len(a)}
         res[f"tol_{tol:g}"] = {
             "batched_registrations_per_s": k / t_batch, "plain_registrations_per_s": k / t_plain,
+            "batched_interactions_evaluated_per_s": sum(r.interactions for r in reps) / t_batch,
             "batched_fixed_config_registrations_per_s": k / t_fixed, "tuning_call_ms": t_tuning * 1e3,
             "tuned_leaf_size": reps[0].leaf_size,
             "speedup": t_plain / t_batch, "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
@@ -563,9 +588,7 @@ def bench_odometry(fga, torch, synth, gold, args, nframes=32):
 def bench_mixture(fga, torch, synth, gold, args):
     """The 1,024 / 900-point Gaussian-mixture registration: direct sum in
     FP64, 200 fixed iterations (launch-bound at this size); pose against the
-    oracle's registration (run live: it takes well under a second)."""
-    import oracle
-    oracle.build(force=False)
+    stored oracle registration of the same FP64 pair and the ground truth."""
     X, Y, Rg, tg = synth.mixture_pair()
     Xd = torch.as_tensor(X, dtype=torch.float64, device="cuda:0")
     Yd = torch.as_tensor(Y, dtype=torch.float64, device="cuda:0")
@@ -578,12 +601,12 @@ def bench_mixture(fga, torch, synth, gold, args):
         R, t, rep = fga.register(Xd, Yd, p)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / n * 1e3
-    omp_threads(all_threads())
-    o = oracle.register(X, Y, oracle.Params(max_iter=200))
     log(f"mixture FP64 direct: {ms:.2f} ms per 200-iteration registration")
-    return {"ms_per_registration": ms, "iterations": rep.iters,
-            "interactions_per_s": rep.interactions / (ms * 1e-3),
-            "error_vs_oracle": vs_oracle(o, R, t, X), "phi_deg_vs_ground_truth": phi_deg(Rg, R)}
+    return {"ms_per_registration": ms, "registrations_per_s": 1e3 / ms, "iterations": rep.iters,
+            "ms_per_iteration": ms / rep.iters, "interactions_per_s": rep.interactions / (ms * 1e-3),
+            "error_vs_oracle": vs_oracle(gold.get("mixture_1024_direct_fp64"), R, t, X),
+            "accuracy_vs_ground_truth": {"phi_deg": phi_deg(Rg, R),
+                                         "dt_over_diag": float(np.linalg.norm(t - tg) / diag_of(X))}}
 
 
 def bench_landmarks(fga, torch, synth, gold, args, samples=32):
@@ -591,20 +614,20 @@ def bench_landmarks(fga, torch, synth, gold, args, samples=32):
     to 90 degrees about each axis, 1,888 points) with 0, 1 and 3 prior correspondences as
     RBF landmark masses (Eq. RBF_function, S = N o B): success rate (RMSE of
     the registered template under 1% of the bounding-box diagonal), time per
-    registration, and the pose against the oracle's for the first samples."""
-    import oracle
-    oracle.build(force=False)
+    registration, and the pose against the stored oracle registrations of
+    the first samples."""
     log(f"landmark masses: {samples} misaligned pairs, 0 / 1 / 3 prior matches")
     p = fga.default_params(theta=0.0, max_iter=300, tol=1e-8)
     res = {}
-    omp_threads(all_threads())
+    lm_gold = gold.get("landmarks_misaligned90") or {}
     for k in (0, 1, 3):
+        recs = lm_gold.get(f"priors_{k}") or []
         ok, ms, err = 0, [], []
         for j in range(samples):
             X, Y, Rg, tg, idx = synth.misaligned_pair(j, max_deg=90.0)
             lm = None
             if k:
-                pick = np.random.default_rng([7, j]).choice(len(Y), k, replace=False)
+                pick = synth.landmark_picks(j, k, len(Y))
                 lm = (idx[pick], pick)
             Xd = torch.as_tensor(X, dtype=torch.float32, device="cuda:0")
             Yd = torch.as_tensor(Y, dtype=torch.float32, device="cuda:0")
@@ -615,16 +638,14 @@ def bench_landmarks(fga, torch, synth, gold, args, samples=32):
             ms.append((time.perf_counter() - t0) * 1e3)
             rmse = float(np.sqrt(np.mean(np.sum((Y @ R.T + t - X[idx]) ** 2, 1))))
             ok += rmse < 0.01 * diag_of(X)
-            if j < 4:
-                o = oracle.register(np.ascontiguousarray(X, np.float32).astype(np.float64),
-                                    np.ascontiguousarray(Y, np.float32).astype(np.float64),
-                                    oracle.Params(max_iter=300, tol=1e-8), landmarks=lm)
-                err.append((phi_deg(o["R"], R), float(np.linalg.norm(t - o["t"]) / diag_of(X))))
-        e = np.array(err)
+            if j < len(recs):
+                v = vs_oracle(recs[j], R, t, X)
+                err.append((v["phi_deg"], v["dt_over_diag"]))
+        e = np.array(err) if err else np.full((1, 2), np.nan)
         res[f"priors_{k}"] = {"success_rate": ok / samples, "ms_per_registration_median": float(np.median(ms)),
                               "registrations_per_s": 1e3 / float(np.mean(ms)),
                               "vs_oracle_max_phi_deg": float(e[:, 0].max()),
-                              "vs_oracle_max_dt_over_diag": float(e[:, 1].max())}
+                              "vs_oracle_max_dt_over_diag": float(e[:, 1].max()), "pairs_vs_oracle": len(err)}
         log(f"  {k} priors: success {ok}/{samples}, {np.median(ms):.2f} ms per registration")
     return res
 

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "random_rotation", "mixture", "mixture_pair", "lidar_pair", "mesh_pair",
     "precision_pair", "batch_pairs", "batch_pair", "config_seed",
-    "BATCH_PAIRS", "uniform_grid_pair", "misaligned_pair", "lidar_sequence",
+    "BATCH_PAIRS", "uniform_grid_pair", "misaligned_pair", "landmark_picks", "lidar_sequence",
 ]
 
 BATCH_PAIRS = 256
@@ -126,6 +126,12 @@ def misaligned_pair(seed: int, per_comp: int = 236, max_deg: float = 135.0):
     tt = rng.uniform(-0.1, 0.1, size=3)
     Y = X[idx] @ Rt.T + tt
     return X, Y, Rt.T, -Rt.T @ tt, idx
+
+
+def landmark_picks(seed: int, k: int, m: int) -> np.ndarray:
+    """k distinct template indices (of m) whose true correspondences serve as
+    prior matches for misaligned pair `seed`."""
+    return np.random.default_rng([7, seed]).choice(m, k, replace=False)
 
 
 def precision_pair(seed: int = config_seed(3), per_comp: int = 16384):

@@ -1,6 +1,8 @@
 """Writes tests/golden/oracle_runs.json: FP64 oracle registrations of the
 benchmark workloads at their full sizes, for the parity tests and the
-benchmark's error columns (the oracle is far too slow to run there live).
+benchmark's error columns (the benchmark never runs the oracle itself outside
+its CPU-baseline timing), and tests/golden/oracle_forces.npz: the oracle's
+direct-sum forces on sampled template points of the mesh and precision pairs.
 
 Only `oracle/` and the seeded input generators in `synth/` are used. Every
 input is rounded to FP32 first, exactly as the HIP path receives it; each
@@ -8,8 +10,9 @@ record stores a SHA-256 of those FP32 inputs so that a reader can tell when
 the generators have changed since the record was written.
 
 Usage:  python tests/golden/make_oracle_runs.py [section ...]
-Sections: lidar, mesh, precision, batch, odometry (default: all). Existing records of
-other sections are kept. The whole run takes about an hour on 8 cores.
+Sections: lidar, mesh, precision, batch, odometry, mixture, landmarks, forces
+(default: all). Existing records of other sections are kept. The whole run
+takes about an hour on 8 cores.
 """
 import hashlib
 import json
@@ -26,6 +29,7 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_runs.json")
+FORCES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_forces.npz")
 
 
 def f32(a):
@@ -39,13 +43,17 @@ def input_hash(*arrays):
     return h.hexdigest()
 
 
-def run(X, Y, checkpoints=(), **kw):
-    """Oracle registration of the FP32-rounded pair; poses (caller frame) at
-    the listed iteration counts and at the end."""
-    X64, Y64 = f32(X).astype(np.float64), f32(Y).astype(np.float64)
+def run(X, Y, checkpoints=(), round32=True, landmarks=None, **kw):
+    """Oracle registration of the pair (rounded to FP32 first unless the HIP
+    path receives it in FP64); poses (caller frame) at the listed iteration
+    counts and at the end."""
+    if round32:
+        X64, Y64 = f32(X).astype(np.float64), f32(Y).astype(np.float64)
+    else:
+        X64, Y64 = np.asarray(X, np.float64), np.asarray(Y, np.float64)
     p = oracle.Params(**kw)
     t0 = time.time()
-    res = oracle.register(X64, Y64, p, trace=bool(checkpoints))
+    res = oracle.register(X64, Y64, p, trace=bool(checkpoints), landmarks=landmarks)
     rec = {"R": res["R"].tolist(), "t": res["t"].tolist(), "iters": res["iters"],
            "converged": bool(res["converged"]), "interactions": int(res["interactions"]),
            "params": {k: v for k, v in vars(p).items() if k != "extras"},
@@ -117,7 +125,51 @@ def main(sections):
             print("odometry", k, rec["seconds"], flush=True)
         db["odometry_lidar_pairs_bh0.5"] = recs
         save(db)
+    if "mixture" in sections:
+        # the 1,024 / 900-point mixture pair, given to the HIP path in FP64
+        X, Y, _, _ = synth.mixture_pair()
+        rec = run(X, Y, round32=False, theta=0.0, max_iter=200)
+        rec["input_sha256"] = input_hash(X, Y)
+        db["mixture_1024_direct_fp64"] = rec
+        save(db)
+        print("mixture", rec["seconds"], flush=True)
+    if "landmarks" in sections:
+        # misaligned pairs 0..3 (Euler angles up to 90 degrees) with 0, 1 and
+        # 3 prior correspondences as RBF landmark masses
+        lm_db = {}
+        for k in (0, 1, 3):
+            recs = []
+            for j in range(4):
+                X, Y, _, _, idx = synth.misaligned_pair(j, max_deg=90.0)
+                lm = None
+                if k:
+                    pick = synth.landmark_picks(j, k, len(Y))
+                    lm = (idx[pick], pick)
+                rec = run(X, Y, landmarks=lm, theta=0.0, max_iter=300, tol=1e-8)
+                rec["input_sha256"] = input_hash(X, Y)
+                recs.append(rec)
+            lm_db[f"priors_{k}"] = recs
+            print("landmarks", k, flush=True)
+        db["landmarks_misaligned90"] = lm_db
+        save(db)
+    if "forces" in sections:
+        # Eq. (GAForce) with uniform masses 1/n on the FP32-rounded clouds
+        # (no normalisation), on 4,096 template points of the mesh pair and
+        # 512 of the precision pair
+        arr = {}
+        for name, pair, count, seed in (("mesh", synth.mesh_pair, 4096, 2),
+                                        ("precision", synth.precision_pair, 512, 1)):
+            X, Y, _, _ = pair()
+            X64, Y64 = f32(X).astype(np.float64), f32(Y).astype(np.float64)
+            idx = np.random.default_rng(seed).choice(len(Y64), count, replace=False)
+            t0 = time.time()
+            F = oracle.direct_forces(np.ascontiguousarray(Y64[idx]), X64, np.full(len(X64), 1.0 / len(X64)))
+            arr[f"{name}_idx"] = idx.astype(np.int32)
+            arr[f"{name}_F"] = F
+            arr[f"{name}_input_sha256"] = np.array(input_hash(X, Y))
+            print("forces", name, time.time() - t0, flush=True)
+        np.savez_compressed(FORCES, **arr)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch", "odometry"])
+    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch", "odometry", "mixture", "landmarks", "forces"])
