@@ -235,7 +235,7 @@ def measured_traffic(name):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; use --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

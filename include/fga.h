@@ -43,7 +43,7 @@ typedef enum {
   FGA_E_DEVICE = 3,      /* HIP runtime or kernel error */
   FGA_E_NONFINITE = 4,   /* NaN or Inf in the input points or masses */
   FGA_E_DEGENERATE = 5,  /* zero-extent input, or a collinear template */
-  FGA_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+  FGA_E_UNSUPPORTED = 6  /* valid request the library does not implement */
 } fga_status;
 
 typedef enum { FGA_F32 = 0, FGA_F64 = 1 } fga_dtype;

@@ -80,7 +80,7 @@ fga_status check_params(const fga_params* p) {
     return FGA_E_INVALID_ARG;
   }
   if (p->max_depth != kQBits) {
-    set_error("max_depth %d: this build supports the paper's depth limit 20 only", p->max_depth);
+    set_error("max_depth %d: only the paper's depth limit 20 is supported", p->max_depth);
     return FGA_E_UNSUPPORTED;
   }
   if (p->max_iter < 0) {
