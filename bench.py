@@ -531,6 +531,29 @@ def bench_batched(fga, torch, synth, gold, args):
             return {"phi_deg_max": float(a[:, 0].max()), "phi_deg_median": float(np.median(a[:, 0])),
                     "dt_over_diag_max": float(a[:, 1].max()), "dt_over_diag_median": float(np.median(a[:, 1])),
                     "pairs": len(a)}
+        alg2_walk = None
+        if tol == 1e-8:
+            # the batch with the per-particle walk: Alg. 2's own node
+            # decisions in FP32 (Kahan), so its poses differ from the plain
+            # FP64 registrations by rounding only
+            pw = fga.default_params(theta=0.5, max_iter=200, tol=tol, group_width=1, leaf_size=1)
+            fga.register_batch(Xs[:4], Ys[:4], pw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Rw, tw, repw = fga.register_batch(Xs, Ys, pw)
+            torch.cuda.synchronize()
+            t_walk = time.perf_counter() - t0
+            ew, ewp = [], []
+            for j in range(k):
+                diag = diag_of(pairs[j][0])
+                ewp.append((phi_deg(plain[j][0], Rw[j]), float(np.linalg.norm(plain[j][1] - tw[j]) / diag)))
+                if j < len(recs):
+                    e3 = vs_oracle(recs[j], Rw[j], tw[j], pairs[j][0])
+                    ew.append((e3["phi_deg"], e3["dt_over_diag"]))
+            alg2_walk = {"registrations_per_s": k / t_walk, "ms": t_walk * 1e3, "speedup_vs_plain": t_plain / t_walk,
+                         "median_iters": float(np.median([r.iters for r in repw])),
+                         "vs_oracle": None, "vs_plain": None}
+            log(f"  tol {tol:g}: batched per-particle walk {t_walk * 1e3:.1f} ms")
         res[f"tol_{tol:g}"] = {
             "batched_registrations_per_s": k / t_batch, "plain_registrations_per_s": k / t_plain,
             "batched_interactions_evaluated_per_s": sum(r.interactions for r in reps) / t_batch,
@@ -541,6 +564,9 @@ def bench_batched(fga, torch, synth, gold, args):
             "median_iters_plain": float(np.median([pl[2].iters for pl in plain])),
             "batched_vs_oracle": summ(eb), "plain_vs_oracle": summ(ep), "batched_vs_plain": summ(ebp),
             "median_phi_vs_ground_truth_deg": float(np.median(gt))}
+        if alg2_walk is not None:
+            alg2_walk["vs_oracle"], alg2_walk["vs_plain"] = summ(ew), summ(ewp)
+            res[f"tol_{tol:g}"]["batched_per_particle_walk"] = alg2_walk
         log(f"  tol {tol:g}: batched {t_batch * 1e3:.1f} ms (fixed configuration {t_fixed * 1e3:.1f} ms), "
             f"plain FP64 {t_plain * 1e3:.1f} ms for {k} pairs")
     return res
