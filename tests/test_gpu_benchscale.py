@@ -178,3 +178,21 @@ def test_batch_256_pairs_against_oracle(gold, tol):
           f"median dt {np.median(errs[:, 1]):.2e}; outside the gates: {bad.tolist()}")
     assert np.median(errs[:, 0]) < PHI_GATE and np.median(errs[:, 1]) < DT_GATE
     assert len(bad) <= 0.01 * len(pairs), bad
+
+
+def test_batch_256_pairs_per_particle_walk_tracks_oracle(gold):
+    """The whole batch with the per-particle walk (Alg. 2's own MAC for every
+    particle): FP32 Kahan forces with FP64 reductions, so every pair ends
+    within rounding of the oracle's registration (gates 1e-4 degrees and 1e-6
+    of the diagonal, 500 and 100 times tighter than the registration gates)."""
+    recs = gold["batch_256_bh0.5_tol1e-08"]
+    pairs = synth.batch_pairs()
+    p = fga.default_params(theta=0.5, max_iter=200, tol=1e-8, group_width=1, leaf_size=1)
+    R, t, reps = fga.register_batch([dev(x[0]) for x in pairs], [dev(x[1]) for x in pairs], p)
+    errs = np.array([pose_err(recs[j], R[j], t[j], pairs[j][0]) for j in range(len(pairs))])
+    print(f"per-particle walk batch: max phi {errs[:, 0].max():.2e} deg, max dt {errs[:, 1].max():.2e}")
+    assert all(r.traversal == 1 for r in reps)
+    assert errs[:, 0].max() < 1e-4 and errs[:, 1].max() < 1e-6
+    iters = np.array([r.iters for r in reps])
+    ref_iters = np.array([recs[j]["iters"] for j in range(len(pairs))])
+    assert np.mean(np.abs(iters - ref_iters) <= 1) >= 0.99
