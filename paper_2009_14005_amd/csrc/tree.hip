@@ -775,8 +775,10 @@ fga_status morton_sort(int nseg, const TreeSeg* segs, const vec4_t<T>* X, int64_
   for (int shift = 0; shift < 3 * kQBits; shift += 8) {
     k_rs_hist<<<ntiles, kBlock, 0, s>>>(k0, dtiles, shift, hist);
     k_scan_tile<<<scan_blocks, kBlock, 0, s>>>(hist, hist_entries, scan_tot);
-    k_scan_u32_1block<<<1, 1024, 0, s>>>(scan_tot, scan_blocks);
-    k_scan_add<<<scan_blocks, kBlock, 0, s>>>(hist, hist_entries, scan_tot);
+    if (scan_blocks > 1) {  // one tile is already the whole exclusive scan
+      k_scan_u32_1block<<<1, 1024, 0, s>>>(scan_tot, scan_blocks);
+      k_scan_add<<<scan_blocks, kBlock, 0, s>>>(hist, hist_entries, scan_tot);
+    }
     k_rs_scatter<<<ntiles, kBlock, 0, s>>>(k0, v0, dtiles, shift, hist, k1, v1);
     std::swap(k0, k1);
     std::swap(v0, v1);
