@@ -745,10 +745,14 @@ def cpu_baseline(X, Y, extras, out, fga, torch, synth, gold, args):
                                     "interactions_per_s_all_threads": c_all / t_all,
                                     "interactions_per_s_one_thread": (stp.interactions - c_all) / t_one,
                                     "note": "tree build excluded"}
-    # C2 direct: the oracle's direct sum on 4,096 template points was timed by the sweep
-    sw = out.get("mesh_theta_sweep")
-    if sw:
-        t = sw["oracle_direct_sample_s"]
+    # C2 direct: the oracle's direct sum for 4,096 template points, all threads
+    if "sweep" in extras:
+        Xs = f64(X)
+        Ys = f64(Y[np.random.default_rng(2).choice(len(Y), 4096, replace=False)])
+        omp_threads(nth)
+        t0 = time.perf_counter()
+        oracle.direct_forces(Ys, Xs, np.full(len(Xs), 1.0 / len(Xs)))
+        t = time.perf_counter() - t0
         per["mesh_1048576_direct"] = {"threads": nth, "sample": "4,096 template points x 1,048,576 references",
                                       "interactions_per_s": 4096 * len(X) / t,
                                       "iteration_s_extrapolated": t * len(Y) / 4096}

@@ -128,7 +128,9 @@ def _tree_case(seed, n, dup=0):
     return X, m
 
 
-@pytest.mark.parametrize("seed,n,dup", [(1, 1000, 0), (2, 65536, 0), (3, 5000, 40), (4, 9, 0)])
+# 65,536 and 65,537 points: the last size whose radix-sort histogram one scan
+# tile holds, and the first that needs the three-launch scan
+@pytest.mark.parametrize("seed,n,dup", [(1, 1000, 0), (2, 65536, 0), (5, 65537, 0), (3, 5000, 40), (4, 9, 0)])
 def test_tree_topology_matches_oracle(seed, n, dup):
     X, m = _tree_case(seed, n, dup)
     t = fga.Tree(dev(X), dev(m))
@@ -141,7 +143,8 @@ def test_tree_topology_matches_oracle(seed, n, dup):
     assert info["nodes"] == st["branching"] + st["leaves"]
     # leaf point sets identical (GPU leaves index sorted points, mapped through order)
     nl, ids = ot.leaves()
-    ref = sorted(tuple(sorted(np.flatnonzero(ids == k))) for k in range(nl))
+    by_leaf = np.argsort(ids, kind="stable")
+    ref = sorted(tuple(g.tolist()) for g in np.split(by_leaf, np.cumsum(np.bincount(ids, minlength=nl))[:-1]))
     leaf = ex["skip"] == np.arange(info["nodes"]) + 1
     got = sorted(tuple(sorted(ex["order"][f:l + 1])) for f, l in zip(ex["first"][leaf], ex["last"][leaf]))
     assert got == ref
