@@ -1024,6 +1024,55 @@ extern "C" {
 
 // Registration state of Alg. 2 (defined below); lm_X / lm_Y: landmark
 // correspondences; dims = 2: planar clouds embedded at z = 0.
+// A second stream of the current device, at the default priority, created on
+// first use and kept until the process ends: a registration sorts its template
+// on it while the reference tree is built on the caller's stream (the two
+// chains are independent and launch-bound). Null if it cannot be created.
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s2 = nullptr;
+  if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[dev] = s2;
+  return s2;
+}
+
+// Work of one registration set-up split over the caller's stream and the side
+// stream: fork() makes the side stream wait for what the caller's stream has
+// queued, join() makes the caller's stream wait for what the side stream has
+// queued since. Without a side stream both run everything on the caller's.
+struct Fork {
+  hipStream_t s, s2 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  explicit Fork(hipStream_t st) : s(st) {
+    hipStream_t side = side_stream();
+    if (!side || hipEventCreateWithFlags(&e0, hipEventDisableTiming) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(e0, s) != hipSuccess || hipStreamWaitEvent(side, e0, 0) != hipSuccess)
+      return;
+    s2 = side;
+  }
+  hipStream_t side() const { return s2 ? s2 : s; }
+  void join() {
+    if (s2) {
+      // if the record fails, wait for the whole side stream instead
+      if (hipEventRecord(e1, s2) != hipSuccess || hipStreamWaitEvent(s, e1, 0) != hipSuccess)
+        (void)hipStreamSynchronize(s2);
+      s2 = nullptr;
+    }
+  }
+  ~Fork() {
+    join();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t m, fga_dtype dt,
                                const fga_params* p, void* stream, bool defer, fga_state** out,
                                const int64_t* lm_X = nullptr, const int64_t* lm_Y = nullptr,
@@ -1198,10 +1247,16 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   fga_params pp = *p;
   fga_status st = prep_pairs(1, &cx, &cy, dt, pp, &po, &S->norm, s, dims);
   if (st != FGA_OK) return fail(st);
+  // the template's Morton sort on the side stream, beside the tree builds
+  // below; joined before anything reads the sorted template
+  Fork fork(s);
   TreeSeg sy{0, m};
-  st = S->f64 ? sort_points_morton<double>(1, &sy, S->Q, m, nullptr, s)
-              : sort_points_morton<float>(1, &sy, S->Q, m, nullptr, s);
-  if (st != FGA_OK) return fail(st);
+  st = S->f64 ? sort_points_morton<double>(1, &sy, S->Q, m, nullptr, fork.side())
+              : sort_points_morton<float>(1, &sy, S->Q, m, nullptr, fork.side());
+  if (st != FGA_OK) {
+    fork.join();
+    return fail(st);
+  }
   const bool bh = p->theta > 0;
   // leaf sizes: the given one, or (leaf_size 0, FP32) every option for the
   // autotuner; FP64 keeps Alg. 1's singleton leaves
@@ -1291,7 +1346,11 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   // the trees: all of them when they are to be tuned, else only the chosen one
   for (size_t li = 0; li < S->trees.size(); ++li)
     if (!tuned || (int)li == (best >> 16))
-      if (fga_status bs = build_tree(li); bs != FGA_OK) return fail(bs);
+      if (fga_status bs = build_tree(li); bs != FGA_OK) {
+        fork.join();
+        return fail(bs);
+      }
+  fork.join();
   const std::vector<int> used = tuned ? std::vector<int>{best} : cands;
   size_t max_items = 0;
   for (int c : used) {
