@@ -373,15 +373,28 @@ static fga_status upload_items(fga_state* S, const std::vector<int4>& v, int4** 
   return FGA_OK;
 }
 
-// Measures the cost of every group: one iteration with one wave per group
+// Wave items of an iteration that measures the groups' costs: every group
+// in `parts` parts by subtrees (a fixed rule, so registrations of identical
+// inputs run identical launches), the parts of a group in adjacent waves.
+// The parts' list lengths add up to about the group's.
+constexpr int kMeasureParts = 2;  // parts per group in the cost-measuring iteration (at most the cap)
+
+static std::vector<int4> measuring_items(const fga_state::Groups& gt, int parts) {
+  std::vector<int4> v;
+  v.reserve((size_t)gt.n * parts);
+  for (int k = 0; k < gt.n; ++k)
+    for (int r = 0; r < parts; ++r) v.push_back(make_int4(gt.host[k].x, gt.host[k].y, r | parts << 8, k));
+  return v;
+}
+
+// Measures the cost of every group: one iteration with `parts` waves per group
 // over the whole reference counts the list entries of each group; the state
 // is restored afterwards.
-static fga_status measure_groups(fga_state* S, int K, int li, fga_state::Groups& gt) {
+static fga_status measure_groups(fga_state* S, int K, int li, fga_state::Groups& gt, int parts) {
   RigidState saved;
   FGA_HIP(hipMemcpyAsync(&saved, S->st, sizeof saved, hipMemcpyDeviceToHost, S->s));
   FGA_HIP(hipStreamSynchronize(S->s));
-  std::vector<int4> ident(gt.n);
-  for (int k = 0; k < gt.n; ++k) ident[k] = make_int4(gt.host[k].x, gt.host[k].y, 1 << 8, k);
+  const std::vector<int4> ident = measuring_items(gt, parts);
   int4* wi = nullptr;
   FGA_TRY(upload_items(S, ident, &wi));
   unsigned* cost = nullptr;
@@ -397,10 +410,10 @@ static fga_status measure_groups(fga_state* S, int K, int li, fga_state::Groups&
   pd.tile = kBlock * K;
   pd.witems = wi;
   pd.n_groups = gt.n;
-  pd.n_witems = gt.n;
+  pd.n_witems = (int)ident.size();
   pd.gcost = cost;
-  pd.jr = 1;
-  pd.n_items = (gt.n + kBlock / kWave - 1) / (kBlock / kWave);
+  pd.jr = parts;
+  pd.n_items = (pd.n_witems + kBlock / kWave - 1) / (kBlock / kWave);
   gt.cost.assign(gt.n, 0u);
   fga_status st = FGA_OK;
   if (hipMemsetAsync(cost, 0, sizeof(unsigned) * gt.n, S->s) != hipSuccess) st = FGA_E_DEVICE;
@@ -456,7 +469,7 @@ static fga_status wave_items(fga_state* S, int K, int li, fga_state::Groups& gt,
                              const int4** dev, int* count) {
   auto it = gt.items.find(cap);
   if (it == gt.items.end()) {
-    if (gt.cost.empty()) FGA_TRY(measure_groups(S, K, li, gt));
+    if (gt.cost.empty()) FGA_TRY(measure_groups(S, K, li, gt, std::min(kMeasureParts, cap)));
     std::vector<double> cs(gt.cost.begin(), gt.cost.end());
     double total = 0.0;
     for (double c : cs) total += c;
@@ -522,16 +535,16 @@ static fga_status apply_split(fga_state* S, PairDev& pd, int code, bool build = 
     FGA_TRY(ensure_groups(S, pd.group, (mode - 16) >> 2, li, &gt));
     pd.n_groups = gt->n;
     if (build && defer) {
-      // one wave per group for now; the first iteration measures the costs
-      // (also when tuning measured them already: every registration then
-      // runs the same first iteration and the same splits, bit for bit)
-      std::vector<int4> ident(gt->n);
-      for (int k = 0; k < gt->n; ++k) ident[k] = make_int4(gt->host[k].x, gt->host[k].y, 1 << 8, k);
+      // a fixed split for now (every group in at most kMeasureParts parts);
+      // the first iteration measures the costs (also when tuning measured
+      // them already: every registration then runs the same first
+      // iteration and the same splits, bit for bit)
+      const std::vector<int4> ident = measuring_items(*gt, std::min(kMeasureParts, pd.jr));
       pool_free(S->ident_items, S->s);
       S->ident_items = nullptr;
       FGA_TRY(upload_items(S, ident, &S->ident_items));
       pd.witems = S->ident_items;
-      pd.n_witems = gt->n;
+      pd.n_witems = (int)ident.size();
       S->pend_K = pd.group;
       S->pend_fi = (mode - 16) >> 2;
       S->pend_cap = pd.jr;
@@ -1436,9 +1449,9 @@ fga_status fga_state_create_landmarks(const void* X, int64_t n, const void* Y, i
   return state_create(X, n, Y, m, dt, p, stream, false, out, lm_X, lm_Y, n_landmarks);
 }
 
-// The first iteration of a deferred group split: one wave per group counts
-// every group's list entries while it iterates; the balanced wave items are
-// then built from those costs.
+// The first iteration of a deferred group split: the fixed measuring split
+// counts every group's list entries while it iterates; the balanced wave
+// items are then built from those costs.
 static fga_status first_step_measured(fga_state* S) {
   fga_state::Groups* gt = nullptr;
   FGA_TRY(ensure_groups(S, S->pend_K, S->pend_fi, S->pend_li, &gt));
