@@ -418,6 +418,20 @@ def test_deterministic_repeat():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("cap", [1, 2, 16])
+def test_group_walk_part_caps_against_oracle(cap):
+    """The group walk with at most 1, 2 or 16 parts per group (its
+    cost-measuring first iteration runs min(2, cap) parts of every group):
+    repeatable bit for bit, and within the registration gates of the oracle."""
+    X, Y, _, _ = synth.mixture_pair(15, per_comp=2500, m=16000)
+    kw = dict(theta=0.5, max_iter=40, group_width=64, tile=cap, leaf_size=1)
+    R1, t1, rep = fga_run(X, Y, **kw)
+    R2, t2, _ = fga_run(X, Y, **kw)
+    assert rep.traversal == 64 and rep.iters == 40
+    assert np.array_equal(R1, R2) and np.array_equal(t1, t2)
+    check_transform(R1, t1, oracle_run(X, Y, 0.5, 40), X)
+
+
 def test_stepwise_trajectory_matches_oracle():
     X, Y, _, _ = synth.mixture_pair(14, per_comp=64, m=400)
     Xn, Yn, info = oracle.normalise(X, Y)
