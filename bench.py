@@ -61,10 +61,11 @@ def parse():
     ap.add_argument("--iters", type=int, default=100, help="iterations per registration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the extra workloads")
-    ap.add_argument("--extras", default="sweep,lidar,direct,precision,batched,odometry,mixture,landmarks",
+    ap.add_argument("--extras",
+                    default="sweep,lidar,direct,precision,batched,odometry,mixture,landmarks,planar,energy",
                     help="comma list of extra workloads: sweep (mesh theta 0.3/0.8 and direct), "
-                         "lidar, direct, precision, "
-                         "batched, odometry, mixture, landmarks")
+                         "lidar, direct, precision, batched, odometry, mixture, landmarks, "
+                         "planar (D = 2), energy")
     ap.add_argument("--batch-pairs", type=int, default=256)
     ap.add_argument("--leaf", type=int, default=0,
                     help="leaf size of the group-walk registrations (0 = autotuned)")
@@ -317,6 +318,10 @@ def main():
         out["mixture_fp64_direct"] = bench_mixture(**ctx)
     if "landmarks" in extras:
         out["landmarks"] = bench_landmarks(**ctx)
+    if "planar" in extras:
+        out["planar"] = bench_planar(**ctx)
+    if "energy" in extras:
+        out["energy"] = bench_energy(**ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, Y, extras, out, **ctx)
     print(json.dumps(out), flush=True)
@@ -633,6 +638,84 @@ def bench_mixture(fga, torch, synth, gold, args):
             "error_vs_oracle": vs_oracle(gold.get("mixture_1024_direct_fp64"), R, t, X),
             "accuracy_vs_ground_truth": {"phi_deg": phi_deg(Rg, R),
                                          "dt_over_diag": float(np.linalg.norm(t - tg) / diag_of(X))}}
+
+
+def emb3(R2):
+    """A 2 x 2 rotation as the 3 x 3 rotation about z."""
+    R = np.eye(3)
+    R[:2, :2] = R2
+    return R
+
+
+def bench_planar(fga, torch, synth, gold, args):
+    """The planar mixture (D = 2: 262,144 reference and 196,608 template
+    points, quadtree, theta 0.5, FP32 Kahan forces, 100 iterations per
+    registration): registrations/s, Alg. 2 interactions per second over whole
+    registrations (the per-particle walk's count of the same registration),
+    and the pose against the stored oracle registration and the ground
+    truth."""
+    log("planar mixture (D = 2): 262,144 + 196,608 points, theta 0.5")
+    X, Y, R_gt, t_gt = synth.planar_pair()
+    Xd = torch.as_tensor(np.ascontiguousarray(X, np.float32), device="cuda:0")
+    Yd = torch.as_tensor(np.ascontiguousarray(Y, np.float32), device="cuda:0")
+    p = fga.default_params(theta=0.5, max_iter=args.iters, tol=0.0, leaf_size=args.leaf)
+    fga.register_2d(Xd, Yd, p)  # tunes the walk, warms the code paths
+    torch.cuda.synchronize()
+    n = 5
+    t0 = time.perf_counter()
+    for _ in range(n):
+        R, t, rep = fga.register_2d(Xd, Yd, p)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / n
+    pa = type(p).from_buffer_copy(p)
+    pa.group_width, pa.tile, pa.leaf_size = 1, 1, 1
+    _, _, ra = fga.register_2d(Xd, Yd, pa)
+    rec = gold.get("planar_262144_bh0.5")
+    ev = None
+    if rec:
+        ev = {"phi_deg": phi_deg(emb3(np.array(rec["R"])), emb3(R)),
+              "dt_over_diag": float(np.linalg.norm(t - np.array(rec["t"])) / diag_of(X))}
+    log(f"  {el * 1e3:.2f} ms per registration, {ra.interactions / el:.3e} Alg. 2 interactions/s")
+    return {"ms_per_registration": el * 1e3, "registrations_per_s": 1.0 / el,
+            "alg2_interactions_per_registration": ra.interactions,
+            "alg2_interactions_per_s": ra.interactions / el,
+            "interactions_evaluated_per_registration": rep.interactions,
+            "oracle_alg2_interactions_per_registration": (rec or {}).get("interactions"),
+            "traversal": rep.traversal, "leaf_size": rep.leaf_size, "error_vs_oracle": ev,
+            "accuracy_vs_ground_truth": {"phi_deg": phi_deg(emb3(R_gt), emb3(R)),
+                                         "dt_over_diag": float(np.linalg.norm(t - t_gt) / diag_of(X))}}
+
+
+def bench_energy(fga, torch, synth, gold, args):
+    """Plummer energy (the convergence diagnostic; its negative gradient is
+    Eq. GAForce), uniform reference masses 1/n and unit template masses: the
+    direct sum over the 131,072-point precision pair and the Alg. 2 traversal
+    (theta 0.5, per-particle decisions, tree build included) over the mesh
+    pair. Time per evaluation (best of 3), interactions/s, and the relative
+    difference from the stored oracle values."""
+    log("Plummer energy: direct 131,072 x 131,072, Barnes-Hut 1,048,576 x 1,048,576")
+    recs = gold.get("energy") or {}
+    res = {}
+    for key, pair, theta in (("precision_131072_direct", synth.precision_pair, 0.0),
+                             ("mesh_1048576_bh0.5", synth.mesh_pair, 0.5)):
+        X, Y, _, _ = pair()
+        Xd = torch.as_tensor(np.ascontiguousarray(X, np.float32), device="cuda:0")
+        Yd = torch.as_tensor(np.ascontiguousarray(Y, np.float32), device="cuda:0")
+        mX = torch.full((len(X),), 1.0 / len(X), dtype=torch.float32, device="cuda:0")
+        fga.energy(Yd, Xd, mX, None, theta)
+        torch.cuda.synchronize()
+        best = 1e9
+        for _ in range(3):
+            t0 = time.perf_counter()
+            E, cnt = fga.energy(Yd, Xd, mX, None, theta)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        rec = recs.get(key)
+        res[key] = {"ms_per_evaluation": best * 1e3, "interactions": cnt, "interactions_per_s": cnt / best,
+                    "E": E, "rel_diff_vs_oracle": abs(E - rec["E"]) / abs(rec["E"]) if rec else None,
+                    "oracle_interactions": rec["interactions"] if rec else None}
+        log(f"  {key}: {best * 1e3:.2f} ms, {cnt / best:.3e} interactions/s")
+    return res
 
 
 def bench_landmarks(fga, torch, synth, gold, args, samples=32):

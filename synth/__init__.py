@@ -27,13 +27,14 @@ __all__ = [
     "random_rotation", "mixture", "mixture_pair", "lidar_pair", "mesh_pair",
     "precision_pair", "batch_pairs", "batch_pair", "config_seed",
     "BATCH_PAIRS", "uniform_grid_pair", "misaligned_pair", "landmark_picks", "lidar_sequence",
+    "planar_pair",
 ]
 
 BATCH_PAIRS = 256
 
 
 def config_seed(k: int) -> int:
-    """Seed of configuration ``k`` (0..4)."""
+    """Seed of configuration ``k`` (0..6)."""
     return 14005 + k
 
 
@@ -132,6 +133,24 @@ def landmark_picks(seed: int, k: int, m: int) -> np.ndarray:
     """k distinct template indices (of m) whose true correspondences serve as
     prior matches for misaligned pair `seed`."""
     return np.random.default_rng([7, seed]).choice(m, k, replace=False)
+
+
+def planar_pair(seed: int = config_seed(6), per_comp: int = 32768, m: int = 196608,
+                max_deg: float = 30.0, t_half: float = 0.1, noise: float = 0.005):
+    """The mixture recipe in the plane (D = 2): the x, y coordinates of an
+    8-component mixture (262,144 points by default) as reference; the
+    template an m-point subset without replacement, rotated about z by an
+    angle U[0, max_deg], translated U[-t_half, t_half]^2 and noised. Returns
+    X, Y (n x 2, m x 2), R_gt (2 x 2), t_gt."""
+    rng = np.random.default_rng(seed)
+    X, _, _ = mixture(rng, 8, per_comp)
+    X = X[:, :2]
+    idx = rng.choice(X.shape[0], size=m, replace=False)
+    a = np.deg2rad(rng.uniform(0.0, max_deg))
+    Ry = np.array([[np.cos(a), -np.sin(a)], [np.sin(a), np.cos(a)]])
+    ty = rng.uniform(-t_half, t_half, size=2)
+    Y = X[idx] @ Ry.T + ty + noise * rng.normal(size=(m, 2))
+    return X, Y, Ry.T, -Ry.T @ ty
 
 
 def precision_pair(seed: int = config_seed(3), per_comp: int = 16384):

@@ -10,8 +10,8 @@ record stores a SHA-256 of those FP32 inputs so that a reader can tell when
 the generators have changed since the record was written.
 
 Usage:  python tests/golden/make_oracle_runs.py [section ...]
-Sections: lidar, mesh, precision, batch, odometry, mixture, landmarks, forces
-(default: all). Existing records of other sections are kept. The whole run
+Sections: lidar, mesh, precision, batch, odometry, mixture, landmarks, forces,
+planar, energy (default: all). Existing records of other sections are kept. The whole run
 takes about an hour on 8 cores.
 """
 import hashlib
@@ -152,6 +152,34 @@ def main(sections):
             print("landmarks", k, flush=True)
         db["landmarks_misaligned90"] = lm_db
         save(db)
+    if "planar" in sections:
+        # the planar mixture (D = 2, quadtree), theta 0.5, 100 iterations
+        X, Y, _, _ = synth.planar_pair()
+        rec = run(X, Y, checkpoints=(3,), theta=0.5, max_iter=100)
+        rec["input_sha256"] = input_hash(X, Y)
+        db["planar_262144_bh0.5"] = rec
+        save(db)
+        print("planar", rec["seconds"], flush=True)
+    if "energy" in sections:
+        # Plummer energy (uniform reference masses 1/n, unit template
+        # masses) of the FP32-rounded pairs: the direct sum on the precision
+        # pair, the Alg. 2 traversal at theta 0.5 on the mesh pair
+        en = {}
+        X, Y, _, _ = synth.precision_pair()
+        X64, Y64 = f32(X).astype(np.float64), f32(Y).astype(np.float64)
+        t0 = time.time()
+        e = oracle.gpe(Y64, X64, np.full(len(X64), 1.0 / len(X64)))
+        en["precision_131072_direct"] = {"E": e, "interactions": len(X64) * len(Y64),
+                                         "input_sha256": input_hash(X, Y), "seconds": time.time() - t0}
+        X, Y, _, _ = synth.mesh_pair()
+        X64, Y64 = f32(X).astype(np.float64), f32(Y).astype(np.float64)
+        t0 = time.time()
+        e, cnt = oracle.BHTree(X64, np.full(len(X64), 1.0 / len(X64))).gpe(Y64, None, theta=0.5, count=True)
+        en["mesh_1048576_bh0.5"] = {"E": e, "interactions": cnt, "input_sha256": input_hash(X, Y),
+                                    "seconds": time.time() - t0}
+        db["energy"] = en
+        save(db)
+        print("energy", {k: v["seconds"] for k, v in en.items()}, flush=True)
     if "forces" in sections:
         # Eq. (GAForce) with uniform masses 1/n on the FP32-rounded clouds
         # (no normalisation), on 4,096 template points of the mesh pair and
@@ -172,4 +200,5 @@ def main(sections):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch", "odometry", "mixture", "landmarks", "forces"])
+    main(sys.argv[1:] or ["lidar", "precision", "mesh", "batch", "odometry", "mixture", "landmarks", "forces",
+                          "planar", "energy"])

@@ -88,3 +88,25 @@ def test_mesh_sample_forces_on_a_few_rows(forces):
     rows = [0, 1, 2047, 4095]
     F = oracle.direct_forces(np.ascontiguousarray(Y64[idx[rows]]), X64, np.full(len(X64), 1.0 / len(X64)))
     np.testing.assert_allclose(F, forces["mesh_F"][rows], rtol=1e-13, atol=0)
+
+
+def test_planar_record_matches_its_inputs():
+    X, Y, _, _ = synth.planar_pair()
+    rec = RUNS["planar_262144_bh0.5"]
+    assert rec["input_sha256"] == _hash(X, Y)
+    assert rec["iters"] == 100 and "3" in rec["at"]
+    assert np.allclose(np.asarray(rec["R"]) @ np.asarray(rec["R"]).T, np.eye(2), atol=1e-12)
+
+
+def test_energy_records_are_the_oracle_values():
+    en = RUNS["energy"]
+    X, Y, _, _ = synth.mesh_pair()
+    assert en["mesh_1048576_bh0.5"]["input_sha256"] == _hash(X, Y)
+    f = lambda a: np.ascontiguousarray(a, np.float32).astype(np.float64)  # noqa: E731
+    X, Y = f(X), f(Y)
+    e, cnt = oracle.BHTree(X, np.full(len(X), 1.0 / len(X))).gpe(Y, None, theta=0.5, count=True)
+    assert cnt == en["mesh_1048576_bh0.5"]["interactions"]
+    assert abs(e - en["mesh_1048576_bh0.5"]["E"]) <= 1e-12 * abs(e)
+    Xp, Yp, _, _ = synth.precision_pair()
+    assert en["precision_131072_direct"]["input_sha256"] == _hash(Xp, Yp)
+    assert en["precision_131072_direct"]["interactions"] == len(Xp) * len(Yp)

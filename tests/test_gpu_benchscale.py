@@ -196,3 +196,45 @@ def test_batch_256_pairs_per_particle_walk_tracks_oracle(gold):
     iters = np.array([r.iters for r in reps])
     ref_iters = np.array([recs[j]["iters"] for j in range(len(pairs))])
     assert np.mean(np.abs(iters - ref_iters) <= 1) >= 0.99
+
+
+# ------------------------------------------- planar (D = 2) and energy
+def _rot3(R2):
+    R = np.eye(3)
+    R[:2, :2] = np.asarray(R2)
+    return R
+
+
+def test_planar_registration_against_oracle(gold):
+    """The planar mixture at the benchmark's size (262,144 + 196,608 points,
+    quadtree, theta 0.5, FP32 Kahan, autotuned walk), after 3 and 100
+    iterations, against the stored oracle registration."""
+    rec = gold["planar_262144_bh0.5"]
+    X, Y, _, _ = synth.planar_pair()
+    assert rec["input_sha256"] == input_hash(X, Y)
+    diag = np.linalg.norm(X.max(0) - X.min(0))
+    for it, ref in ((3, rec["at"]["3"]), (100, rec)):
+        R, t, rep = fga.register_2d(dev(X), dev(Y), fga.default_params(theta=0.5, max_iter=it, tol=0.0))
+        phi = phi_deg(_rot3(ref["R"]), _rot3(R))
+        dt = float(np.linalg.norm(t - np.array(ref["t"])) / diag)
+        print(f"planar, {it} iterations: phi {phi:.2e} deg, dt {dt:.2e}")
+        assert rep.iters == it and R.shape == (2, 2)
+        assert phi < PHI_GATE and dt < DT_GATE, (it, phi, dt)
+
+
+@pytest.mark.parametrize("key", ["precision_131072_direct", "mesh_1048576_bh0.5"])
+def test_energy_at_benchmark_sizes_against_oracle(gold, key):
+    """Plummer energy of the 131,072-point precision pair (direct) and the
+    mesh pair (Alg. 2 traversal, theta 0.5) against the stored oracle values:
+    relative difference under 1e-5, and the traversal's interaction count
+    within 0.1% of the oracle tree's."""
+    rec = gold["energy"][key]
+    direct = key.startswith("precision")
+    X, Y, _, _ = (synth.precision_pair if direct else synth.mesh_pair)()
+    assert rec["input_sha256"] == input_hash(X, Y)
+    mX = torch.full((len(X),), 1.0 / len(X), dtype=torch.float32, device="cuda:0")
+    E, cnt = fga.energy(dev(Y), dev(X), mX, None, 0.0 if direct else 0.5)
+    rel = abs(E - rec["E"]) / abs(rec["E"])
+    print(f"{key}: E {E:.12e} oracle {rec['E']:.12e} rel {rel:.2e}, count {cnt} oracle {rec['interactions']}")
+    assert rel < 1e-5
+    assert abs(cnt - rec["interactions"]) <= 1e-3 * rec["interactions"]
