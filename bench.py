@@ -868,6 +868,20 @@ def cpu_baseline(X, Y, extras, out, fga, torch, synth, gold, args):
         per["batch_256_bh0.5"] = {"pairs_timed": [int(j) for j in sel], "seconds": t8,
                                   "registrations_per_s": 8 / t8,
                                   "batch_s_extrapolated": t8 / 8 * synth.BATCH_PAIRS}
+    # planar (D = 2): one Alg. 2 iteration (quadtree, theta 0.5), all threads
+    if "planar" in extras:
+        X2, Y2, _, _ = synth.planar_pair()
+        Xn, Yn, _ = oracle.normalise(f64(X2), f64(Y2))
+        mX, mY = oracle.masses(Xn, Yn, prm)
+        omp_threads(nth)
+        stp = oracle.Stepper(Xn, Yn, mX, mY, oracle.Params(theta=0.5))
+        t0 = time.perf_counter()
+        stp.step()
+        t_it = time.perf_counter() - t0
+        per["planar_262144_bh0.5"] = {f"threads_{nth}_iteration_s": t_it,
+                                      "interactions_per_s": stp.interactions / t_it,
+                                      "registration_100it_s_extrapolated": 100 * t_it,
+                                      "note": "tree build excluded"}
     omp_threads(nth)
     res["per_workload"] = per
     log(f"  oracle: {res['value']:.3e} interactions/s on {nth} threads")
