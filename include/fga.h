@@ -110,7 +110,8 @@ typedef struct {
                              bounding box (at least as accurate as per-particle); 32 = groups
                              of at most 32 such particles, each held twice over the wave's
                              lanes (the two copies split the interaction list); 0 = chosen
-                             by the autotuner among 1, 64 and 128. FP64 uses 1. The choice changes
+                             by the autotuner among 1, 64 and 128 (and 32 for planar sets,
+                             fga_register_2d). FP64 uses 1. The choice changes
                              which nodes are accepted, so with 0 the result of identical
                              inputs can differ (within the MAC's accuracy) between processes
                              whose timings made different choices; FGA_TUNE_CACHE pins them. */

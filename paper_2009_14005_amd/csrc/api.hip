@@ -1308,9 +1308,11 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
     for (int fi = 0; fi < 4; ++fi) {
       if (gw == 0 || gw == 64) modes.push_back(16 + 1 + 4 * fi);
       if (gw == 0 || gw == 128) modes.push_back(16 + 2 + 4 * fi);
-      // runs of 32 on request only: on the LiDAR and mesh workloads every
-      // one of them timed slower than the runs of 64 (the walks double)
-      if (gw == 32) modes.push_back(16 + 1 + 4 * (fi + 4));
+      // runs of 32: on request, and for planar sets, where a run's box is
+      // wider for its particle count and the 32-runs timed fastest (13% on
+      // the planar mixture); on the LiDAR and mesh workloads every one of
+      // them timed slower than the runs of 64 (the walks double)
+      if (gw == 32 || (gw == 0 && dims == 2)) modes.push_back(16 + 1 + 4 * (fi + 4));
     }
   }
   std::vector<int> cands;
@@ -1341,7 +1343,8 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   const std::string key = tune_key(bh, S->f64, m, n, p->precision, p->group_width) +
                           (bh ? "_t" + std::to_string(std::lround(p->theta * 1000)) + "_L" +
                                     std::to_string(leaf_auto ? 0 : S->tree_leaf[0])
-                              : "");
+                              : "") +
+                          (dims == 2 ? "_D2" : "");
   int best = cands[0];
   bool tuned = cands.size() == 1;
   if (!tuned) {

@@ -145,3 +145,34 @@ def test_cached_choice_with_a_leaf_tree_is_reused(tmp_path):
     assert (out["leaf"], out["trav"]) == (2, 64)
 
 
+
+
+PLANAR_CHILD = r"""
+import json, sys
+sys.path.insert(0, {root!r})
+import numpy as np, torch
+import paper_2009_14005_amd as fga
+import synth
+dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device="cuda:0")
+X2, Y2, _, _ = synth.planar_pair(per_comp=4096, m=24576)
+X3, Y3, _, _ = synth.mixture_pair(7, per_comp=4096, m=24576)
+p = fga.default_params(theta=0.5, max_iter=5, tol=0.0)
+a = fga.register_2d(dev(X2), dev(Y2), p)
+b = fga.register(dev(X3), dev(Y3), p)
+c = fga.register_2d(dev(X2), dev(Y2), p)
+print(json.dumps({{"t2": a[2].traversal, "t3": b[2].traversal,
+                  "same": bool(np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]))}}))
+"""
+
+
+def test_planar_and_3d_choices_are_cached_apart(tmp_path):
+    """A planar and a 3D registration of the same sizes are tuned once each
+    (their candidates differ: runs of 32 are a candidate in the plane only),
+    and a repeated planar registration takes its cached choice."""
+    env = dict(os.environ, FGA_TUNE_CACHE=str(tmp_path / "tune.cache"), FGA_TUNE_LOG="1")
+    r = subprocess.run([sys.executable, "-c", PLANAR_CHILD.format(root=ROOT)], capture_output=True,
+                       text=True, timeout=240, env=env)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stderr.count("[fga tune] initial pose") == 2, r.stderr[-3000:]
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["same"] and out["t3"] in (1, 64, 128) and out["t2"] in (1, 32, 64, 128)
