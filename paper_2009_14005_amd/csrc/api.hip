@@ -1400,6 +1400,7 @@ static fga_status state_create(const void* X, int64_t n, const void* Y, int64_t 
   pd.n = (int)n;
   pd.m = (int)m;
   pd.n_nodes = S->n_nodes;
+  pd.planar = dims == 2 ? 1 : 0;
   S->c = make_iter_consts(*p);
   // manual stepping has no iteration cap; fga_register applies max_iter itself
   const int big = 0x7fffffff;

@@ -169,6 +169,7 @@ struct PairDev {
   unsigned* gcost;      // optional: list entries evaluated per group are added here
   int n_groups;
   int n_witems;
+  int planar = 0;       // 1: planar sets (z constant): the group walk skips the z terms
 };
 
 

@@ -314,7 +314,7 @@ __device__ inline float wave_max_f(float v) {
 // Adds the list entries [0, cnt) to the K particles of this lane if `sel`.
 // With KAHAN the list's sum is one tile, added to the total with Kahan
 // compensation.
-template <int K, bool KAHAN>
+template <int K, bool KAHAN, bool PL = false>
 __device__ inline void group_sum(const float4* list, int cnt, const float (&y)[K][3], float eps2,
                                  bool sel, float (&acc)[K][3], float (&cmp)[K][3]) {
   float t[K][3];
@@ -327,13 +327,13 @@ __device__ inline void group_sum(const float4* list, int cnt, const float (&y)[K
     const float4 x = list[e];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = x.z - y[k][2];
-      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+      const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = PL ? 0.f : x.z - y[k][2];
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, PL ? eps2 : fmaf(dz, dz, eps2)));
       const float r = __builtin_amdgcn_rsqf(r2);
       const float s = x.w * r * (r * r);
       t[k][0] = fmaf(dx, s, t[k][0]);
       t[k][1] = fmaf(dy, s, t[k][1]);
-      t[k][2] = fmaf(dz, s, t[k][2]);
+      if (!PL) t[k][2] = fmaf(dz, s, t[k][2]);
     }
   }
   if (!sel) return;
@@ -354,7 +354,7 @@ __device__ inline void group_sum(const float4* list, int cnt, const float (&y)[K
 // The same sum for a group held R > 1 times over the lanes: replica `rep`
 // takes entries rep, rep + R, ... of the list (padded with zero-mass entries
 // to a multiple of R, cnt).
-template <int K, bool KAHAN>
+template <int K, bool KAHAN, bool PL = false>
 __device__ inline void group_sum_rep(const float4* list, int cnt, int rep, int R,
                                      const float (&y)[K][3], float eps2, bool sel,
                                      float (&acc)[K][3], float (&cmp)[K][3]) {
@@ -369,13 +369,13 @@ __device__ inline void group_sum_rep(const float4* list, int cnt, int rep, int R
     const float4 x = list[i * R + rep];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = x.z - y[k][2];
-      const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+      const float dx = x.x - y[k][0], dy = x.y - y[k][1], dz = PL ? 0.f : x.z - y[k][2];
+      const float r2 = fmaf(dx, dx, fmaf(dy, dy, PL ? eps2 : fmaf(dz, dz, eps2)));
       const float r = __builtin_amdgcn_rsqf(r2);
       const float s = x.w * r * (r * r);
       t[k][0] = fmaf(dx, s, t[k][0]);
       t[k][1] = fmaf(dy, s, t[k][1]);
-      t[k][2] = fmaf(dz, s, t[k][2]);
+      if (!PL) t[k][2] = fmaf(dz, s, t[k][2]);
     }
   }
   if (!sel) return;
@@ -394,8 +394,9 @@ __device__ inline void group_sum_rep(const float4* list, int cnt, int rep, int R
 }
 
 // Squared diagonal of the box of the lanes selected by `sel` (their valid
-// particles), and the box itself, uniform over the wave.
-template <int K>
+// particles), and the box itself, uniform over the wave. PL: a planar set,
+// whose z is the same for every point (the box is flat).
+template <int K, bool PL = false>
 __device__ inline float group_box(const bool (&valid)[K], const float (&y)[K][3], bool sel,
                                   float (&lo)[3], float (&hi)[3]) {
 #pragma unroll
@@ -414,19 +415,22 @@ __device__ inline float group_box(const bool (&valid)[K], const float (&y)[K][3]
     }
   float d2 = 0.f;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < (PL ? 2 : 3); ++a) {
     lo[a] = wave_min_f(lo[a]);
     hi[a] = wave_max_f(hi[a]);
     d2 = fmaf(hi[a] - lo[a], hi[a] - lo[a], d2);
   }
+  if (PL) lo[2] = hi[2] = 0.f;  // unused
   return d2;
 }
 
-// Squared distance from c to the box [lo, hi] (0 inside).
+// Squared distance from c to the box [lo, hi] (0 inside); PL: in the plane
+// of a planar set (x and y only).
+template <bool PL = false>
 __device__ inline float box_dist2(const float (&lo)[3], const float (&hi)[3], const float (&c)[3]) {
   float d2 = 0.f;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < (PL ? 2 : 3); ++a) {
     const float u = fmaxf(fmaxf(lo[a] - c[a], c[a] - hi[a]), 0.f);
     d2 = fmaf(u, u, d2);
   }
@@ -444,7 +448,7 @@ constexpr int kLargeParent = 1 << 28;  // stack entry flag: the block's parent i
 constexpr int kIndexMask = kLargeParent - 1;
 
 // The walk for a group: the particles of the lanes with `sel`, part r of nr.
-template <int K, bool KAHAN>
+template <int K, bool KAHAN, bool PL = false>
 __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
                                   const float4* __restrict__ X, int n_points, int r, int nr,
                                   float theta2, float eps2, bool sel,
@@ -465,7 +469,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
     // instead: the same nodes are visited and accepted, two steps sooner.
     auto walked_open = [&](const BHWide& b) {
       const float c3[3] = {b.cm.x, b.cm.y, b.cm.z};
-      const float d2 = box_dist2(lo, hi, c3);
+      const float d2 = box_dist2<PL>(lo, hi, c3);
       return b.child != -1 && !(__float_as_uint(b.l2) >> 31) && b.last - b.first + 1 > kSplitPts &&
              !(fabsf(b.l2) < theta2 * d2);
     };
@@ -484,11 +488,11 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
   }
   auto flush = [&]() {
     if (R == 1) {
-      group_sum<K, KAHAN>(g.list, cnt, y, eps2, sel, acc, cmp);
+      group_sum<K, KAHAN, PL>(g.list, cnt, y, eps2, sel, acc, cmp);
     } else {
       const int padded = (cnt + R - 1) / R * R;  // zero-mass entries up to a multiple of R
       if (lane < padded - cnt) g.list[cnt + lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-      group_sum_rep<K, KAHAN>(g.list, padded, rep, R, y, eps2, sel, acc, cmp);
+      group_sum_rep<K, KAHAN, PL>(g.list, padded, rep, R, y, eps2, sel, acc, cmp);
     }
     count += (sel && rep == 0) ? (unsigned)(cnt * nvalid) : 0u;
     entries += (unsigned)cnt;
@@ -539,7 +543,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
     const bool leaf = nd.child == -1;
     const bool twig = __float_as_uint(nd.l2) >> 31;
     const float c3[3] = {nd.cm.x, nd.cm.y, nd.cm.z};
-    const float d2 = box_dist2(lo, hi, c3);
+    const float d2 = box_dist2<PL>(lo, hi, c3);
     const bool accept = on && ((leaf && nd.first == nd.last) || fabsf(nd.l2) < theta2 * d2);
     const bool own = accept && mine;
     const bool pts = on && !accept && (leaf || twig) && mine;
@@ -612,7 +616,7 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
 // (uniform) receives the number of list entries evaluated. Returns false if
 // the stack overflowed (never for trees of depth at most kQBits + 1;
 // the sum is then incomplete).
-template <int K, bool KAHAN>
+template <int K, bool KAHAN, bool PL = false>
 __device__ inline bool bh_group(const BHWide* __restrict__ nodes, int n_nodes,
                                 const float4* __restrict__ X, int n_points, int r, int nr, int R,
                                 float theta2, float eps2,
@@ -624,14 +628,14 @@ __device__ inline bool bh_group(const BHWide* __restrict__ nodes, int n_nodes,
   for (int k = 0; k < K; ++k) nvalid += valid[k] ? 1 : 0;
   if (__ballot(nvalid > 0) == 0ull) return true;
   float lo[3], hi[3];
-  group_box<K>(valid, y, true, lo, hi);
+  group_box<K, PL>(valid, y, true, lo, hi);
   float cmp[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int a = 0; a < 3; ++a) cmp[k][a] = 0.f;
   const int rep = (int)(threadIdx.x & (kWave - 1)) / (kWave / R);
-  const bool ok = group_walk<K, KAHAN>(nodes, n_nodes, X, n_points, r, nr, theta2, eps2, true,
+  const bool ok = group_walk<K, KAHAN, PL>(nodes, n_nodes, X, n_points, r, nr, theta2, eps2, true,
                                        nvalid, rep, R, lo, hi, y, acc, cmp, count, entries, g);
   if (R > 1) {  // add the replicas' partial sums
 #pragma unroll

@@ -269,7 +269,7 @@ __device__ void iteration_item(const PairDev& pd, const IterConsts& c, int item,
 // part r of nr of the walk (heavy groups are split over several waves by
 // subtrees).
 // FP32 only.
-template <int PREC, int K>
+template <int PREC, int K, bool PL = false>
 __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int item,
                                      double* lds, GroupLds* g) {
   const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x & (kWave - 1);
@@ -307,7 +307,7 @@ __device__ void iteration_item_group(const PairDev& pd, const IterConsts& c, int
     }
   }
   unsigned cnt = 0, entries = 0;
-  const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN>(
+  const bool ok = bh_group<K, PREC == FGA_PREC_FP32_KAHAN, PL>(
       pd.nodes, pd.n_nodes, (const float4*)pd.X, pd.n, r, nr, R, c.ftheta2, c.feps2,
       valid, y, acc, cnt, entries, g[wave]);
   if (!ok && lane == 0) atomicOr(&pd.st->flags, 2);
@@ -326,12 +326,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   iteration_item<T, BH, PREC, S>(pd, c, (int)blockIdx.x, lds, stk);
 }
 
-template <int PREC, int K>
+template <int PREC, int K, bool PL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kGroupWavesPerSimd))) void k_iteration_group(PairDev pd, IterConsts c) {
   __shared__ double lds[kRow * (kBlock / kWave)];
   __shared__ GroupLds g[kBlock / kWave];
   if (pd.st->converged) return;  // uniform: the state was written by the previous launch
-  iteration_item_group<PREC, K>(pd, c, (int)blockIdx.x, lds, g);
+  iteration_item_group<PREC, K, PL>(pd, c, (int)blockIdx.x, lds, g);
 }
 
 // Persistent batched iteration: blocks pull (pair, item) entries from a work
@@ -415,14 +415,23 @@ template <typename T>
 fga_status launch_iteration(const PairDev& pd, const IterConsts& c, hipStream_t s, hipEvent_t between) {
   const bool bh = pd.nodes != nullptr;
   const dim3 grid((unsigned)pd.n_items);
-  if (sizeof(T) == 4 && bh && pd.group > 0) {  // group traversal, K particles per lane
+  if (sizeof(T) == 4 && bh && pd.group > 0 && pd.planar) {  // planar sets: no z terms
     switch (c.prec * 4 + pd.group) {
-      case FGA_PREC_FP32 * 4 + 1: k_iteration_group<FGA_PREC_FP32, 1><<<grid, kBlock, 0, s>>>(pd, c); break;
-      case FGA_PREC_FP32 * 4 + 2: k_iteration_group<FGA_PREC_FP32, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
-      case FGA_PREC_FP32_ALL * 4 + 1: k_iteration_group<FGA_PREC_FP32_ALL, 1><<<grid, kBlock, 0, s>>>(pd, c); break;
-      case FGA_PREC_FP32_ALL * 4 + 2: k_iteration_group<FGA_PREC_FP32_ALL, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
-      case FGA_PREC_FP32_KAHAN * 4 + 2: k_iteration_group<FGA_PREC_FP32_KAHAN, 2><<<grid, kBlock, 0, s>>>(pd, c); break;
-      default: k_iteration_group<FGA_PREC_FP32_KAHAN, 1><<<grid, kBlock, 0, s>>>(pd, c);
+      case FGA_PREC_FP32 * 4 + 1: k_iteration_group<FGA_PREC_FP32, 1, true><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32 * 4 + 2: k_iteration_group<FGA_PREC_FP32, 2, true><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_ALL * 4 + 1: k_iteration_group<FGA_PREC_FP32_ALL, 1, true><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_ALL * 4 + 2: k_iteration_group<FGA_PREC_FP32_ALL, 2, true><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_KAHAN * 4 + 2: k_iteration_group<FGA_PREC_FP32_KAHAN, 2, true><<<grid, kBlock, 0, s>>>(pd, c); break;
+      default: k_iteration_group<FGA_PREC_FP32_KAHAN, 1, true><<<grid, kBlock, 0, s>>>(pd, c);
+    }
+  } else if (sizeof(T) == 4 && bh && pd.group > 0) {  // group traversal, K particles per lane
+    switch (c.prec * 4 + pd.group) {
+      case FGA_PREC_FP32 * 4 + 1: k_iteration_group<FGA_PREC_FP32, 1, false><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32 * 4 + 2: k_iteration_group<FGA_PREC_FP32, 2, false><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_ALL * 4 + 1: k_iteration_group<FGA_PREC_FP32_ALL, 1, false><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_ALL * 4 + 2: k_iteration_group<FGA_PREC_FP32_ALL, 2, false><<<grid, kBlock, 0, s>>>(pd, c); break;
+      case FGA_PREC_FP32_KAHAN * 4 + 2: k_iteration_group<FGA_PREC_FP32_KAHAN, 2, false><<<grid, kBlock, 0, s>>>(pd, c); break;
+      default: k_iteration_group<FGA_PREC_FP32_KAHAN, 1, false><<<grid, kBlock, 0, s>>>(pd, c);
     }
   } else if (sizeof(T) == 8) {
     if (bh) k_iteration<T, true, FGA_PREC_FP64, 1><<<grid, kBlock, 0, s>>>(pd, c);
