@@ -1056,9 +1056,10 @@ static hipStream_t side_stream() {
 }
 
 // Work of one registration set-up split over the caller's stream and the side
-// stream: fork() makes the side stream wait for what the caller's stream has
-// queued, join() makes the caller's stream wait for what the side stream has
-// queued since. Without a side stream both run everything on the caller's.
+// stream: constructing a Fork makes the side stream wait for what the
+// caller's stream has queued, join() makes the caller's stream wait for what
+// the side stream has queued since. Without a side stream (or if an event
+// call fails) side() is the caller's stream and everything runs there.
 struct Fork {
   hipStream_t s, s2 = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
