@@ -297,7 +297,7 @@ constexpr int kGRepMax = 8;   // replicas of a small group's particles over the 
 struct GroupLds {
   float4 list[kGList + kGRepMax];  // slack for zero-mass padding to a multiple of the replicas
   int stk[kGStack];
-  unsigned mark[kWave];            // 1 + the lane that starts an entry at this lane, else 0
+  unsigned mark[kWave];            // nonzero where an entry starts: 1 (pops), 1 + its lane (point appends)
 };
 
 __device__ inline float wave_min_f(float v) {
@@ -520,15 +520,20 @@ __device__ inline bool group_walk(const BHWide* __restrict__ nodes, int n_nodes,
     T = E > 0 ? __builtin_amdgcn_readlane(incl, E - 1) : 0;
     sp -= E;
     // this lane's node: entry e is the last whose first lane (incl - c) is at
-    // or below the lane; the entries' first lanes are distinct (relaxed
-    // atomics: the marks pass between lanes, so a lane's own -1 must not be
-    // forwarded to its read)
+    // or below the lane. The entries' first lanes are distinct and increase
+    // with the entry, so e is the number of first lanes at or below this
+    // lane, minus one: each entry marks its first lane, a ballot collects the
+    // marks (relaxed atomics: the marks pass between lanes, so a lane's own
+    // store must not be forwarded to its read)
     __hip_atomic_store(&g.mark[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     if (lane < E)
-      __hip_atomic_store(&g.mark[incl - c], (unsigned)lane + 1u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_WAVEFRONT);
-    const int e = (int)wave_incl_max_u32(__hip_atomic_load(&g.mark[lane], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WAVEFRONT)) - 1;
+      __hip_atomic_store(&g.mark[incl - c], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const bool first =
+        __hip_atomic_load(&g.mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) != 0u;
+    const unsigned long long starts = __ballot(first);
+    const int e = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(starts >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((unsigned)starts, 0u)) +
+                  (first ? 1 : 0) - 1;
     // entry lane: its first node minus its first lane (+ 64, >= 1) and the
     // shared-parent flag in bit 30, fetched by the node lanes in one move
     const int pk = ((ch & kIndexMask) - (incl - c) + kWave) | ((ch & kLargeParent) ? 1 << 30 : 0);
